@@ -1,0 +1,149 @@
+"""GNN dynamics model and its per-node linearization (oracle; test
+infrastructure only).
+
+Model (Sec. V-A eq. forward_dynamics; message passing as Sec. III-A eq. 1,
+sum aggregation, ReLU MLPs, edge feature built from the relative state):
+  h0_i      = act(W_enc [x^i; P^i u] + b_enc)             P^i u: node i's force, 0 if not actuated
+  m_ij      = act(W_e^l [h_i; h_i - h_j] + b_e^l)         j in N_i (senders of edges j -> i)
+  h_i       <- act(W_n^l [h_i; sum_{j in N_i} m_ij] + b_n^l)   for l = 0..L-1
+  o_i       = W_dec h_i + b_dec                            o_i[3:6] is the velocity increment / dt
+  v+        = v + dt o_i[3:6],   p+ = p + dt v+            (semi-implicit Euler)
+
+Linearization (Sec. V-A "Linearization" and eq. linearized_dynamics): each node's
+local dynamics are differentiated independently by forward-mode automatic
+differentiation (value, tangent) pairs seeded on the states of every node of
+its L-hop receptive set and on u.  ReLU uses the subgradient 0 at 0 (the
+derivative mask is z > 0).  The offset is c = f(xhat,uhat) - sum_j A^{ij} xhat^j - B uhat.
+
+``activation='identity'`` replaces every ReLU by the identity; it exists only
+so the tests can compare against a closed-form affine model.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .graph import ball, in_neighbours, jacobian_pattern
+
+
+def _act(z, activation):
+    if activation == "identity":
+        return z, np.ones_like(z)
+    mask = (z > 0).astype(np.float64)
+    return z * mask, mask
+
+
+def node_input(x, u, i, act):
+    """[x^i; P^i u] with P^i selecting node i's 3 force inputs (zero if unactuated)."""
+    f = np.zeros(3)
+    hit = np.nonzero(np.asarray(act) == i)[0]
+    if hit.size:
+        a = int(hit[0])
+        f = np.asarray(u[3 * a:3 * a + 3], dtype=np.float64)
+    return np.concatenate([x[i], f])
+
+
+def gnn_forward(x, u, W, row_ptr, col, act, activation="relu"):
+    """One step x -> x+ for every node; x is [M][6], returns [M][6]."""
+    M = x.shape[0]
+    inp = np.stack([node_input(x, u, i, act) for i in range(M)])
+    h, _ = _act(inp @ W.W_enc.T + W.b_enc, activation)
+    for l in range(W.L):
+        agg = np.zeros_like(h)
+        for i in range(M):
+            for j in in_neighbours(row_ptr, col, i):
+                e = np.concatenate([h[i], h[i] - h[j]])
+                m, _ = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
+                agg[i] += m
+        h, _ = _act(np.concatenate([h, agg], axis=1) @ W.W_node[l].T + W.b_node[l], activation)
+    o = h @ W.W_dec.T + W.b_dec
+    vn = x[:, 3:] + W.dt * o[:, 3:6]
+    pn = x[:, :3] + W.dt * vn
+    return np.concatenate([pn, vn], axis=1)
+
+
+def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
+    """Forward-mode derivative of f^i on node i's receptive subgraph.
+
+    Returns (f_i [6], S (sorted receptive nodes), J [6][6|S| + nu]) where the
+    columns of J are the seeds x^{S[0]}, x^{S[1]}, ..., then u.
+    """
+    L = W.L
+    nu = u.shape[0]
+    S = ball(row_ptr, col, i, L)
+    T = 6 * len(S) + nu
+    pos = {j: p for p, j in enumerate(S)}
+    du = np.zeros((nu, T))
+    du[:, 6 * len(S):] = np.eye(nu)
+
+    def seed_x(j):
+        t = np.zeros((6, T))
+        t[:, 6 * pos[j]:6 * pos[j] + 6] = np.eye(6)
+        return t
+
+    # encoder on every node of the receptive set
+    h, dh = {}, {}
+    for j in S:
+        inp = node_input(x, u, j, act)
+        dinp = np.vstack([seed_x(j), np.zeros((3, T))])
+        hit = np.nonzero(np.asarray(act) == j)[0]
+        if hit.size:
+            a = int(hit[0])
+            dinp[6:9] = du[3 * a:3 * a + 3]
+        z = W.W_enc @ inp + W.b_enc
+        hv, mask = _act(z, activation)
+        h[j], dh[j] = hv, mask[:, None] * (W.W_enc @ dinp)
+    # message-passing rounds: after round l only nodes within L-1-l hops are needed
+    for l in range(L):
+        keep = ball(row_ptr, col, i, L - 1 - l)
+        nh, ndh = {}, {}
+        for n in keep:
+            agg = np.zeros(W.Hd)
+            dagg = np.zeros((W.Hd, T))
+            for j in in_neighbours(row_ptr, col, n):
+                e = np.concatenate([h[n], h[n] - h[j]])
+                de = np.vstack([dh[n], dh[n] - dh[j]])
+                m, mask = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
+                agg += m
+                dagg += mask[:, None] * (W.W_edge[l] @ de)
+            z = W.W_node[l] @ np.concatenate([h[n], agg]) + W.b_node[l]
+            hv, mask = _act(z, activation)
+            nh[n] = hv
+            ndh[n] = mask[:, None] * (W.W_node[l] @ np.vstack([dh[n], dagg]))
+        h, dh = nh, ndh
+    o = W.W_dec @ h[i] + W.b_dec
+    do = W.W_dec @ dh[i]
+    dx_i = seed_x(i)
+    vn = x[i, 3:] + W.dt * o[3:6]
+    dvn = dx_i[3:] + W.dt * do[3:6]
+    pn = x[i, :3] + W.dt * vn
+    dpn = dx_i[:3] + W.dt * dvn
+    return np.concatenate([pn, vn]), S, np.vstack([dpn, dvn])
+
+
+def gnn_linearize(xhat, uhat, W, row_ptr, col, act, stages=None, nodes=None,
+                  activation="relu"):
+    """A^{ij}_k (L-hop pattern, ascending), B^i_k, c^i_k and f^i_k.
+
+    Only the requested (stage, node) pairs are computed (all by default); the
+    remaining entries are left as NaN so that accidental use is visible.
+    Returns (prow, pcol, A [N][nnz][6][6], B [N][M][6][nu], c [N][M][6], f [N][M][6]).
+    """
+    N, nu = uhat.shape
+    M = xhat.shape[1]
+    prow, pcol = jacobian_pattern(row_ptr, col, M, W.L)
+    A = np.full((N, len(pcol), 6, 6), np.nan)
+    B = np.full((N, M, 6, nu), np.nan)
+    c = np.full((N, M, 6), np.nan)
+    f = np.full((N, M, 6), np.nan)
+    for k in (range(N) if stages is None else stages):
+        for i in (range(M) if nodes is None else nodes):
+            fi, S, J = gnn_linearize_node(xhat[k], uhat[k], W, row_ptr, col, act, i, activation)
+            assert list(pcol[prow[i]:prow[i + 1]]) == S
+            lin = J[:, 6 * len(S):] @ uhat[k]
+            for p, j in enumerate(S):
+                A[k, prow[i] + p] = J[:, 6 * p:6 * p + 6]
+                lin = lin + J[:, 6 * p:6 * p + 6] @ xhat[k, j]
+            B[k, i] = J[:, 6 * len(S):]
+            c[k, i] = fi - lin
+            f[k, i] = fi
+    return prow, pcol, A, B, c, f

@@ -1,0 +1,342 @@
+"""Seeded synthetic workloads for graph-neural MPC on chain graphs.
+
+This module only *constructs inputs*: graphs, model parameters, initial
+states, nominal trajectories, cost weights and constraint rows.  It holds
+none of the method's arithmetic (no dynamics, no Jacobians, no condensing),
+so both the HIP path and the FP64 oracle can draw their inputs from it.
+
+Every array is produced by ``numpy.random.default_rng(seed)`` (PCG64) in a
+fixed draw order, in float64; callers cast to the precision they run in.
+
+Readings of the paper that shape the inputs (Sec. IV-A, Sec. V-A):
+  * the graph is a chain of M nodes with directed edges j -> i for
+    1 <= |i - j| <= hops (both directions present, no self loops), stored as
+    CSR indexed by the receiver i (the edge e^{ij} runs from v_j to v_i);
+  * each node carries x^i = [p^i; v^i] in R^6; stacked states are node-major;
+  * the inputs are 3D forces at a set of actuated nodes, u = [f_a1; f_a2; ...]
+    in ascending node order, so n_u = 3 * n_act;
+  * the synthetic nominal trajectory is a seeded random walk around x0 (the
+    method linearizes around any given trajectory; it does not have to be a
+    rollout of the model).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NBX = 6  # states per node: position (3) and velocity (3)
+
+
+# --------------------------------------------------------------------------
+# graph
+# --------------------------------------------------------------------------
+def chain_csr(M: int, hops: int):
+    """Incoming-edge CSR of a chain: row i lists j with 1 <= |i-j| <= hops."""
+    row_ptr = np.zeros(M + 1, dtype=np.int32)
+    cols = []
+    for i in range(M):
+        nb = [j for j in range(max(0, i - hops), min(M, i + hops + 1)) if j != i]
+        cols.extend(nb)
+        row_ptr[i + 1] = row_ptr[i] + len(nb)
+    return row_ptr, np.asarray(cols, dtype=np.int32)
+
+
+def actuated_nodes(M: int, n_act: int):
+    """0-based actuated nodes: node ceil(a*M/n_act) (1-based) for a = 1..n_act.
+
+    For M=10, n_act=2 this is nodes 5 and 10 (1-based); for n_act=4 it is
+    M/4, M/2, 3M/4 and M.
+    """
+    return np.asarray([int(math.ceil(a * M / n_act)) - 1 for a in range(1, n_act + 1)],
+                      dtype=np.int32)
+
+
+# --------------------------------------------------------------------------
+# model parameters
+# --------------------------------------------------------------------------
+@dataclass
+class MSDParams:
+    """Mass-spring-damper chain: springs/dampers along every graph edge."""
+    k: float = 10.0
+    c: float = 0.1
+    m: float = 1.0
+    dt: float = 0.01
+    k3: float = 0.0          # cubic spring coefficient (0 = linear)
+    gravity: float = 0.0     # magnitude of gravity along -z (0 = off)
+    anchor: int = 0          # node tied to the ground by (k, c, k3)
+
+
+@dataclass
+class GNNWeights:
+    """Weights of the message-passing GNN, float64, (out, in) row-major.
+
+    enc: Hd x (6 + 3)   encoder on [x^i; P^i u]
+    edge[l]: Hd x 2Hd   edge MLP on [h_i; h_i - h_j]
+    node[l]: Hd x 2Hd   node MLP on [h_i; sum_j m_ij]
+    dec: 6 x Hd         decoder; channels 3..5 are the velocity increment
+    """
+    Hd: int
+    L: int
+    W_enc: np.ndarray
+    b_enc: np.ndarray
+    W_edge: list
+    b_edge: list
+    W_node: list
+    b_node: list
+    W_dec: np.ndarray
+    b_dec: np.ndarray
+    dt: float = 0.01
+
+    def rounded_bf16(self) -> "GNNWeights":
+        """Copy with every weight and bias rounded to bfloat16 (RNE), as float64."""
+        r = bf16_round
+        return GNNWeights(self.Hd, self.L, r(self.W_enc), r(self.b_enc),
+                          [r(w) for w in self.W_edge], [r(b) for b in self.b_edge],
+                          [r(w) for w in self.W_node], [r(b) for b in self.b_node],
+                          r(self.W_dec), r(self.b_dec), self.dt)
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def xavier(rng, fan_out: int, fan_in: int):
+    bound = math.sqrt(6.0 / (fan_in + fan_out))
+    return rng.uniform(-bound, bound, size=(fan_out, fan_in))
+
+
+def gnn_weights(seed: int, Hd: int, L: int, dt: float = 0.01, nin: int = 9,
+                nout: int = 6, bias_scale: float = 0.0) -> GNNWeights:
+    """Xavier-uniform weights (gain 1), drawn enc, (edge, node) x L, dec.
+
+    Biases are zero unless ``bias_scale`` > 0, in which case they are drawn
+    uniformly from [0, bias_scale) after all weights (used by tests that need
+    every ReLU active).
+    """
+    rng = np.random.default_rng(seed)
+    W_enc = xavier(rng, Hd, nin)
+    W_edge, W_node = [], []
+    for _ in range(L):
+        W_edge.append(xavier(rng, Hd, 2 * Hd))
+        W_node.append(xavier(rng, Hd, 2 * Hd))
+    W_dec = xavier(rng, nout, Hd)
+    if bias_scale > 0:
+        b_enc = rng.uniform(0, bias_scale, Hd)
+        b_edge = [rng.uniform(0, bias_scale, Hd) for _ in range(L)]
+        b_node = [rng.uniform(0, bias_scale, Hd) for _ in range(L)]
+        b_dec = rng.uniform(0, bias_scale, nout)
+    else:
+        b_enc = np.zeros(Hd)
+        b_edge = [np.zeros(Hd) for _ in range(L)]
+        b_node = [np.zeros(Hd) for _ in range(L)]
+        b_dec = np.zeros(nout)
+    return GNNWeights(Hd, L, W_enc, b_enc, W_edge, b_edge, W_node, b_node, W_dec, b_dec, dt)
+
+
+# --------------------------------------------------------------------------
+# trajectories, costs, constraints
+# --------------------------------------------------------------------------
+def initial_state(rng, M: int, sigma: float):
+    return rng.normal(0.0, sigma, size=(M, NBX))
+
+
+def nominal_trajectory(rng, x0, N: int, nu: int, walk: float):
+    """x_hat[0] = x0, x_hat[k+1] = x_hat[k] + walk * N(0, 1); u_hat ~ U(-1, 1)."""
+    M = x0.shape[0]
+    xhat = np.empty((N + 1, M, NBX))
+    xhat[0] = x0
+    for k in range(N):
+        xhat[k + 1] = xhat[k] + walk * rng.normal(size=(M, NBX))
+    uhat = rng.uniform(-1.0, 1.0, size=(N, nu))
+    return xhat, uhat
+
+
+@dataclass
+class Costs:
+    Q: np.ndarray      # [N+1][M][6] diagonal, or [N+1][M][6][6] full
+    q: np.ndarray      # [N+1][M][6]
+    R: np.ndarray      # [N][nu][nu]
+    r: np.ndarray      # [N][nu]
+    full_Q: bool = False
+
+
+def tracking_costs(M: int, N: int, nu: int, qdiag, rho_r: float):
+    Q = np.broadcast_to(np.asarray(qdiag, dtype=np.float64), (N + 1, M, NBX)).copy()
+    R = np.broadcast_to(rho_r * np.eye(nu), (N, nu, nu)).copy()
+    return Costs(Q, np.zeros((N + 1, M, NBX)), R, np.zeros((N, nu)))
+
+
+def random_costs(rng, M: int, N: int, nu: int, full_Q: bool = False):
+    """Random positive-definite stage costs with nonzero linear terms."""
+    if full_Q:
+        G = rng.normal(size=(N + 1, M, NBX, NBX))
+        Q = np.einsum("kmab,kmcb->kmac", G, G) / NBX + 0.1 * np.eye(NBX)
+    else:
+        Q = rng.uniform(0.1, 2.0, size=(N + 1, M, NBX))
+    G = rng.normal(size=(N, nu, nu))
+    R = np.einsum("kab,kcb->kac", G, G) / nu + 0.1 * np.eye(nu)
+    q = rng.normal(size=(N + 1, M, NBX))
+    r = rng.normal(size=(N, nu))
+    return Costs(Q, q, R, r, full_Q)
+
+
+@dataclass
+class StateRows:
+    """Half-space rows C x^i_k <= d on single nodes (Sec. IV-B)."""
+    node: np.ndarray    # int32 [n_c]
+    stage: np.ndarray   # int32 [n_c], 1..N
+    C: np.ndarray       # [n_c][6]
+    d: np.ndarray       # [n_c]
+
+    @property
+    def n(self):
+        return int(self.node.shape[0])
+
+
+def no_rows():
+    return StateRows(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, NBX)), np.zeros(0))
+
+
+def random_rows(rng, M: int, N: int, n_c: int):
+    node = rng.integers(0, M, size=n_c).astype(np.int32)
+    stage = rng.integers(1, N + 1, size=n_c).astype(np.int32)
+    C = rng.normal(size=(n_c, NBX))
+    d = rng.normal(size=n_c)
+    return StateRows(node, stage, C, d)
+
+
+def sphere_obstacle_rows(rng, M: int, N: int, xhat, radius: float = 0.1,
+                         clearance: float = 0.15, n_nodes: int = 10):
+    """Node-position half-spaces keeping nodes outside a sphere obstacle.
+
+    Rest positions hang along -z: r^i = (0, 0, -i/M).  The sphere (radius
+    ``radius``) sits beside a seeded node c in [0.4M, 0.6M) at distance
+    ``clearance`` along a seeded horizontal unit vector.  For each of the
+    ``n_nodes`` nodes nearest the centre and each stage k = 1..N, the row
+    linearizes "outside the sphere" around the nominal position:
+    n = unit(r^i + p_hat^i_k - centre), C = [-n^T, 0], d = n^T (r^i - centre) - radius,
+    so that C x^i_k <= d  <=>  n^T (r^i + p^i_k - centre) >= radius.
+    """
+    rest = np.zeros((M, 3))
+    rest[:, 2] = -np.arange(M) / M
+    c = int(rng.integers(int(0.4 * M), int(0.6 * M)))
+    ang = rng.uniform(0, 2 * math.pi)
+    w = np.array([math.cos(ang), math.sin(ang), 0.0])
+    centre = rest[c] + clearance * w
+    dist = np.linalg.norm(rest - centre, axis=1)
+    nodes = np.sort(np.argsort(dist, kind="stable")[:n_nodes])
+    node, stage, C, d = [], [], [], []
+    for k in range(1, N + 1):
+        for i in nodes:
+            v = rest[i] + xhat[k, i, :3] - centre
+            n = v / np.linalg.norm(v)
+            node.append(i)
+            stage.append(k)
+            C.append(np.concatenate([-n, np.zeros(3)]))
+            d.append(float(n @ (rest[i] - centre)) - radius)
+    return StateRows(np.asarray(node, np.int32), np.asarray(stage, np.int32),
+                     np.asarray(C), np.asarray(d))
+
+
+# --------------------------------------------------------------------------
+# complete problem instances
+# --------------------------------------------------------------------------
+@dataclass
+class Problem:
+    name: str
+    M: int
+    hops: int
+    N: int
+    act: np.ndarray
+    row_ptr: np.ndarray
+    col: np.ndarray
+    x0: np.ndarray
+    xhat: np.ndarray
+    uhat: np.ndarray
+    costs: Costs
+    rows: StateRows
+    lb: np.ndarray
+    ub: np.ndarray
+    model: str                      # "msd" or "gnn"
+    msd: MSDParams = field(default_factory=MSDParams)
+    gnn: GNNWeights | None = None
+    dtype: str = "f32"              # arithmetic of condensing: "f64" | "f32"
+    gnn_dtype: str = "f32"          # arithmetic of the GNN MLPs: "f32" | "bf16"
+
+    @property
+    def nu(self):
+        return 3 * len(self.act)
+
+    @property
+    def L(self):
+        return self.gnn.L if self.model == "gnn" else 1
+
+    @property
+    def E(self):
+        return int(self.col.shape[0])
+
+
+def make_problem(name: str, *, M: int, hops: int, N: int, n_act: int, model: str,
+                 seed: int, Hd: int = 64, L: int = 2, weight_seed: int | None = None,
+                 x0_sigma: float = 0.1, walk: float = 0.0, qdiag=(1, 1, 1, .01, .01, .01),
+                 rho_r: float = 0.1, obstacle: bool = False, random_cost: bool = False,
+                 full_Q: bool = False, n_random_rows: int = 0, umax: float = 1.0,
+                 msd: MSDParams | None = None, dtype: str = "f32", gnn_dtype: str = "f32",
+                 bias_scale: float = 0.0) -> Problem:
+    """Build one seeded instance.  Draw order: weights (own seed), x0, x_hat/u_hat,
+    then obstacle or random rows, then random costs."""
+    act = actuated_nodes(M, n_act)
+    nu = 3 * n_act
+    row_ptr, col = chain_csr(M, hops)
+    gnn = None
+    if model == "gnn":
+        gnn = gnn_weights(seed if weight_seed is None else weight_seed, Hd, L,
+                          dt=(msd or MSDParams()).dt, bias_scale=bias_scale)
+    rng = np.random.default_rng(seed)
+    x0 = initial_state(rng, M, x0_sigma)
+    xhat, uhat = nominal_trajectory(rng, x0, N, nu, walk)
+    if obstacle:
+        rows = sphere_obstacle_rows(rng, M, N, xhat)
+    elif n_random_rows:
+        rows = random_rows(rng, M, N, n_random_rows)
+    else:
+        rows = no_rows()
+    if random_cost:
+        costs = random_costs(rng, M, N, nu, full_Q)
+    else:
+        costs = tracking_costs(M, N, nu, qdiag, rho_r)
+    lb = -umax * np.ones(N * nu)
+    ub = umax * np.ones(N * nu)
+    return Problem(name, M, hops, N, act, row_ptr, col, x0, xhat, uhat, costs, rows, lb, ub,
+                   model, msd or MSDParams(), gnn, dtype, gnn_dtype)
+
+
+def msd10_fp64() -> Problem:
+    """Plain condensing in FP64: linear MSD chain of 10 nodes, nearest-neighbour
+    edges, forces at nodes 5 and 10, N=10, Q=I, R=0.1I, |u|<=1, x0 ~ N(0, 0.1^2)."""
+    return make_problem("msd10_fp64", M=10, hops=1, N=10, n_act=2, model="msd", seed=0,
+                        x0_sigma=0.1, qdiag=(1, 1, 1, 1, 1, 1), dtype="f64")
+
+
+def gnn100_fp32() -> Problem:
+    """GNN-linearized condensing in FP32: 100-node 1-2-hop chain, Hd=64, L=2,
+    forces at nodes 50 and 100, N=20."""
+    return make_problem("gnn100_fp32", M=100, hops=2, N=20, n_act=2, model="gnn", seed=2,
+                        weight_seed=1, Hd=64, L=2, x0_sigma=0.02, walk=0.002)
+
+
+def gnn1000_bf16(model: str = "gnn") -> Problem:
+    """Paper-scale single instance: 1000-node 1-2-hop chain, Hd=128, L=3 (BF16
+    MLPs, FP32 condensing), forces at 4 nodes (n_u=12), N=20, 200 obstacle rows.
+    ``model='msd'`` gives the plain (analytic-Jacobian) form on the same graph."""
+    return make_problem("gnn1000_bf16" if model == "gnn" else "msd1000_fp32",
+                        M=1000, hops=2, N=20, n_act=4, model=model, seed=3, Hd=128, L=3,
+                        x0_sigma=0.02, walk=0.002, obstacle=True,
+                        gnn_dtype="bf16" if model == "gnn" else "f32")

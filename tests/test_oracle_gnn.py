@@ -1,0 +1,138 @@
+"""Pins of the oracle's GNN model and its per-node forward-mode linearization."""
+import numpy as np
+import pytest
+
+from oracle.gnn import gnn_forward, gnn_linearize
+from oracle.graph import ball
+from paper_2602_17601_amd import workloads as wl
+
+
+def _small(M=7, hops=2, Hd=12, L=2, seed=5, bias_scale=0.0):
+    rp, col = wl.chain_csr(M, hops)
+    act = wl.actuated_nodes(M, 2)
+    W = wl.gnn_weights(seed, Hd, L, bias_scale=bias_scale)
+    rng = np.random.default_rng(seed + 100)
+    x = rng.normal(0, 0.5, size=(M, 6))
+    u = rng.uniform(-1, 1, size=6)
+    return rp, col, act, W, x, u
+
+
+def _dense_jac(prow, pcol, A, M):
+    D = np.zeros((6 * M, 6 * M))
+    for i in range(M):
+        for e in range(prow[i], prow[i + 1]):
+            D[6 * i:6 * i + 6, 6 * pcol[e]:6 * pcol[e] + 6] = A[e]
+    return D
+
+
+def test_forward_mode_matches_central_differences():
+    rp, col, act, W, x, u = _small()
+    M = x.shape[0]
+    prow, pcol, A, B, c, f = gnn_linearize(x[None], u[None], W, rp, col, act)
+    J = _dense_jac(prow, pcol, A[0], M)
+    h = 1e-6
+    xv = x.reshape(-1)
+    Jfd = np.zeros_like(J)
+    for a in range(6 * M):
+        xp = xv.copy(); xp[a] += h
+        xm = xv.copy(); xm[a] -= h
+        Jfd[:, a] = (gnn_forward(xp.reshape(M, 6), u, W, rp, col, act)
+                     - gnn_forward(xm.reshape(M, 6), u, W, rp, col, act)).reshape(-1) / (2 * h)
+    np.testing.assert_allclose(J, Jfd, atol=1e-8)
+    Bfd = np.zeros((6 * M, 6))
+    for a in range(6):
+        up = u.copy(); up[a] += h
+        um = u.copy(); um[a] -= h
+        Bfd[:, a] = (gnn_forward(x, up, W, rp, col, act)
+                     - gnn_forward(x, um, W, rp, col, act)).reshape(-1) / (2 * h)
+    np.testing.assert_allclose(B[0].reshape(6 * M, 6), Bfd, atol=1e-8)
+    # the per-node value equals the whole-graph forward
+    np.testing.assert_allclose(f[0], gnn_forward(x, u, W, rp, col, act), atol=1e-14)
+    # something is actually nonzero off the diagonal at L hops
+    assert np.abs(J - np.eye(6 * M)).max() > 1e-4
+
+
+def test_identity_activation_matches_kronecker_closed_form():
+    """With every activation the identity the model is affine, and its state
+    Jacobian is a product of per-layer Kronecker operators:
+      encoder  E  = I_M (x) W_enc[:, :6]
+      layer l  T_l = I_M (x) W_n1 + D (x) (W_n2 (W_a + W_b)) - Adj (x) (W_n2 W_b)
+      decoder  O  = I_M (x) W_dec
+    with W_e = [W_a W_b], W_n = [W_n1 W_n2], D = diag(in-degree), Adj[i, j] = 1 for j in N_i;
+    then dv+ = [0 I] + dt O[3:6] T_L ... T_1 E and dp+ = [I 0] + dt dv+."""
+    M, Hd, L = 6, 10, 2
+    rp, col, act, W, x, u = _small(M=M, Hd=Hd, L=L, seed=9)
+    prow, pcol, A, B, c, f = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity")
+    J = _dense_jac(prow, pcol, A[0], M)
+    Adj = np.zeros((M, M))
+    for i in range(M):
+        for j in col[rp[i]:rp[i + 1]]:
+            Adj[i, j] = 1.0
+    D = np.diag(Adj.sum(1))
+    I = np.eye(M)
+    Z = np.kron(I, W.W_enc[:, :6])
+    for l in range(L):
+        Wa, Wb = W.W_edge[l][:, :Hd], W.W_edge[l][:, Hd:]
+        Wn1, Wn2 = W.W_node[l][:, :Hd], W.W_node[l][:, Hd:]
+        T = np.kron(I, Wn1) + np.kron(D, Wn2 @ (Wa + Wb)) - np.kron(Adj, Wn2 @ Wb)
+        Z = T @ Z
+    O = np.kron(I, W.W_dec) @ Z                      # [6M][6M], rows (node, channel)
+    sel_v = np.kron(I, np.hstack([np.zeros((3, 3)), np.eye(3)]))
+    sel_p = np.kron(I, np.hstack([np.eye(3), np.zeros((3, 3))]))
+    dO_v = O.reshape(M, 6, 6 * M)[:, 3:6, :].reshape(3 * M, 6 * M)
+    dv = sel_v + W.dt * dO_v
+    dp = sel_p + W.dt * dv
+    ref = np.stack([dp.reshape(M, 3, 6 * M), dv.reshape(M, 3, 6 * M)], axis=1)
+    ref = ref.transpose(0, 1, 2, 3).reshape(M, 6, 6 * M).reshape(6 * M, 6 * M)
+    np.testing.assert_allclose(J, ref, atol=1e-12)
+
+
+def test_locality_outside_receptive_field_is_exact_zero():
+    rp, col, act, W, x, u = _small(M=12, L=2)
+    M = 12
+    base = gnn_forward(x, u, W, rp, col, act)
+    for i in (0, 5, 11):
+        inside = set(ball(rp, col, i, W.L))
+        for j in range(M):
+            if j in inside:
+                continue
+            x2 = x.copy()
+            x2[j] += 0.37
+            assert np.array_equal(gnn_forward(x2, u, W, rp, col, act)[i], base[i])
+
+
+def test_permutation_equivariance():
+    """Relabelling the nodes (and the graph and actuators with them) permutes
+    the next states and conjugates the Jacobian blocks."""
+    rp, col, act, W, x, u = _small(M=8, L=2)
+    M = 8
+    perm = np.random.default_rng(3).permutation(M)        # new label of old node
+    inv = np.argsort(perm)
+    rows = [[] for _ in range(M)]
+    for i in range(M):
+        for j in col[rp[i]:rp[i + 1]]:
+            rows[perm[i]].append(perm[j])
+    rp2 = np.zeros(M + 1, np.int32)
+    col2 = []
+    for i in range(M):
+        col2 += sorted(rows[i])
+        rp2[i + 1] = len(col2)
+    col2 = np.asarray(col2, np.int32)
+    # actuator order must keep u's layout: actuator a is old node act[a], new label perm[act[a]]
+    act2 = perm[act]
+    x2 = x[inv]
+    f1 = gnn_forward(x, u, W, rp, col, act)
+    f2 = gnn_forward(x2, u, W, rp2, col2, act2)
+    np.testing.assert_allclose(f2[perm], f1, atol=1e-13)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    vals = np.array([1.0, 1.00390625, 1.005859375, 1.0078125, -3.140625, 1e-3])
+    r = wl.bf16_round(vals)
+    # 1 + 2^-8 is exactly halfway between 1 and 1 + 2^-7: ties to even -> 1
+    assert r[1] == 1.0
+    # 1 + 1.5*2^-8 rounds up to 1 + 2^-7
+    assert r[2] == 1.0078125
+    assert r[3] == 1.0078125
+    assert r[4] == -3.140625
+    assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
