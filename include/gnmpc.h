@@ -1,0 +1,237 @@
+/*
+ * gnmpc -- graph-neural MPC hot path on AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of the HIP library libgnmpc.so.  Plain pointers and sizes only.
+ *
+ * The library implements, for one MPC step of Algorithm 1 of
+ * "Graph Neural Model Predictive Control for High-Dimensional Systems":
+ *   - linearization of the node dynamics into block-sparse Jacobians
+ *     A^{ij}_k, B^i_k and offsets c^i_k (Sec. V-A, eq. linearized_dynamics),
+ *     either of the message-passing GNN model (Sec. V-A eq. forward_dynamics)
+ *     or of an analytic mass-spring-damper chain;
+ *   - graph-sparse condensing (Sec. V-B, Thm. 1 proof, eqs. sparse_gamma_i_xb,
+ *     sparse_gamma_i_u, H, g and the stacked constraint rows);
+ *   - the condensed QP (Sec. III-B eq. condensed_matrices) with box input
+ *     bounds, solved by ADMM.
+ *
+ * Conventions (shared by every entry point)
+ *   Layouts are row-major and C-contiguous.  A node state is x^i = [p^i; v^i]
+ *   (6 values); stacked states are stage-major then node-major.
+ *   Cost convention: stage cost 1/2 x'Qx + q'x + 1/2 u'Ru + r'u and QP
+ *   objective 1/2 u'Hu + g'u (the paper's H and g formulas hold exactly in
+ *   this convention).
+ *   "device" pointers are HIP device allocations on the plan's device, owned
+ *   by the caller; "host" pointers are ordinary memory, read during the call
+ *   only.  `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *   take a stream enqueue work and return without synchronizing; results are
+ *   valid once the stream has been synchronized.
+ *   Every call returns a gnmpc_status.  Arguments are validated on the host
+ *   before any GPU work is enqueued; on an error nothing is enqueued and
+ *   gnmpc_plan_last_error() describes the problem.  Errors found on the GPU
+ *   (non-finite data, QP status) are reported in device-side info structs.
+ *   A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef GNMPC_H
+#define GNMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GNMPC_OK = 0,
+  GNMPC_INVALID_ARG = 1,     /* null pointer, non-positive size, bad enum      */
+  GNMPC_BAD_GRAPH = 2,       /* malformed CSR: unsorted, duplicate, self loop, out of range */
+  GNMPC_SHAPE = 3,           /* size disagrees with the plan                     */
+  GNMPC_UNSUPPORTED = 4,     /* valid request outside what this build supports  */
+  GNMPC_HIP_ERROR = 5,       /* a HIP runtime call failed                       */
+  GNMPC_BAD_CONSTRAINT = 6,  /* state row on stage 0 or outside 1..N, bad node  */
+  GNMPC_NOT_READY = 7,       /* graph / model / rows not set yet                */
+  GNMPC_NO_DEVICE = 8        /* no usable GPU                                   */
+} gnmpc_status;
+
+typedef enum { GNMPC_F64 = 0, GNMPC_F32 = 1, GNMPC_BF16 = 2 } gnmpc_dtype;
+
+/* QP status written to gnmpc_qp_info.status on the device. */
+typedef enum {
+  GNMPC_QP_SOLVED = 0,
+  GNMPC_QP_MAXITER = 1,      /* soft: the last iterate is returned              */
+  GNMPC_QP_PRIMAL_INFEASIBLE = 2,
+  GNMPC_QP_NONFINITE = 3,
+  GNMPC_QP_NOT_PD = 4
+} gnmpc_qp_status;
+
+typedef struct gnmpc_plan gnmpc_plan;
+
+/* Problem dimensions fixed at plan creation. */
+typedef struct {
+  int32_t M;        /* nodes |V|                                                */
+  int32_t nu;       /* inputs n_u                                               */
+  int32_t N;        /* horizon                                                  */
+  int32_t n_c_max;  /* maximum number of single-node state rows                  */
+  int32_t dtype;    /* GNMPC_F64 or GNMPC_F32: arithmetic of linearize outputs,  */
+                    /* condensing and the QP (GNN MLPs may run in BF16, below)  */
+} gnmpc_dims;
+
+/* Mass-spring-damper chain (the plain, analytic-Jacobian form).  Springs and
+ * dampers act along every graph edge; node `anchor` (or none if -1) is tied to
+ * the ground by the same spring and damper.  F(d) = k d + k3 |d|^2 d;
+ * a^i = (sum_j F(p^j-p^i) + c (v^j-v^i) + anchor terms + f^i) / m - gravity e_z;
+ * v+ = v + dt a, p+ = p + dt v+. */
+typedef struct {
+  double k, c, m, dt, k3, gravity;
+  int32_t anchor;
+  int32_t reserved;
+} gnmpc_msd_params;
+
+/* Message-passing GNN of Sec. V-A (sum aggregation, ReLU, edge feature from
+ * the relative state):
+ *   h0_i = relu(W_enc [x^i; P^i u] + b_enc)
+ *   m_ij = relu(W_e[l] [h_i; h_i - h_j] + b_e[l]),  j in N_i
+ *   h_i <- relu(W_n[l] [h_i; sum_j m_ij] + b_n[l]),  l = 0..L-1
+ *   o_i  = W_dec h_i + b_dec;  v+ = v + dt o_i[3:6];  p+ = p + dt v+
+ * Weights are passed packed, float64, (out, in) row-major, in the order
+ * W_enc[Hd][9], b_enc[Hd], then per layer W_e[Hd][2Hd], b_e[Hd], W_n[Hd][2Hd],
+ * b_n[Hd], then W_dec[6][Hd], b_dec[6]. */
+typedef struct {
+  int32_t Hd;       /* hidden width (multiple of 32, <= 256)                     */
+  int32_t L;        /* message-passing rounds (must equal the graph's L)          */
+  int32_t dtype;    /* GNMPC_F32 or GNMPC_BF16 (BF16 operands, FP32 accumulate)   */
+  int32_t reserved;
+  double dt;
+} gnmpc_gnn_desc;
+
+/* ADMM settings (operator splitting in the form of Stellato et al., OSQP). */
+typedef struct {
+  double rho;        /* penalty of the inequality rows (> 0)                     */
+  double sigma;      /* primal regularization (> 0)                              */
+  double alpha;      /* over-relaxation in (0, 2)                                */
+  double eps_abs, eps_rel;
+  double kappa_fp64; /* condition bound above which the factorization and the   */
+                     /* iterations switch to FP64 (e.g. 1e7)                     */
+  int32_t max_iter;
+  int32_t check_every;
+} gnmpc_admm_settings;
+
+/* Device-side QP report. */
+typedef struct {
+  int32_t status;    /* gnmpc_qp_status                                          */
+  int32_t iters;
+  int32_t used_fp64; /* 1 if the condition estimate exceeded kappa_fp64          */
+  int32_t reserved;
+  double prim_res, dual_res, kappa_est, obj;
+} gnmpc_qp_info;
+
+const char* gnmpc_version(void);
+const char* gnmpc_status_string(int32_t status);
+
+/* ---------------- host-only graph utilities (no GPU needed) ---------------- */
+
+/* Check an incoming-edge CSR: row i lists the senders j of edges j -> i
+ * (Sec. III-A: the edge e^{ij} runs from v_j to v_i and N_i is the set of
+ * senders).  Rows must be strictly ascending, 0 <= j < M, j != i,
+ * row_ptr[0] = 0, row_ptr[M] = E, non-decreasing.  Returns GNMPC_OK or
+ * GNMPC_BAD_GRAPH / GNMPC_INVALID_ARG. */
+gnmpc_status gnmpc_graph_check(const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t E);
+
+/* Block pattern of the L-round Jacobian (Sec. V-A eq. linearized_dynamics
+ * with Assumption 1 applied L times): row i holds every node that reaches i
+ * in at most L hops, i included, ascending.  Host arrays; pass col_out =
+ * NULL to query the size in *nnz_out; otherwise col_out must hold `cap`
+ * entries.  row_ptr_out has M+1 entries. */
+gnmpc_status gnmpc_graph_closure(const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t E,
+                                 int32_t L, int32_t* row_ptr_out, int32_t* col_out, int64_t cap,
+                                 int64_t* nnz_out);
+
+/* ---------------- plans ---------------- */
+
+/* Create a plan on `device`; all workspace for the given dimensions is
+ * allocated here so that the per-step calls allocate nothing. */
+gnmpc_status gnmpc_plan_create(gnmpc_plan** plan, const gnmpc_dims* dims, int32_t device);
+void gnmpc_plan_destroy(gnmpc_plan* plan);
+/* Text of the last error on this plan ("" if none).  Owned by the plan. */
+const char* gnmpc_plan_last_error(const gnmpc_plan* plan);
+
+/* Set the graph (host CSR of incoming edges, checked as gnmpc_graph_check)
+ * and the number of message-passing rounds L that fixes the Jacobian pattern
+ * (L = 1 for the mass-spring-damper model).  Builds and uploads the pattern. */
+gnmpc_status gnmpc_graph_set(gnmpc_plan* plan, const int32_t* row_ptr, const int32_t* col,
+                             int32_t M, int32_t E, int32_t L);
+/* Number of Jacobian blocks nnz of the plan's pattern. */
+gnmpc_status gnmpc_graph_nnz(const gnmpc_plan* plan, int64_t* nnz);
+/* Copy the plan's pattern to host arrays (row_ptr_out[M+1], col_out[nnz]). */
+gnmpc_status gnmpc_graph_pattern(const gnmpc_plan* plan, int32_t* row_ptr_out, int32_t* col_out);
+
+/* Choose the mass-spring-damper model.  act[n_act] are the actuated nodes
+ * (host, distinct, in [0, M)); u = [f_act[0]; f_act[1]; ...] so nu = 3 n_act. */
+gnmpc_status gnmpc_model_set_msd(gnmpc_plan* plan, const gnmpc_msd_params* prm,
+                                 const int32_t* act, int32_t n_act);
+
+/* Choose the GNN model; weights are host float64 packed as described at
+ * gnmpc_gnn_desc, n_weights their count.  The graph must have been set with
+ * the same L. */
+gnmpc_status gnmpc_model_set_gnn(gnmpc_plan* plan, const gnmpc_gnn_desc* desc,
+                                 const double* weights, int64_t n_weights,
+                                 const int32_t* act, int32_t n_act);
+
+/* Structure of the single-node state rows C x^{node}_{stage} <= d (Sec. IV-B:
+ * half-spaces X^i_k; condensed as in the stacked-constraint formula of
+ * Sec. V-B).  Host arrays of n_c entries; 1 <= stage <= N (stage-0 rows do not
+ * depend on u and are rejected with GNMPC_BAD_CONSTRAINT).  n_c <= n_c_max. */
+gnmpc_status gnmpc_rows_set(gnmpc_plan* plan, int32_t n_c, const int32_t* node, const int32_t* stage);
+
+/* ---------------- the per-step hot path ---------------- */
+
+/* Linearize the plan's model around (xhat, uhat) (Sec. V-A "Linearization";
+ * Algorithm 1 "Linearize GNN dynamics").  Device arrays of the plan dtype:
+ *   xhat [N+1][M][6] (stage N is unused), uhat [N][nu]
+ *   A    [N][nnz][6][6]  A^{ij}_k = d f^i / d x^j at stage k, blocks in pattern order
+ *   B    [N][M][6][nu]   B^i_k = d f^i / d u
+ *   c    [N][M][6]       c^i_k = f^i - sum_j A^{ij}_k xhat^j_k - B^i_k uhat_k
+ *   fnext[N][M][6]       f(xhat_k, uhat_k), may be NULL
+ * ReLU uses the subgradient 0 at 0. */
+gnmpc_status gnmpc_linearize(gnmpc_plan* plan, const void* xhat, const void* uhat,
+                             void* A, void* B, void* c, void* fnext, void* stream);
+
+/* Condense the linear time-varying OCP (Sec. V-B): propagate the sensitivities
+ * S^i_{k+1} = sum_{j in N~_i} A^{ij}_k S^j_k (+ B^i_k in column block k) and
+ * Gx^i_{k+1} = sum_j A^{ij}_k Gx^j_k + c^i_k from S_0 = 0, Gx_0 = x0, then form
+ *   H  = sum_k sum_i S^i_k' Q^i_k S^i_k + blkdiag(R_k)            [N nu][N nu], full symmetric
+ *   g  = sum_k sum_i S^i_k' (Q^i_k Gx^i_k + q^i_k) + [r_k]         [N nu]
+ *   Ct[t] = C_t S^{node_t}_{stage_t},  dt[t] = d_t - C_t Gx^{node_t}_{stage_t}   for each state row.
+ * Device arrays of the plan dtype: A, B, c as produced by gnmpc_linearize;
+ * x0 [M][6]; Q [N+1][M][6] (diagonal, Q_full = 0) or [N+1][M][6][6] (Q_full = 1);
+ * q [N+1][M][6]; R [N][nu][nu]; r [N][nu]; rowC [n_c][6]; rowd [n_c] (n_c as
+ * set by gnmpc_rows_set; may be NULL when n_c = 0); outputs H, g, Ct [n_c][N nu],
+ * dt [n_c]; Gx [N+1][M][6] may be NULL.  Sums are taken in a fixed order, so
+ * repeated calls give bitwise identical results. */
+gnmpc_status gnmpc_condense(gnmpc_plan* plan, const void* A, const void* B, const void* c,
+                            const void* x0, const void* Q, int32_t Q_full, const void* q,
+                            const void* R, const void* r, const void* rowC, const void* rowd,
+                            void* H, void* g, void* Ct, void* dt, void* Gx, void* stream);
+
+/* Solve  min 1/2 u'Hu + g'u  s.t.  lb <= u <= ub,  lc <= Ct u <= uc
+ * (the condensed QP of Sec. III-B with native box bounds, Algorithm 1
+ * "Solve QP") by ADMM.  Device arrays of the plan dtype: H [n][n] symmetric
+ * positive definite, g, lb, ub [n], Ct [n_c][n], lc, uc [n_c] (lc or uc may be
+ * NULL for -inf / +inf; infinite entries are allowed); output u [n];
+ * info (device, may be NULL).  n <= N nu and n_c <= n_c_max of the plan.
+ * The factorization runs in the plan dtype unless its condition estimate
+ * exceeds settings->kappa_fp64, in which case factorization and iterations are
+ * redone in FP64 (info->used_fp64 = 1). */
+gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* plan, int32_t n, const void* H, const void* g,
+                                const void* lb, const void* ub, int32_t n_c, const void* Ct,
+                                const void* lc, const void* uc, const gnmpc_admm_settings* settings,
+                                void* u, gnmpc_qp_info* info, void* stream);
+
+/* Default ADMM settings (rho 0.1, sigma 1e-6, alpha 1.6, eps 1e-6, kappa_fp64 1e7,
+ * 4000 iterations, convergence checked every 10). */
+void gnmpc_admm_default_settings(gnmpc_admm_settings* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNMPC_H */

@@ -1,0 +1,361 @@
+// C-ABI entry points of libgnmpc: argument validation, graph preparation on
+// the host, plan workspace and launch sequencing.  Every check runs before any
+// HIP call, so invalid requests never touch the GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+using namespace gnmpc;
+
+namespace {
+
+const char* kVersion = "gnmpc 0.1 (gfx950)";
+
+gnmpc_status fail(gnmpc_plan* p, gnmpc_status s, const std::string& msg) {
+  if (p) p->last_error = msg;
+  return s;
+}
+
+template <typename T>
+void dfree(T*& ptr) {
+  if (ptr) (void)hipFree((void*)ptr);
+  ptr = nullptr;
+}
+
+template <typename T>
+gnmpc_status upload(gnmpc_plan* p, T*& dst, const T* src, size_t count) {
+  dfree(dst);
+  if (count == 0) return GNMPC_OK;
+  GNMPC_HIP_TRY(p, hipMalloc((void**)&dst, sizeof(T) * count));
+  GNMPC_HIP_TRY(p, hipMemcpy(dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
+  return GNMPC_OK;
+}
+
+// Breadth-first closure over incoming edges: nodes that reach i in <= L hops.
+void closure(const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t L, std::vector<int32_t>& prow,
+             std::vector<int32_t>& pcol) {
+  prow.assign(M + 1, 0);
+  pcol.clear();
+  std::vector<int32_t> mark(M, -1), frontier, next, found;
+  for (int32_t i = 0; i < M; ++i) {
+    found.assign(1, i);
+    mark[i] = i;
+    frontier.assign(1, i);
+    for (int32_t h = 0; h < L && !frontier.empty(); ++h) {
+      next.clear();
+      for (int32_t n : frontier)
+        for (int32_t e = row_ptr[n]; e < row_ptr[n + 1]; ++e) {
+          int32_t j = col[e];
+          if (mark[j] != i) {
+            mark[j] = i;
+            next.push_back(j);
+            found.push_back(j);
+          }
+        }
+      frontier.swap(next);
+    }
+    std::sort(found.begin(), found.end());
+    pcol.insert(pcol.end(), found.begin(), found.end());
+    prow[i + 1] = (int32_t)pcol.size();
+  }
+}
+
+bool dims_ok(const gnmpc_dims* d) {
+  return d && d->M > 0 && d->nu > 0 && d->N > 0 && d->n_c_max >= 0 &&
+         (d->dtype == GNMPC_F64 || d->dtype == GNMPC_F32) && (long)d->M * 6 < (1L << 30) &&
+         (long)d->N * d->nu <= 4096;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gnmpc_version(void) { return kVersion; }
+
+const char* gnmpc_status_string(int32_t s) {
+  switch (s) {
+    case GNMPC_OK: return "ok";
+    case GNMPC_INVALID_ARG: return "invalid argument";
+    case GNMPC_BAD_GRAPH: return "malformed graph";
+    case GNMPC_SHAPE: return "shape mismatch";
+    case GNMPC_UNSUPPORTED: return "unsupported";
+    case GNMPC_HIP_ERROR: return "HIP runtime error";
+    case GNMPC_BAD_CONSTRAINT: return "bad constraint row";
+    case GNMPC_NOT_READY: return "plan not ready";
+    case GNMPC_NO_DEVICE: return "no usable GPU";
+    default: return "unknown status";
+  }
+}
+
+void gnmpc_admm_default_settings(gnmpc_admm_settings* s) {
+  if (!s) return;
+  s->rho = 0.1;
+  s->sigma = 1e-6;
+  s->alpha = 1.6;
+  s->eps_abs = 1e-6;
+  s->eps_rel = 1e-6;
+  s->kappa_fp64 = 1e7;
+  s->max_iter = 4000;
+  s->check_every = 10;
+}
+
+gnmpc_status gnmpc_graph_check(const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t E) {
+  if (!row_ptr || M <= 0 || E < 0 || (E > 0 && !col)) return GNMPC_INVALID_ARG;
+  if (row_ptr[0] != 0 || row_ptr[M] != E) return GNMPC_BAD_GRAPH;
+  for (int32_t i = 0; i < M; ++i) {
+    if (row_ptr[i + 1] < row_ptr[i]) return GNMPC_BAD_GRAPH;
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int32_t j = col[e];
+      if (j < 0 || j >= M || j == i) return GNMPC_BAD_GRAPH;
+      if (e > row_ptr[i] && col[e - 1] >= j) return GNMPC_BAD_GRAPH;  // unsorted or duplicate
+    }
+  }
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_graph_closure(const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t E, int32_t L,
+                                 int32_t* row_ptr_out, int32_t* col_out, int64_t cap, int64_t* nnz_out) {
+  gnmpc_status s = gnmpc_graph_check(row_ptr, col, M, E);
+  if (s != GNMPC_OK) return s;
+  if (L < 0 || !nnz_out) return GNMPC_INVALID_ARG;
+  std::vector<int32_t> prow, pcol;
+  closure(row_ptr, col, M, L, prow, pcol);
+  *nnz_out = (int64_t)pcol.size();
+  if (!col_out) return GNMPC_OK;
+  if (!row_ptr_out || cap < (int64_t)pcol.size()) return GNMPC_INVALID_ARG;
+  std::memcpy(row_ptr_out, prow.data(), sizeof(int32_t) * (M + 1));
+  std::memcpy(col_out, pcol.data(), sizeof(int32_t) * pcol.size());
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_plan_create(gnmpc_plan** plan, const gnmpc_dims* dims, int32_t device) {
+  if (!plan) return GNMPC_INVALID_ARG;
+  *plan = nullptr;
+  if (!dims_ok(dims) || device < 0) return GNMPC_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= device) return GNMPC_NO_DEVICE;
+  gnmpc_plan* p = new gnmpc_plan();
+  p->device = device;
+  p->dims = *dims;
+  p->elem = dims->dtype == GNMPC_F64 ? 8 : 4;
+  gnmpc_status st = GNMPC_OK;
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (st != GNMPC_OK) return;
+    if (hipMalloc(ptr, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      p->last_error = "hipMalloc failed";
+      st = GNMPC_HIP_ERROR;
+    }
+  };
+  if (hipSetDevice(device) != hipSuccess) {
+    delete p;
+    return GNMPC_NO_DEVICE;
+  }
+  const int M = dims->M, nu = dims->nu, N = dims->N;
+  p->S_elems = S_offset(N + 1, M, nu);
+  alloc(&p->d_S, p->S_elems * p->elem);
+  alloc(&p->d_Gx, (size_t)(N + 1) * M * NBX * p->elem);
+  p->part_elems = condense_partial_elems(M, nu, N);
+  alloc(&p->d_part, p->part_elems * p->elem);
+  p->qp_bytes = qp_workspace_bytes(N * nu, dims->n_c_max);
+  alloc(&p->d_qp, p->qp_bytes);
+  alloc((void**)&p->d_qp_flag, 64);
+  if (st == GNMPC_OK && hipMemset(p->d_qp_flag, 0, 64) != hipSuccess) st = GNMPC_HIP_ERROR;
+  if (st != GNMPC_OK) {
+    gnmpc_plan_destroy(p);
+    return st;
+  }
+  *plan = p;
+  return GNMPC_OK;
+}
+
+void gnmpc_plan_destroy(gnmpc_plan* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  gnn_free(p);
+  dfree(p->d_row_ptr);
+  dfree(p->d_col);
+  dfree(p->d_prow);
+  dfree(p->d_pcol);
+  dfree(p->d_erow);
+  dfree(p->d_diag);
+  dfree(p->d_act_of_node);
+  dfree(p->d_row_node);
+  dfree(p->d_row_stage);
+  if (p->d_S) (void)hipFree(p->d_S);
+  if (p->d_Gx) (void)hipFree(p->d_Gx);
+  if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_qp) (void)hipFree(p->d_qp);
+  dfree(p->d_qp_flag);
+  delete p;
+}
+
+const char* gnmpc_plan_last_error(const gnmpc_plan* p) { return p ? p->last_error.c_str() : "null plan"; }
+
+gnmpc_status gnmpc_graph_set(gnmpc_plan* p, const int32_t* row_ptr, const int32_t* col, int32_t M, int32_t E,
+                             int32_t L) {
+  if (!p) return GNMPC_INVALID_ARG;
+  gnmpc_status s = gnmpc_graph_check(row_ptr, col, M, E);
+  if (s != GNMPC_OK) return fail(p, s, "graph_set: malformed CSR");
+  if (M != p->dims.M) return fail(p, GNMPC_SHAPE, "graph_set: M differs from the plan");
+  if (L < 1 || L > 8) return fail(p, GNMPC_INVALID_ARG, "graph_set: L must be in 1..8");
+  std::vector<int32_t> prow, pcol;
+  closure(row_ptr, col, M, L, prow, pcol);
+  int wmax = 0;
+  std::vector<int32_t> erow(pcol.size()), diag(M);
+  for (int32_t i = 0; i < M; ++i) {
+    wmax = std::max(wmax, prow[i + 1] - prow[i]);
+    for (int32_t e = prow[i]; e < prow[i + 1]; ++e) {
+      erow[e] = i;
+      if (pcol[e] == i) diag[i] = e;
+    }
+  }
+  if (wmax > kMaxWidth) return fail(p, GNMPC_UNSUPPORTED, "graph_set: Jacobian pattern row wider than 64 blocks");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  p->graph_ready = false;
+  p->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
+  p->h_col.assign(col, col + E);
+  p->h_prow = prow;
+  p->h_pcol = pcol;
+  p->M = M;
+  p->E = E;
+  p->L = L;
+  p->nnz = (long)pcol.size();
+  p->wmax = wmax;
+  if ((s = upload(p, p->d_row_ptr, row_ptr, M + 1)) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_col, col, (size_t)E)) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_prow, prow.data(), prow.size())) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_pcol, pcol.data(), pcol.size())) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_erow, erow.data(), erow.size())) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_diag, diag.data(), diag.size())) != GNMPC_OK) return s;
+  p->graph_ready = true;
+  p->model = 0;  // a model must be (re)bound to the new graph
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_graph_nnz(const gnmpc_plan* p, int64_t* nnz) {
+  if (!p || !nnz) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return GNMPC_NOT_READY;
+  *nnz = p->nnz;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_graph_pattern(const gnmpc_plan* p, int32_t* row_ptr_out, int32_t* col_out) {
+  if (!p || !row_ptr_out || !col_out) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return GNMPC_NOT_READY;
+  std::memcpy(row_ptr_out, p->h_prow.data(), sizeof(int32_t) * p->h_prow.size());
+  std::memcpy(col_out, p->h_pcol.data(), sizeof(int32_t) * p->h_pcol.size());
+  return GNMPC_OK;
+}
+
+static gnmpc_status set_actuators(gnmpc_plan* p, const int32_t* act, int32_t n_act) {
+  if (n_act < 0 || (n_act > 0 && !act)) return fail(p, GNMPC_INVALID_ARG, "actuators: bad list");
+  if (3 * n_act != p->dims.nu) return fail(p, GNMPC_SHAPE, "actuators: nu must equal 3 * n_act");
+  std::vector<int32_t> of(p->M, -1);
+  for (int32_t a = 0; a < n_act; ++a) {
+    if (act[a] < 0 || act[a] >= p->M) return fail(p, GNMPC_INVALID_ARG, "actuators: node out of range");
+    if (of[act[a]] >= 0) return fail(p, GNMPC_INVALID_ARG, "actuators: duplicate node");
+    of[act[a]] = a;
+  }
+  p->h_act.assign(act, act + n_act);
+  p->n_act = n_act;
+  return upload(p, p->d_act_of_node, of.data(), of.size());
+}
+
+gnmpc_status gnmpc_model_set_msd(gnmpc_plan* p, const gnmpc_msd_params* prm, const int32_t* act, int32_t n_act) {
+  if (!p || !prm) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "model_set_msd: set the graph first");
+  if (!(prm->m > 0) || !(prm->dt > 0) || !std::isfinite(prm->k) || !std::isfinite(prm->c) ||
+      !std::isfinite(prm->k3) || !std::isfinite(prm->gravity) || prm->anchor < -1 || prm->anchor >= p->M)
+    return fail(p, GNMPC_INVALID_ARG, "model_set_msd: bad parameters");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  gnmpc_status s = set_actuators(p, act, n_act);
+  if (s != GNMPC_OK) return s;
+  p->msd = *prm;
+  p->model = 1;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_model_set_gnn(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* weights, int64_t n_weights,
+                                 const int32_t* act, int32_t n_act) {
+  if (!p || !desc || !weights) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "model_set_gnn: set the graph first");
+  if (desc->L != p->L) return fail(p, GNMPC_SHAPE, "model_set_gnn: L differs from the graph's L");
+  if (desc->Hd <= 0 || desc->Hd % 32 != 0 || desc->Hd > 256 || !(desc->dt > 0) ||
+      (desc->dtype != GNMPC_F32 && desc->dtype != GNMPC_BF16))
+    return fail(p, GNMPC_INVALID_ARG, "model_set_gnn: Hd must be a multiple of 32 up to 256, dtype F32 or BF16");
+  const long Hd = desc->Hd;
+  const long expect = Hd * 9 + Hd + desc->L * (2 * (Hd * 2 * Hd + Hd)) + 6 * Hd + 6;
+  if (n_weights != expect) return fail(p, GNMPC_SHAPE, "model_set_gnn: wrong number of weights");
+  for (int64_t t = 0; t < n_weights; ++t)
+    if (!std::isfinite(weights[t])) return fail(p, GNMPC_INVALID_ARG, "model_set_gnn: non-finite weight");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  gnmpc_status s = set_actuators(p, act, n_act);
+  if (s != GNMPC_OK) return s;
+  s = gnn_set(p, desc, weights, n_weights);
+  if (s != GNMPC_OK) return s;
+  p->model = 2;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_rows_set(gnmpc_plan* p, int32_t n_c, const int32_t* node, const int32_t* stage) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (n_c < 0 || (n_c > 0 && (!node || !stage))) return fail(p, GNMPC_INVALID_ARG, "rows_set: bad arrays");
+  if (n_c > p->dims.n_c_max) return fail(p, GNMPC_SHAPE, "rows_set: n_c exceeds n_c_max");
+  for (int32_t t = 0; t < n_c; ++t) {
+    if (node[t] < 0 || node[t] >= p->dims.M) return fail(p, GNMPC_BAD_CONSTRAINT, "rows_set: node out of range");
+    if (stage[t] < 1 || stage[t] > p->dims.N)
+      return fail(p, GNMPC_BAD_CONSTRAINT, "rows_set: stage must be in 1..N (stage-0 rows do not depend on u)");
+  }
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  gnmpc_status s;
+  if ((s = upload(p, p->d_row_node, node, (size_t)n_c)) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_row_stage, stage, (size_t)n_c)) != GNMPC_OK) return s;
+  p->n_c = n_c;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
+                             void* fnext, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!xhat || !uhat || !A || !B || !c) return fail(p, GNMPC_INVALID_ARG, "linearize: null array");
+  if (!p->graph_ready || p->model == 0) return fail(p, GNMPC_NOT_READY, "linearize: graph and model must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (p->model == 1) return launch_msd_linearize(p, xhat, uhat, A, B, c, fnext, s);
+  return launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
+}
+
+gnmpc_status gnmpc_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                            const void* Q, int32_t Q_full, const void* q, const void* R, const void* r,
+                            const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt, void* Gx,
+                            void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!A || !B || !c || !x0 || !Q || !q || !R || !r || !H || !g)
+    return fail(p, GNMPC_INVALID_ARG, "condense: null array");
+  if (Q_full != 0 && Q_full != 1) return fail(p, GNMPC_INVALID_ARG, "condense: Q_full must be 0 or 1");
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "condense: graph must be set");
+  if (p->n_c > 0 && (!rowC || !rowd || !Ct || !dt)) return fail(p, GNMPC_INVALID_ARG, "condense: null row array");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_condense(p, A, B, c, x0, Q, Q_full, q, R, r, rowC, rowd, H, g, Ct, dt, Gx, (hipStream_t)stream);
+}
+
+gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const void* g, const void* lb,
+                                const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc,
+                                const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!H || !g || !lb || !ub || !u || !st) return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: null array");
+  if (n <= 0 || n > p->dims.N * p->dims.nu) return fail(p, GNMPC_SHAPE, "solve_box_qp: n outside 1..N*nu");
+  if (n_c < 0 || n_c > p->dims.n_c_max) return fail(p, GNMPC_SHAPE, "solve_box_qp: n_c outside 0..n_c_max");
+  if (n_c > 0 && !Ct) return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: Ct is null");
+  if (!(st->rho > 0) || !(st->sigma > 0) || !(st->alpha > 0 && st->alpha < 2) || !(st->eps_abs >= 0) ||
+      !(st->eps_rel >= 0) || st->max_iter < 1 || st->check_every < 1 || !(st->kappa_fp64 > 0))
+    return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: bad settings");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal definition of gnmpc_plan and the launchers of each kernel file.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+struct GnnState;  // defined in gnn.hip
+
+struct gnmpc_plan {
+  int device = 0;
+  gnmpc_dims dims{};
+  std::string last_error;
+  int elem = 4;  // bytes per element of the plan dtype
+
+  // graph and Jacobian pattern
+  bool graph_ready = false;
+  int M = 0, E = 0, L = 0;
+  long nnz = 0;
+  int wmax = 0;  // longest pattern row
+  std::vector<int32_t> h_row_ptr, h_col, h_prow, h_pcol;
+  int32_t *d_row_ptr = nullptr, *d_col = nullptr;
+  int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_erow = nullptr, *d_diag = nullptr;
+
+  // model
+  int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN
+  gnmpc_msd_params msd{};
+  int n_act = 0;
+  std::vector<int32_t> h_act;
+  int32_t* d_act_of_node = nullptr;  // [M]: actuator index of the node or -1
+  GnnState* gnn = nullptr;
+
+  // single-node state rows
+  int n_c = 0;
+  int32_t *d_row_node = nullptr, *d_row_stage = nullptr;
+
+  // condensing workspace
+  void* d_S = nullptr;     // S_k for k = 1..N, stage k stored as [M][6][k nu]
+  size_t S_elems = 0;
+  void* d_Gx = nullptr;    // [N+1][M][6]
+  void* d_part = nullptr;  // split-K partial sums of the Gram kernel
+  size_t part_elems = 0;
+
+  // QP workspace
+  void* d_qp = nullptr;
+  size_t qp_bytes = 0;
+  int32_t* d_qp_flag = nullptr;
+};
+
+namespace gnmpc {
+
+__host__ __device__ inline size_t S_offset(int k, int M, int nu) {  // element offset of S_k (k >= 1)
+  return (size_t)NBX * M * nu * ((size_t)k * (k - 1) / 2);
+}
+
+// msd_linearize.hip
+gnmpc_status launch_msd_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B,
+                                  void* c, void* fnext, hipStream_t s);
+// condense.hip
+size_t condense_partial_elems(int M, int nu, int N);
+gnmpc_status launch_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                             const void* Q, int Q_full, const void* q, const void* R, const void* r,
+                             const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt,
+                             void* Gx, hipStream_t s);
+// qp_admm.hip
+size_t qp_workspace_bytes(int n, int n_c);
+gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
+                       int n_c, const void* Ct, const void* lc, const void* uc,
+                       const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
+// gnn.hip
+gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w);
+void gnn_free(gnmpc_plan* p);
+gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B,
+                                  void* c, void* fnext, hipStream_t s);
+
+}  // namespace gnmpc

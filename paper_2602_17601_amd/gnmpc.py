@@ -1,0 +1,269 @@
+"""Thin ctypes binding over the C-ABI of libgnmpc.so (include/gnmpc.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Device arrays are torch tensors on the plan's GPU (torch provides the
+memory and the stream); host arrays are numpy arrays.  There is no fallback:
+if the library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads torch's HIP runtime first, so the library binds to the same one
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgnmpc.so")
+
+OK, INVALID_ARG, BAD_GRAPH, SHAPE, UNSUPPORTED, HIP_ERROR, BAD_CONSTRAINT, NOT_READY, NO_DEVICE = range(9)
+F64, F32, BF16 = 0, 1, 2
+QP_SOLVED, QP_MAXITER, QP_PRIMAL_INFEASIBLE, QP_NONFINITE, QP_NOT_PD = range(5)
+
+
+class GnmpcError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"gnmpc status {status} ({status_string(status)}): {msg}")
+
+
+class Dims(C.Structure):
+    _fields_ = [("M", C.c_int32), ("nu", C.c_int32), ("N", C.c_int32), ("n_c_max", C.c_int32),
+                ("dtype", C.c_int32)]
+
+
+class MsdParams(C.Structure):
+    _fields_ = [("k", C.c_double), ("c", C.c_double), ("m", C.c_double), ("dt", C.c_double),
+                ("k3", C.c_double), ("gravity", C.c_double), ("anchor", C.c_int32), ("reserved", C.c_int32)]
+
+
+class GnnDesc(C.Structure):
+    _fields_ = [("Hd", C.c_int32), ("L", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32),
+                ("dt", C.c_double)]
+
+
+class AdmmSettings(C.Structure):
+    _fields_ = [("rho", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("eps_abs", C.c_double),
+                ("eps_rel", C.c_double), ("kappa_fp64", C.c_double), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class QpInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("used_fp64", C.c_int32), ("reserved", C.c_int32),
+                ("prim_res", C.c_double), ("dual_res", C.c_double), ("kappa_est", C.c_double), ("obj", C.c_double)]
+
+
+QP_INFO_BYTES = C.sizeof(QpInfo)
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} not found: build it with `python -m paper_2602_17601_amd.build_lib`")
+        L = C.CDLL(_LIB_PATH)
+        i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+        P = C.POINTER
+        sig = {
+            "gnmpc_version": ([], C.c_char_p),
+            "gnmpc_status_string": ([i32], C.c_char_p),
+            "gnmpc_graph_check": ([vp, vp, i32, i32], i32),
+            "gnmpc_graph_closure": ([vp, vp, i32, i32, i32, vp, vp, i64, P(i64)], i32),
+            "gnmpc_plan_create": ([P(vp), P(Dims), i32], i32),
+            "gnmpc_plan_destroy": ([vp], None),
+            "gnmpc_plan_last_error": ([vp], C.c_char_p),
+            "gnmpc_graph_set": ([vp, vp, vp, i32, i32, i32], i32),
+            "gnmpc_graph_nnz": ([vp, P(i64)], i32),
+            "gnmpc_graph_pattern": ([vp, vp, vp], i32),
+            "gnmpc_model_set_msd": ([vp, P(MsdParams), vp, i32], i32),
+            "gnmpc_model_set_gnn": ([vp, P(GnnDesc), vp, i64, vp, i32], i32),
+            "gnmpc_rows_set": ([vp, i32, vp, vp], i32),
+            "gnmpc_linearize": ([vp] + [vp] * 7, i32),
+            "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
+            "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
+            "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    try:
+        return lib().gnmpc_status_string(int(s)).decode()
+    except ImportError:
+        return "?"
+
+
+def version():
+    return lib().gnmpc_version().decode()
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _hp(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None and a.size else None
+
+
+def graph_check(row_ptr, col):
+    rp, cl = _i32(row_ptr), _i32(col)
+    return lib().gnmpc_graph_check(_hp(rp), _hp(cl), len(rp) - 1, len(cl))
+
+
+def graph_closure(row_ptr, col, L):
+    """Jacobian block pattern (row_ptr, col) of the L-round closure (host)."""
+    rp, cl = _i32(row_ptr), _i32(col)
+    M = len(rp) - 1
+    nnz = C.c_int64(0)
+    s = lib().gnmpc_graph_closure(_hp(rp), _hp(cl), M, len(cl), L, None, None, 0, C.byref(nnz))
+    if s != OK:
+        raise GnmpcError(s, "graph_closure")
+    prow = np.zeros(M + 1, np.int32)
+    pcol = np.zeros(nnz.value, np.int32)
+    s = lib().gnmpc_graph_closure(_hp(rp), _hp(cl), M, len(cl), L, _hp(prow), _hp(pcol), nnz.value, C.byref(nnz))
+    if s != OK:
+        raise GnmpcError(s, "graph_closure")
+    return prow, pcol
+
+
+def default_admm_settings(**kw):
+    s = AdmmSettings()
+    lib().gnmpc_admm_default_settings(C.byref(s))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A gnmpc plan: dimensions, graph, model, state rows and all workspace."""
+
+    def __init__(self, M, nu, N, n_c_max=0, dtype=F32, device=0):
+        self.M, self.nu, self.N, self.n_c_max, self.dtype = M, nu, N, n_c_max, dtype
+        self.device = device
+        self.tdtype = torch.float64 if dtype == F64 else torch.float32
+        d = Dims(M, nu, N, n_c_max, dtype)
+        h = C.c_void_p()
+        s = lib().gnmpc_plan_create(C.byref(h), C.byref(d), device)
+        if s != OK:
+            raise GnmpcError(s, "plan_create")
+        self._h = h
+        self.nnz = None
+        self.n_c = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gnmpc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s, what):
+        if s != OK:
+            msg = lib().gnmpc_plan_last_error(self._h).decode()
+            raise GnmpcError(s, f"{what}: {msg}")
+
+    def _dev(self, t, shape, name, dtype=None, allow_none=False):
+        if t is None:
+            if allow_none:
+                return None
+            raise GnmpcError(INVALID_ARG, f"{name} is required")
+        dtype = dtype or self.tdtype
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device.index == self.device):
+            raise GnmpcError(INVALID_ARG, f"{name} must be a tensor on cuda:{self.device}")
+        if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise GnmpcError(SHAPE, f"{name}: expected contiguous {dtype} {tuple(shape)}, got {t.dtype} "
+                                    f"{tuple(t.shape)} contiguous={t.is_contiguous()}")
+        return C.c_void_p(t.data_ptr())
+
+    # ---- setup
+    def graph_set(self, row_ptr, col, L):
+        rp, cl = _i32(row_ptr), _i32(col)
+        self._check(lib().gnmpc_graph_set(self._h, _hp(rp), _hp(cl), len(rp) - 1, len(cl), L), "graph_set")
+        n = C.c_int64(0)
+        self._check(lib().gnmpc_graph_nnz(self._h, C.byref(n)), "graph_nnz")
+        self.nnz = n.value
+        self.L = L
+
+    def graph_pattern(self):
+        prow = np.zeros(self.M + 1, np.int32)
+        pcol = np.zeros(self.nnz, np.int32)
+        self._check(lib().gnmpc_graph_pattern(self._h, _hp(prow), _hp(pcol)), "graph_pattern")
+        return prow, pcol
+
+    def model_set_msd(self, prm, act):
+        p = MsdParams(prm.k, prm.c, prm.m, prm.dt, prm.k3, prm.gravity, prm.anchor, 0)
+        a = _i32(act)
+        self._check(lib().gnmpc_model_set_msd(self._h, C.byref(p), _hp(a), len(a)), "model_set_msd")
+
+    def model_set_gnn(self, W, act, dtype=F32):
+        flat = [W.W_enc, W.b_enc]
+        for l in range(W.L):
+            flat += [W.W_edge[l], W.b_edge[l], W.W_node[l], W.b_node[l]]
+        flat += [W.W_dec, W.b_dec]
+        w = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).reshape(-1) for x in flat]))
+        d = GnnDesc(W.Hd, W.L, dtype, 0, W.dt)
+        a = _i32(act)
+        self._check(lib().gnmpc_model_set_gnn(self._h, C.byref(d), _hp(w), w.size, _hp(a), len(a)),
+                    "model_set_gnn")
+
+    def rows_set(self, node, stage):
+        n, st = _i32(node), _i32(stage)
+        self._check(lib().gnmpc_rows_set(self._h, len(n), _hp(n), _hp(st)), "rows_set")
+        self.n_c = len(n)
+
+    # ---- hot path
+    def linearize(self, xhat, uhat, A, B, c, fnext=None, stream=None):
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(xhat, (N + 1, M, 6), "xhat"), self._dev(uhat, (N, nu), "uhat"),
+                self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True)]
+        self._check(lib().gnmpc_linearize(self._h, *args, _stream(stream)), "linearize")
+
+    def condense(self, A, B, c, x0, Q, q, R, r, rowC, rowd, H, g, Ct, dt, Gx=None, stream=None):
+        M, N, nu, nc = self.M, self.N, self.nu, self.n_c
+        full = 1 if Q.dim() == 4 else 0
+        qshape = (N + 1, M, 6, 6) if full else (N + 1, M, 6)
+        n = N * nu
+        args = [self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(c, (N, M, 6), "c"), self._dev(x0, (M, 6), "x0"), self._dev(Q, qshape, "Q"), full,
+                self._dev(q, (N + 1, M, 6), "q"), self._dev(R, (N, nu, nu), "R"), self._dev(r, (N, nu), "r"),
+                self._dev(rowC, (nc, 6), "rowC", allow_none=nc == 0),
+                self._dev(rowd, (nc,), "rowd", allow_none=nc == 0),
+                self._dev(H, (n, n), "H"), self._dev(g, (n,), "g"),
+                self._dev(Ct, (nc, n), "Ct", allow_none=nc == 0), self._dev(dt, (nc,), "dt", allow_none=nc == 0),
+                self._dev(Gx, (N + 1, M, 6), "Gx", allow_none=True)]
+        self._check(lib().gnmpc_condense(self._h, *args, _stream(stream)), "condense")
+
+    def solve_box_qp(self, H, g, lb, ub, Ct, lc, uc, u, info=None, settings=None, stream=None):
+        n = g.shape[0]
+        nc = 0 if Ct is None else Ct.shape[0]
+        st = settings or default_admm_settings()
+        args = [self._dev(H, (n, n), "H"), self._dev(g, (n,), "g"), self._dev(lb, (n,), "lb"),
+                self._dev(ub, (n,), "ub"), nc, self._dev(Ct, (nc, n), "Ct", allow_none=nc == 0),
+                self._dev(lc, (nc,), "lc", allow_none=True), self._dev(uc, (nc,), "uc", allow_none=True),
+                C.byref(st), self._dev(u, (n,), "u"),
+                self._dev(info, (QP_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)]
+        self._check(lib().gnmpc_solve_box_qp(self._h, n, *args, _stream(stream)), "solve_box_qp")
+
+
+def qp_info(t):
+    """Decode a device info buffer (uint8 tensor of QP_INFO_BYTES) after a sync."""
+    b = bytes(t.cpu().numpy().tobytes())
+    return QpInfo.from_buffer_copy(b)
