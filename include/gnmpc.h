@@ -96,7 +96,7 @@ typedef struct {
  * W_enc[Hd][9], b_enc[Hd], then per layer W_e[Hd][2Hd], b_e[Hd], W_n[Hd][2Hd],
  * b_n[Hd], then W_dec[6][Hd], b_dec[6]. */
 typedef struct {
-  int32_t Hd;       /* hidden width (multiple of 32, <= 256)                     */
+  int32_t Hd;       /* hidden width: 64, 128, 192 or 256                          */
   int32_t L;        /* message-passing rounds (must equal the graph's L)          */
   int32_t dtype;    /* GNMPC_F32 or GNMPC_BF16 (BF16 operands, FP32 accumulate)   */
   int32_t reserved;

@@ -17,12 +17,32 @@ derivative mask is z > 0).  The offset is c = f(xhat,uhat) - sum_j A^{ij} xhat^j
 
 ``activation='identity'`` replaces every ReLU by the identity; it exists only
 so the tests can compare against a closed-form affine model.
+
+``rounding='bf16'`` is for comparisons with a kernel that runs the MLPs on
+bfloat16 operands.  A ReLU mask is a bit decided by floating point, so the
+oracle then takes that decision in the kernel's precision: the *values* of the
+forward pass use operands rounded to bfloat16 at the points where the kernel
+rounds them (the node input [x; Pu], every hidden state h and every message
+sum), while all arithmetic stays FP64 and the *tangents* stay exact.  Given the
+masks, the Jacobian is then the exact derivative.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .graph import ball, in_neighbours, jacobian_pattern
+
+
+def _round(v, rounding):
+    """Round a value operand to the given storage precision (None = exact FP64)."""
+    if rounding is None:
+        return v
+    if rounding == "bf16":
+        f = np.ascontiguousarray(np.asarray(v, dtype=np.float32))
+        u = f.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    raise ValueError(rounding)
 
 
 def _act(z, activation):
@@ -42,11 +62,12 @@ def node_input(x, u, i, act):
     return np.concatenate([x[i], f])
 
 
-def gnn_forward(x, u, W, row_ptr, col, act, activation="relu"):
+def gnn_forward(x, u, W, row_ptr, col, act, activation="relu", rounding=None):
     """One step x -> x+ for every node; x is [M][6], returns [M][6]."""
     M = x.shape[0]
-    inp = np.stack([node_input(x, u, i, act) for i in range(M)])
+    inp = _round(np.stack([node_input(x, u, i, act) for i in range(M)]), rounding)
     h, _ = _act(inp @ W.W_enc.T + W.b_enc, activation)
+    h = _round(h, rounding)
     for l in range(W.L):
         agg = np.zeros_like(h)
         for i in range(M):
@@ -54,14 +75,16 @@ def gnn_forward(x, u, W, row_ptr, col, act, activation="relu"):
                 e = np.concatenate([h[i], h[i] - h[j]])
                 m, _ = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
                 agg[i] += m
+        agg = _round(agg, rounding)
         h, _ = _act(np.concatenate([h, agg], axis=1) @ W.W_node[l].T + W.b_node[l], activation)
+        h = _round(h, rounding)
     o = h @ W.W_dec.T + W.b_dec
     vn = x[:, 3:] + W.dt * o[:, 3:6]
     pn = x[:, :3] + W.dt * vn
     return np.concatenate([pn, vn], axis=1)
 
 
-def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
+def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", rounding=None):
     """Forward-mode derivative of f^i on node i's receptive subgraph.
 
     Returns (f_i [6], S (sorted receptive nodes), J [6][6|S| + nu]) where the
@@ -83,7 +106,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
     # encoder on every node of the receptive set
     h, dh = {}, {}
     for j in S:
-        inp = node_input(x, u, j, act)
+        inp = _round(node_input(x, u, j, act), rounding)
         dinp = np.vstack([seed_x(j), np.zeros((3, T))])
         hit = np.nonzero(np.asarray(act) == j)[0]
         if hit.size:
@@ -91,7 +114,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
             dinp[6:9] = du[3 * a:3 * a + 3]
         z = W.W_enc @ inp + W.b_enc
         hv, mask = _act(z, activation)
-        h[j], dh[j] = hv, mask[:, None] * (W.W_enc @ dinp)
+        h[j], dh[j] = _round(hv, rounding), mask[:, None] * (W.W_enc @ dinp)
     # message-passing rounds: after round l only nodes within L-1-l hops are needed
     for l in range(L):
         keep = ball(row_ptr, col, i, L - 1 - l)
@@ -105,9 +128,10 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
                 m, mask = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
                 agg += m
                 dagg += mask[:, None] * (W.W_edge[l] @ de)
+            agg = _round(agg, rounding)
             z = W.W_node[l] @ np.concatenate([h[n], agg]) + W.b_node[l]
             hv, mask = _act(z, activation)
-            nh[n] = hv
+            nh[n] = _round(hv, rounding)
             ndh[n] = mask[:, None] * (W.W_node[l] @ np.vstack([dh[n], dagg]))
         h, dh = nh, ndh
     o = W.W_dec @ h[i] + W.b_dec
@@ -121,7 +145,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
 
 
 def gnn_linearize(xhat, uhat, W, row_ptr, col, act, stages=None, nodes=None,
-                  activation="relu"):
+                  activation="relu", rounding=None):
     """A^{ij}_k (L-hop pattern, ascending), B^i_k, c^i_k and f^i_k.
 
     Only the requested (stage, node) pairs are computed (all by default); the
@@ -137,7 +161,7 @@ def gnn_linearize(xhat, uhat, W, row_ptr, col, act, stages=None, nodes=None,
     f = np.full((N, M, 6), np.nan)
     for k in (range(N) if stages is None else stages):
         for i in (range(M) if nodes is None else nodes):
-            fi, S, J = gnn_linearize_node(xhat[k], uhat[k], W, row_ptr, col, act, i, activation)
+            fi, S, J = gnn_linearize_node(xhat[k], uhat[k], W, row_ptr, col, act, i, activation, rounding)
             assert list(pcol[prow[i]:prow[i + 1]]) == S
             lin = J[:, 6 * len(S):] @ uhat[k]
             for p, j in enumerate(S):

@@ -284,9 +284,9 @@ gnmpc_status gnmpc_model_set_gnn(gnmpc_plan* p, const gnmpc_gnn_desc* desc, cons
   if (!p || !desc || !weights) return GNMPC_INVALID_ARG;
   if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "model_set_gnn: set the graph first");
   if (desc->L != p->L) return fail(p, GNMPC_SHAPE, "model_set_gnn: L differs from the graph's L");
-  if (desc->Hd <= 0 || desc->Hd % 32 != 0 || desc->Hd > 256 || !(desc->dt > 0) ||
+  if (desc->Hd <= 0 || desc->Hd % 64 != 0 || desc->Hd > 256 || !(desc->dt > 0) ||
       (desc->dtype != GNMPC_F32 && desc->dtype != GNMPC_BF16))
-    return fail(p, GNMPC_INVALID_ARG, "model_set_gnn: Hd must be a multiple of 32 up to 256, dtype F32 or BF16");
+    return fail(p, GNMPC_INVALID_ARG, "model_set_gnn: Hd must be a multiple of 64 up to 256, dtype F32 or BF16");
   const long Hd = desc->Hd;
   const long expect = Hd * 9 + Hd + desc->L * (2 * (Hd * 2 * Hd + Hd)) + 6 * Hd + 6;
   if (n_weights != expect) return fail(p, GNMPC_SHAPE, "model_set_gnn: wrong number of weights");

@@ -1,16 +1,704 @@
-// GNN forward and Jacobian kernels (placeholder until the GNN path lands).
+// GNN dynamics model (Sec. V-A eq. forward_dynamics) and its linearization by
+// forward-mode differentiation (Sec. V-A "Linearization", eq.
+// linearized_dynamics), on the GPU.
+//
+// Forward pass at the N linearization points: one launch for the encoder, one
+// per message-passing round and one for the decoder, each over every
+// (stage, node).  The edge MLP is evaluated per node in factored form,
+// W_e [h_i; h_i - h_j] = W_a h_i + W_b h_i - W_b h_j, and the ReLU masks of
+// the encoder, every edge and every node update are kept as bit masks: they
+// are all the Jacobian pass needs from the forward pass.
+//
+// Jacobian pass (seed-centric forward mode): the tangent columns of one or two
+// consecutive "seed" nodes (6 state columns each, plus 3 force columns for an
+// actuated node; at most 16 columns) are pushed through all L rounds inside
+// one workgroup.  After round l they are nonzero only on the nodes within l
+// hops of the seeds, so the workgroup carries exactly those nodes (lists built
+// on the host), and after the decoder it owns the blocks A^{is} and B^i of
+// every node i reached by its seeds.  No tangent ever leaves the chip.
+// In BF16 mode every GEMM operand (weights, activations, tangents) is rounded
+// to bfloat16 (round to nearest even) and products are accumulated in FP32.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "plan.hpp"
 
-namespace gnmpc {
+struct GnnState {
+  int Hd = 0, L = 0, dtype = GNMPC_F32, N = 0, M = 0, E = 0;
+  float dt = 0.f;
+  // weights as FP32 values (bf16-representable in BF16 mode), transposed so
+  // that lane f of a workgroup reads consecutive addresses
+  float *encT = nullptr;           // [9][Hd]
+  float *benc = nullptr;           // [Hd]
+  float *WaT = nullptr, *WbT = nullptr, *be = nullptr;      // [L][Hd(in)][Hd(out)], [L][Hd]
+  float *Wn1T = nullptr, *Wn2T = nullptr, *bn = nullptr;    // [L][Hd][Hd], [L][Hd]
+  float *decT = nullptr, *bdec = nullptr;                   // [Hd][6], [6]
+  // forward-pass workspace
+  float* h = nullptr;              // [L+1][N][M][Hd]
+  uint32_t *mask_enc = nullptr;    // [N][M][Hd/32]
+  uint32_t *mask_node = nullptr;   // [L][N][M][Hd/32]
+  uint32_t *mask_edge = nullptr;   // [L][N][E][Hd/32]
+  float* fnext = nullptr;          // [N][M][6]
+  int maxdeg = 0;
+  // seed tiles
+  int n_tiles = 0, meta_stride = 0, bufX = 0, bufY = 0;
+  size_t jvp_lds = 0;
+  int32_t *meta = nullptr, *seed = nullptr, *seedcol = nullptr, *seedact = nullptr;
+  int32_t *V = nullptr, *Vself = nullptr, *Vebeg = nullptr, *Vecnt = nullptr;
+  int32_t *Eloc = nullptr, *Eid = nullptr, *out3 = nullptr, *bout2 = nullptr;
+  std::vector<void*> allocs;
+};
 
-gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc*, const double*, int64_t) {
-  p->last_error = "GNN model not built into this library";
-  return GNMPC_UNSUPPORTED;
+namespace gnmpc {
+namespace {
+
+constexpr int kCols = 16;  // tangent columns per seed tile
+
+__device__ inline float bf16r(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
 }
-void gnn_free(gnmpc_plan*) {}
-gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void*, const void*, void*, void*, void*, void*, hipStream_t) {
-  p->last_error = "GNN model not built into this library";
-  return GNMPC_UNSUPPORTED;
+
+float host_bf16r(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+__device__ inline bool mbit(const uint32_t* m, int f) { return (m[f >> 5] >> (f & 31)) & 1u; }
+
+// Store the ReLU mask of the 64 features handled by this wave (z > 0).
+__device__ inline void store_mask(uint32_t* words, int f, bool on) {
+  unsigned long long b = __ballot(on);
+  if ((threadIdx.x & 63) == 0) {
+    words[f >> 5] = (uint32_t)(b & 0xFFFFFFFFull);
+    words[(f >> 5) + 1] = (uint32_t)(b >> 32);
+  }
+}
+
+struct FwdArgs {
+  int N, M, E, Hd, L, nu, bf16;
+  float dt;
+  const float *xhat, *uhat;
+  const int32_t *row_ptr, *col, *act_of_node;
+  const float *encT, *benc, *WaT, *WbT, *be, *Wn1T, *Wn2T, *bn, *decT, *bdec;
+  float* h;
+  uint32_t *mask_enc, *mask_node, *mask_edge;
+  float* fnext;
+};
+
+// h0 = relu(W_enc [x; P u] + b); one workgroup of Hd lanes per (stage, node).
+__global__ void fwd_enc_kernel(FwdArgs a) {
+  const int s = blockIdx.x;  // stage * M + node
+  const int k = s / a.M, i = s - k * a.M;
+  const int f = threadIdx.x;
+  float in[9];
+  const float* x = a.xhat + (size_t)s * NBX;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) in[d] = x[d];
+  int act = a.act_of_node[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) in[6 + d] = act >= 0 ? a.uhat[(size_t)k * a.nu + 3 * act + d] : 0.f;
+  float z = a.benc[f];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) z += a.encT[d * a.Hd + f] * (a.bf16 ? bf16r(in[d]) : in[d]);
+  bool on = z > 0.f;
+  float hv = on ? z : 0.f;
+  a.h[(size_t)s * a.Hd + f] = a.bf16 ? bf16r(hv) : hv;
+  store_mask(a.mask_enc + (size_t)s * (a.Hd / 32), f, on);
+}
+
+// One message-passing round l; workgroup of Hd lanes per (stage, node).
+__global__ void fwd_layer_kernel(FwdArgs a, int l) {
+  extern __shared__ float sh[];  // [1 + maxdeg][Hd] inputs, then [Hd] aggregate
+  const int s = blockIdx.x;
+  const int k = s / a.M, i = s - k * a.M;
+  const int f = threadIdx.x, Hd = a.Hd;
+  const float* hin = a.h + (size_t)l * a.N * a.M * Hd;
+  const int e0 = a.row_ptr[i], deg = a.row_ptr[i + 1] - e0;
+  sh[f] = hin[(size_t)s * Hd + f];
+  for (int t = 0; t < deg; ++t) sh[(1 + t) * Hd + f] = hin[((size_t)k * a.M + a.col[e0 + t]) * Hd + f];
+  __syncthreads();
+  const float* WaT = a.WaT + (size_t)l * Hd * Hd;
+  const float* WbT = a.WbT + (size_t)l * Hd * Hd;
+  float ya = 0.f, ybi = 0.f;
+  for (int q = 0; q < Hd; ++q) {
+    ya += WaT[q * Hd + f] * sh[q];
+    ybi += WbT[q * Hd + f] * sh[q];
+  }
+  const float base = ya + ybi + a.be[l * Hd + f];
+  float agg = 0.f;
+  uint32_t* me = a.mask_edge + (((size_t)l * a.N + k) * a.E) * (Hd / 32);
+  for (int t = 0; t < deg; ++t) {
+    const float* hj = sh + (1 + t) * Hd;
+    float ybj = 0.f;
+    for (int q = 0; q < Hd; ++q) ybj += WbT[q * Hd + f] * hj[q];
+    float z = base - ybj;
+    bool on = z > 0.f;
+    agg += on ? z : 0.f;
+    store_mask(me + (size_t)(e0 + t) * (Hd / 32), f, on);
+  }
+  float* sagg = sh + (size_t)(1 + deg) * Hd;  // after the inputs
+  sagg[f] = a.bf16 ? bf16r(agg) : agg;
+  __syncthreads();
+  const float* W1 = a.Wn1T + (size_t)l * Hd * Hd;
+  const float* W2 = a.Wn2T + (size_t)l * Hd * Hd;
+  float z = a.bn[l * Hd + f];
+  for (int q = 0; q < Hd; ++q) z += W1[q * Hd + f] * sh[q] + W2[q * Hd + f] * sagg[q];
+  bool on = z > 0.f;
+  float hv = on ? z : 0.f;
+  a.h[((size_t)(l + 1) * a.N * a.M + s) * Hd + f] = a.bf16 ? bf16r(hv) : hv;
+  store_mask(a.mask_node + ((size_t)l * a.N * a.M + s) * (Hd / 32), f, on);
+}
+
+// o = W_dec h + b; v+ = v + dt o[3:6], p+ = p + dt v+ ; one lane per (stage, node).
+__global__ void fwd_dec_kernel(FwdArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.N * a.M) return;
+  const float* hL = a.h + ((size_t)a.L * a.N * a.M + s) * a.Hd;
+  float o[3] = {a.bdec[3], a.bdec[4], a.bdec[5]};
+  for (int q = 0; q < a.Hd; ++q) {
+    float hv = hL[q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) o[r] += a.decT[q * 6 + 3 + r] * hv;
+  }
+  const float* x = a.xhat + (size_t)s * NBX;
+  float* fo = a.fnext + (size_t)s * NBX;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    float vn = x[3 + r] + a.dt * o[r];
+    fo[3 + r] = vn;
+    fo[r] = x[r] + a.dt * vn;
+  }
+}
+
+struct JvpArgs {
+  int N, M, E, Hd, L, nu, bf16, meta_stride, bufX;
+  float dt;
+  const float *encT, *WaT, *WbT, *Wn1T, *Wn2T, *decT;
+  const uint32_t *mask_enc, *mask_node, *mask_edge;
+  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *Vebeg, *Vecnt, *Eloc, *Eid, *out3, *bout2;
+  float *A, *B;
+  long nnz;
+};
+
+template <typename S>
+struct Store;
+template <>
+struct Store<float> {
+  __device__ static float ld(const float* p) { return *p; }
+  __device__ static void st(float* p, float v, int) { *p = v; }
+};
+template <>
+struct Store<uint16_t> {
+  __device__ static float ld(const uint16_t* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+  __device__ static void st(uint16_t* p, float v, int) { *p = (uint16_t)(__float_as_uint(bf16r(v)) >> 16); }
+};
+
+// Seed-centric forward-mode Jacobian, VALU form.  Workgroup (tile, stage),
+// 2*Hd lanes: lane t owns feature f = t % Hd and columns c0..c0+7, c0 = 8 (t / Hd).
+// Tangent buffers X (rounds 0, 2, ...) and Y (rounds 1, 3, ...) are
+// [nodes][Hd][16] in LDS.
+template <typename S>
+__global__ void jvp_valu_kernel(JvpArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  S* X = reinterpret_cast<S*>(smem_raw);
+  S* Y = X + (size_t)a.bufX * a.Hd * kCols;
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const int Hd = a.Hd;
+  const int f = threadIdx.x % Hd, c0 = 8 * (threadIdx.x / Hd);
+  const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
+  const int sb = mt[0], sc = mt[1], ob = mt[2], oc = mt[3], bb = mt[4], bc = mt[5];
+  const int hw = Hd / 32;
+  // ---- round 0: encoder tangents on the seeds
+  {
+    const int vb = mt[6], vc = mt[7];
+    for (int q = 0; q < vc; ++q) {
+      const int node = a.V[vb + q];
+      const int p = a.Vself[vb + q];  // seed index
+      const int col0 = a.seedcol[sb + p];
+      const bool act = a.seedact[sb + p] >= 0;
+      const bool on = mbit(a.mask_enc + ((size_t)k * a.M + node) * hw, f);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        int cc = c0 + c, d = cc - col0;
+        float v = 0.f;
+        if (on && d >= 0 && (d < 6 || (act && d < 9))) v = a.encT[d * Hd + f];
+        Store<S>::st(X + ((size_t)q * Hd + f) * kCols + cc, v, 0);
+      }
+    }
+  }
+  __syncthreads();
+  for (int l = 1; l <= a.L; ++l) {
+    S* in = (l & 1) ? X : Y;
+    S* out = (l & 1) ? Y : X;
+    const int vb = mt[6 + 2 * l], vc = mt[7 + 2 * l];
+    const float* WaT = a.WaT + (size_t)(l - 1) * Hd * Hd;
+    const float* WbT = a.WbT + (size_t)(l - 1) * Hd * Hd;
+    const float* W1 = a.Wn1T + (size_t)(l - 1) * Hd * Hd;
+    const float* W2 = a.Wn2T + (size_t)(l - 1) * Hd * Hd;
+    const uint32_t* me = a.mask_edge + ((size_t)(l - 1) * a.N + k) * a.E * hw;
+    // phase A: aggregated edge tangents into `out`
+    for (int q = 0; q < vc; ++q) {
+      const int self = a.Vself[vb + q];
+      float P[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) P[c] = 0.f;
+      if (self >= 0) {
+        const S* t = in + (size_t)self * Hd * kCols + c0;
+        for (int r = 0; r < Hd; ++r) {
+          float w = WaT[r * Hd + f] + WbT[r * Hd + f];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) P[c] += w * Store<S>::ld(t + (size_t)r * kCols + c);
+        }
+      }
+      float acc[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+      const int eb = a.Vebeg[vb + q], ec = a.Vecnt[vb + q];
+      for (int t = 0; t < ec; ++t) {
+        const int jl = a.Eloc[eb + t], eid = a.Eid[eb + t];
+        if (!mbit(me + (size_t)eid * hw, f)) continue;
+        float yb[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) yb[c] = 0.f;
+        if (jl >= 0) {
+          const S* tj = in + (size_t)jl * Hd * kCols + c0;
+          for (int r = 0; r < Hd; ++r) {
+            float w = WbT[r * Hd + f];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) yb[c] += w * Store<S>::ld(tj + (size_t)r * kCols + c);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] += P[c] - yb[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) Store<S>::st(out + ((size_t)q * Hd + f) * kCols + c0 + c, acc[c], 0);
+    }
+    __syncthreads();
+    // phase B: node update tangents, written over the aggregate one node at a time
+    const uint32_t* mn = a.mask_node + ((size_t)(l - 1) * a.N + k) * a.M * hw;
+    for (int q = 0; q < vc; ++q) {
+      const int node = a.V[vb + q];
+      const int self = a.Vself[vb + q];
+      float z[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) z[c] = 0.f;
+      if (mbit(mn + (size_t)node * hw, f)) {
+        if (self >= 0) {
+          const S* t = in + (size_t)self * Hd * kCols + c0;
+          for (int r = 0; r < Hd; ++r) {
+            float w = W1[r * Hd + f];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) z[c] += w * Store<S>::ld(t + (size_t)r * kCols + c);
+          }
+        }
+        const S* ag = out + (size_t)q * Hd * kCols + c0;
+        for (int r = 0; r < Hd; ++r) {
+          float w = W2[r * Hd + f];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) z[c] += w * Store<S>::ld(ag + (size_t)r * kCols + c);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 8; ++c) Store<S>::st(out + ((size_t)q * Hd + f) * kCols + c0 + c, z[c], 0);
+      __syncthreads();
+    }
+  }
+  // ---- decoder and the Jacobian blocks
+  S* fin = (a.L & 1) ? Y : X;
+  const int vbL = mt[6 + 2 * a.L];
+  for (int t = threadIdx.x; t < oc * 18; t += blockDim.x) {
+    const int o = t / 18, rem = t % 18, r = rem / 6, d = rem % 6;  // r: 0..2 (row pair), d: input column
+    const int q = a.out3[3 * (ob + o)], p = a.out3[3 * (ob + o) + 1];
+    const long e = a.out3[3 * (ob + o) + 2];
+    const int node = a.V[vbL + q];
+    const int s_node = a.seed[sb + p];
+    const int col = a.seedcol[sb + p] + d;
+    float dov = 0.f;
+    const S* tq = fin + (size_t)q * Hd * kCols + col;
+    for (int ff = 0; ff < Hd; ++ff) dov += a.decT[ff * 6 + 3 + r] * Store<S>::ld(tq + (size_t)ff * kCols);
+    const bool diag = node == s_node;
+    float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
+    float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
+    float* blk = a.A + ((size_t)k * a.nnz + e) * 36;
+    blk[r * 6 + d] = dp;
+    blk[(3 + r) * 6 + d] = dv;
+  }
+  for (int t = threadIdx.x; t < bc * 9; t += blockDim.x) {
+    const int o = t / 9, rem = t % 9, r = rem / 3, d = rem % 3;
+    const int q = a.bout2[2 * (bb + o)], p = a.bout2[2 * (bb + o) + 1];
+    const int node = a.V[vbL + q];
+    const int act = a.seedact[sb + p];
+    const int col = a.seedcol[sb + p] + 6 + d;
+    float dov = 0.f;
+    const S* tq = fin + (size_t)q * Hd * kCols + col;
+    for (int ff = 0; ff < Hd; ++ff) dov += a.decT[ff * 6 + 3 + r] * Store<S>::ld(tq + (size_t)ff * kCols);
+    float dv = a.dt * dov;
+    float* Bi = a.B + (((size_t)k * a.M + node) * NBX) * a.nu;
+    Bi[(3 + r) * a.nu + 3 * act + d] = dv;
+    Bi[r * a.nu + 3 * act + d] = a.dt * dv;
+  }
+  (void)sc;
+}
+
+__global__ void fill_zero_kernel(float* p, long n) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = 0.f;
+}
+
+// c = f - sum_j A^{ij} xhat^j - B^i uhat (and f copied out); one lane per (stage, node).
+__global__ void gnn_offset_kernel(int N, int M, int nu, long nnz, const int32_t* prow, const int32_t* pcol,
+                                  const float* xhat, const float* uhat, const float* A, const float* B,
+                                  const float* fwd, float* c, float* fnext) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N * M) return;
+  const int k = s / M, i = s - k * M;
+  float lin[6] = {0, 0, 0, 0, 0, 0};
+  const float* xk = xhat + (size_t)k * M * NBX;
+  for (int e = prow[i]; e < prow[i + 1]; ++e) {
+    const float* blk = A + ((size_t)k * nnz + e) * 36;
+    const float* xj = xk + (size_t)pcol[e] * NBX;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int d = 0; d < 6; ++d) lin[r] += blk[r * 6 + d] * xj[d];
+  }
+  const float* Bi = B + (size_t)s * NBX * nu;
+  const float* u = uhat + (size_t)k * nu;
+  for (int r = 0; r < 6; ++r)
+    for (int d = 0; d < nu; ++d) lin[r] += Bi[r * nu + d] * u[d];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    float fv = fwd[(size_t)s * NBX + r];
+    c[(size_t)s * NBX + r] = fv - lin[r];
+    if (fnext) fnext[(size_t)s * NBX + r] = fv;
+  }
+}
+
+template <typename T>
+gnmpc_status dalloc(gnmpc_plan* p, T*& ptr, size_t count) {
+  GNMPC_HIP_TRY(p, hipMalloc((void**)&ptr, sizeof(T) * std::max<size_t>(count, 1)));
+  p->gnn->allocs.push_back((void*)ptr);
+  return GNMPC_OK;
+}
+
+template <typename T>
+gnmpc_status dupload(gnmpc_plan* p, T*& ptr, const std::vector<T>& v) {
+  gnmpc_status s = dalloc(p, ptr, v.size());
+  if (s != GNMPC_OK) return s;
+  if (!v.empty()) GNMPC_HIP_TRY(p, hipMemcpy(ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return GNMPC_OK;
+}
+
+// Seed tiles and their per-round node lists (host).
+struct TilePlan {
+  std::vector<int32_t> meta, seed, seedcol, seedact, V, Vself, Vebeg, Vecnt, Eloc, Eid, out3, bout2;
+  int bufX = 0, bufY = 0, n_tiles = 0;
+};
+
+void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
+  const int M = p->M;
+  std::vector<std::vector<int32_t>> outn(M);  // receivers of each sender
+  for (int i = 0; i < M; ++i)
+    for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) outn[p->h_col[e]].push_back(i);
+  std::vector<int32_t> act_of(M, -1);
+  for (int a = 0; a < (int)p->h_act.size(); ++a) act_of[p->h_act[a]] = a;
+  const int stride = 6 + 2 * (L + 1);
+  std::vector<int32_t> where(M, -1);
+  int i = 0;
+  while (i < M) {
+    std::vector<int32_t> seeds, cols;
+    int used = 0;
+    while (i < M && (int)seeds.size() < max_seeds) {
+      int need = 6 + (act_of[i] >= 0 ? 3 : 0);
+      if (used + need > kCols) break;
+      seeds.push_back(i);
+      cols.push_back(used);
+      used += need;
+      ++i;
+    }
+    std::vector<int32_t> m(stride, 0);
+    m[0] = (int32_t)tp.seed.size();
+    m[1] = (int32_t)seeds.size();
+    for (size_t t = 0; t < seeds.size(); ++t) {
+      tp.seed.push_back(seeds[t]);
+      tp.seedcol.push_back(cols[t]);
+      tp.seedact.push_back(act_of[seeds[t]]);
+    }
+    std::vector<std::vector<int32_t>> Vl(L + 1);
+    Vl[0] = seeds;
+    for (int l = 1; l <= L; ++l) {
+      std::vector<int32_t> nxt = Vl[l - 1];
+      for (int32_t j : Vl[l - 1])
+        for (int32_t r : outn[j]) nxt.push_back(r);
+      std::sort(nxt.begin(), nxt.end());
+      nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
+      Vl[l] = nxt;
+    }
+    for (int l = 0; l <= L; ++l) {
+      m[6 + 2 * l] = (int32_t)tp.V.size();
+      m[7 + 2 * l] = (int32_t)Vl[l].size();
+      if (l % 2 == 0) tp.bufX = std::max(tp.bufX, (int)Vl[l].size());
+      else tp.bufY = std::max(tp.bufY, (int)Vl[l].size());
+      if (l > 0) {
+        for (size_t q = 0; q < Vl[l - 1].size(); ++q) where[Vl[l - 1][q]] = (int32_t)q;
+      }
+      for (size_t q = 0; q < Vl[l].size(); ++q) {
+        int32_t node = Vl[l][q];
+        tp.V.push_back(node);
+        if (l == 0) {
+          tp.Vself.push_back((int32_t)q);
+          tp.Vebeg.push_back((int32_t)tp.Eloc.size());
+          tp.Vecnt.push_back(0);
+          continue;
+        }
+        // In-edges whose tangent is nonzero: every edge when the receiver
+        // itself carries a tangent (its edge term W_a dh_i + W_b dh_i survives
+        // even if the sender's tangent is zero, marked by Eloc = -1), else only
+        // the edges from senders that carry one.
+        const bool self_on = where[node] >= 0;
+        tp.Vself.push_back(where[node]);
+        tp.Vebeg.push_back((int32_t)tp.Eloc.size());
+        int cnt = 0;
+        for (int e = p->h_row_ptr[node]; e < p->h_row_ptr[node + 1]; ++e) {
+          int32_t j = p->h_col[e];
+          if (where[j] >= 0 || self_on) {
+            tp.Eloc.push_back(where[j]);
+            tp.Eid.push_back(e);
+            ++cnt;
+          }
+        }
+        tp.Vecnt.push_back(cnt);
+      }
+      if (l > 0)
+        for (int32_t n : Vl[l - 1]) where[n] = -1;
+    }
+    // output blocks: (node of the last round, seed) pairs inside the pattern
+    m[2] = (int32_t)(tp.out3.size() / 3);
+    m[4] = (int32_t)(tp.bout2.size() / 2);
+    int oc = 0, bc = 0;
+    for (size_t q = 0; q < Vl[L].size(); ++q) {
+      int32_t node = Vl[L][q];
+      const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
+      const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
+      for (size_t s = 0; s < seeds.size(); ++s) {
+        const int32_t* it = std::lower_bound(rb, re, seeds[s]);
+        if (it == re || *it != seeds[s]) continue;
+        tp.out3.push_back((int32_t)q);
+        tp.out3.push_back((int32_t)s);
+        tp.out3.push_back((int32_t)(it - p->h_pcol.data()));
+        ++oc;
+        if (act_of[seeds[s]] >= 0) {
+          tp.bout2.push_back((int32_t)q);
+          tp.bout2.push_back((int32_t)s);
+          ++bc;
+        }
+      }
+    }
+    m[3] = oc;
+    m[5] = bc;
+    tp.meta.insert(tp.meta.end(), m.begin(), m.end());
+    ++tp.n_tiles;
+  }
+}
+
+}  // namespace
+
+void gnn_free(gnmpc_plan* p) {
+  if (!p->gnn) return;
+  for (void* q : p->gnn->allocs) (void)hipFree(q);
+  delete p->gnn;
+  p->gnn = nullptr;
+}
+
+gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w) {
+  (void)n_w;
+  gnn_free(p);
+  p->gnn = new GnnState();
+  GnnState& g = *p->gnn;
+  const int Hd = desc->Hd, L = desc->L;
+  g.Hd = Hd;
+  g.L = L;
+  g.dtype = desc->dtype;
+  g.dt = (float)desc->dt;
+  g.N = p->dims.N;
+  g.M = p->M;
+  g.E = p->E;
+  if (p->dims.dtype != GNMPC_F32) {
+    p->last_error = "model_set_gnn: the GNN path writes FP32 Jacobians (plan dtype must be F32)";
+    gnn_free(p);
+    return GNMPC_UNSUPPORTED;
+  }
+  const bool bf = desc->dtype == GNMPC_BF16;
+  auto cv = [&](double v) { float f = (float)v; return bf ? host_bf16r(f) : f; };
+  // unpack W_enc[Hd][9], b_enc, (W_e[Hd][2Hd], b_e, W_n[Hd][2Hd], b_n) x L, W_dec[6][Hd], b_dec
+  size_t o = 0;
+  std::vector<float> encT(9 * Hd), benc(Hd), WaT((size_t)L * Hd * Hd), WbT((size_t)L * Hd * Hd), be((size_t)L * Hd),
+      Wn1T((size_t)L * Hd * Hd), Wn2T((size_t)L * Hd * Hd), bn((size_t)L * Hd), decT(6 * Hd), bdec(6);
+  for (int f = 0; f < Hd; ++f)
+    for (int d = 0; d < 9; ++d) encT[d * Hd + f] = cv(w[o + f * 9 + d]);
+  o += 9 * Hd;
+  for (int f = 0; f < Hd; ++f) benc[f] = (float)w[o + f];  // biases stay FP32 (added to FP32 sums)
+  o += Hd;
+  for (int l = 0; l < L; ++l) {
+    for (int f = 0; f < Hd; ++f)
+      for (int q = 0; q < Hd; ++q) {
+        WaT[((size_t)l * Hd + q) * Hd + f] = cv(w[o + (size_t)f * 2 * Hd + q]);
+        WbT[((size_t)l * Hd + q) * Hd + f] = cv(w[o + (size_t)f * 2 * Hd + Hd + q]);
+      }
+    o += (size_t)2 * Hd * Hd;
+    for (int f = 0; f < Hd; ++f) be[l * Hd + f] = (float)w[o + f];
+    o += Hd;
+    for (int f = 0; f < Hd; ++f)
+      for (int q = 0; q < Hd; ++q) {
+        Wn1T[((size_t)l * Hd + q) * Hd + f] = cv(w[o + (size_t)f * 2 * Hd + q]);
+        Wn2T[((size_t)l * Hd + q) * Hd + f] = cv(w[o + (size_t)f * 2 * Hd + Hd + q]);
+      }
+    o += (size_t)2 * Hd * Hd;
+    for (int f = 0; f < Hd; ++f) bn[l * Hd + f] = (float)w[o + f];
+    o += Hd;
+  }
+  for (int r = 0; r < 6; ++r)
+    for (int f = 0; f < Hd; ++f) decT[f * 6 + r] = cv(w[o + r * Hd + f]);
+  o += 6 * Hd;
+  for (int r = 0; r < 6; ++r) bdec[r] = (float)w[o + r];
+  gnmpc_status s;
+#define UP(ptr, vec) \
+  if ((s = dupload(p, g.ptr, vec)) != GNMPC_OK) return s;
+  UP(encT, encT) UP(benc, benc) UP(WaT, WaT) UP(WbT, WbT) UP(be, be) UP(Wn1T, Wn1T) UP(Wn2T, Wn2T) UP(bn, bn)
+  UP(decT, decT) UP(bdec, bdec)
+  const size_t NM = (size_t)g.N * g.M;
+  if ((s = dalloc(p, g.h, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
+  if ((s = dalloc(p, g.mask_enc, NM * (Hd / 32))) != GNMPC_OK) return s;
+  if ((s = dalloc(p, g.mask_node, (size_t)L * NM * (Hd / 32))) != GNMPC_OK) return s;
+  if ((s = dalloc(p, g.mask_edge, (size_t)L * g.N * std::max(g.E, 1) * (Hd / 32))) != GNMPC_OK) return s;
+  if ((s = dalloc(p, g.fnext, NM * NBX)) != GNMPC_OK) return s;
+  g.maxdeg = 0;
+  for (int i = 0; i < p->M; ++i) g.maxdeg = std::max(g.maxdeg, p->h_row_ptr[i + 1] - p->h_row_ptr[i]);
+  // seed tiles: two seeds per tile when the tangent buffers fit in LDS, else one
+  const size_t elem = bf ? 2 : 4;
+  TilePlan tp;
+  bool fits = false;
+  for (int ms = 2; ms >= 1 && !fits; --ms) {
+    tp = TilePlan();
+    build_tiles(p, L, ms, tp);
+    g.jvp_lds = (size_t)(tp.bufX + tp.bufY) * Hd * kCols * elem;
+    fits = g.jvp_lds <= 160 * 1024;
+  }
+  if (!fits) {
+    p->last_error = "model_set_gnn: tangent buffers exceed LDS for this graph";
+    gnn_free(p);
+    return GNMPC_UNSUPPORTED;
+  }
+  g.n_tiles = tp.n_tiles;
+  g.meta_stride = 6 + 2 * (L + 1);
+  g.bufX = tp.bufX;
+  g.bufY = tp.bufY;
+  UP(meta, tp.meta) UP(seed, tp.seed) UP(seedcol, tp.seedcol) UP(seedact, tp.seedact) UP(V, tp.V)
+  UP(Vself, tp.Vself) UP(Vebeg, tp.Vebeg) UP(Vecnt, tp.Vecnt) UP(Eloc, tp.Eloc) UP(Eid, tp.Eid)
+  UP(out3, tp.out3) UP(bout2, tp.bout2)
+#undef UP
+  return GNMPC_OK;
+}
+
+gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
+                                  void* fnext, hipStream_t s) {
+  GnnState& g = *p->gnn;
+  const int Hd = g.Hd, N = g.N, M = g.M;
+  FwdArgs fa;
+  fa.N = N;
+  fa.M = M;
+  fa.E = g.E;
+  fa.Hd = Hd;
+  fa.L = g.L;
+  fa.nu = p->dims.nu;
+  fa.bf16 = g.dtype == GNMPC_BF16;
+  fa.dt = g.dt;
+  fa.xhat = (const float*)xhat;
+  fa.uhat = (const float*)uhat;
+  fa.row_ptr = p->d_row_ptr;
+  fa.col = p->d_col;
+  fa.act_of_node = p->d_act_of_node;
+  fa.encT = g.encT;
+  fa.benc = g.benc;
+  fa.WaT = g.WaT;
+  fa.WbT = g.WbT;
+  fa.be = g.be;
+  fa.Wn1T = g.Wn1T;
+  fa.Wn2T = g.Wn2T;
+  fa.bn = g.bn;
+  fa.decT = g.decT;
+  fa.bdec = g.bdec;
+  fa.h = g.h;
+  fa.mask_enc = g.mask_enc;
+  fa.mask_node = g.mask_node;
+  fa.mask_edge = g.mask_edge;
+  fa.fnext = g.fnext;
+  fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
+  const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;
+  for (int l = 0; l < g.L; ++l) fwd_layer_kernel<<<N * M, Hd, lds_fwd, s>>>(fa, l);
+  fwd_dec_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa);
+  const long nB = (long)N * M * NBX * p->dims.nu;
+  fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
+  JvpArgs ja;
+  ja.N = N;
+  ja.M = M;
+  ja.E = g.E;
+  ja.Hd = Hd;
+  ja.L = g.L;
+  ja.nu = p->dims.nu;
+  ja.bf16 = fa.bf16;
+  ja.meta_stride = g.meta_stride;
+  ja.bufX = g.bufX;
+  ja.dt = g.dt;
+  ja.encT = g.encT;
+  ja.WaT = g.WaT;
+  ja.WbT = g.WbT;
+  ja.Wn1T = g.Wn1T;
+  ja.Wn2T = g.Wn2T;
+  ja.decT = g.decT;
+  ja.mask_enc = g.mask_enc;
+  ja.mask_node = g.mask_node;
+  ja.mask_edge = g.mask_edge;
+  ja.meta = g.meta;
+  ja.seed = g.seed;
+  ja.seedcol = g.seedcol;
+  ja.seedact = g.seedact;
+  ja.V = g.V;
+  ja.Vself = g.Vself;
+  ja.Vebeg = g.Vebeg;
+  ja.Vecnt = g.Vecnt;
+  ja.Eloc = g.Eloc;
+  ja.Eid = g.Eid;
+  ja.out3 = g.out3;
+  ja.bout2 = g.bout2;
+  ja.A = (float*)A;
+  ja.B = (float*)B;
+  ja.nnz = p->nnz;
+  dim3 grid(g.n_tiles, N);
+  if (fa.bf16) {
+    GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<uint16_t>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
+    jvp_valu_kernel<uint16_t><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);
+  } else {
+    GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<float>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
+    jvp_valu_kernel<float><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);
+  }
+  gnn_offset_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(N, M, p->dims.nu, p->nnz, p->d_prow, p->d_pcol,
+                                                               (const float*)xhat, (const float*)uhat,
+                                                               (const float*)A, (const float*)B, g.fnext,
+                                                               (float*)c, (float*)fnext);
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
 }
 
 }  // namespace gnmpc

@@ -1,0 +1,124 @@
+"""GPU parity of the GNN forward pass and its forward-mode Jacobians (through
+the C-ABI) against the FP64 oracle's per-node automatic differentiation."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.gnn import gnn_forward, gnn_linearize
+from paper_2602_17601_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+gn = pytest.importorskip("paper_2602_17601_amd.gnmpc")
+
+
+def _t(a, dtype=torch.float32):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _gpu_linearize(P, dtype):
+    plan = gn.Plan(P.M, P.nu, P.N, max(P.rows.n, 1), gn.F32)
+    plan.graph_set(P.row_ptr, P.col, P.gnn.L)
+    plan.model_set_gnn(P.gnn, P.act, dtype=dtype)
+    xh = np.asarray(P.xhat, np.float32).astype(np.float64)
+    uh = np.asarray(P.uhat, np.float32).astype(np.float64)
+    A = torch.full((P.N, plan.nnz, 6, 6), float("nan"), device="cuda")
+    B = torch.full((P.N, P.M, 6, P.nu), float("nan"), device="cuda")
+    c = torch.full((P.N, P.M, 6), float("nan"), device="cuda")
+    f = torch.full((P.N, P.M, 6), float("nan"), device="cuda")
+    plan.linearize(_t(xh), _t(uh), A, B, c, f)
+    torch.cuda.synchronize()
+    return plan, xh, uh, _np(A), _np(B), _np(c), _np(f)
+
+
+def _delta_A(A, prow, pcol, M):
+    """A with the identity removed from the diagonal blocks (the part the model learns)."""
+    D = A.copy()
+    for i in range(M):
+        for e in range(prow[i], prow[i + 1]):
+            if pcol[e] == i:
+                D[:, e] -= np.eye(6)
+    return D
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_gnn_fp32_chain100_matches_oracle():
+    """100-node 1-2-hop chain, Hd=64, L=2, N=20, FP32 MLPs: next states and every
+    Jacobian block against FP64 forward-mode AD (rel-Frobenius <= 1e-5)."""
+    P = wl.gnn100_fp32()
+    plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.F32)
+    prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, P.gnn, P.row_ptr, P.col, P.act)
+    gp, gc = plan.graph_pattern()
+    assert np.array_equal(gp, prow) and np.array_equal(gc, pcol)
+    assert np.all(np.isfinite(A)) and np.all(np.isfinite(B)) and np.all(np.isfinite(c))
+    dt = P.gnn.dt
+    # next state increment (f - x)/dt is the model output; compare that, not f itself
+    inc, inc_r = (f - xh[:-1]) / dt, (fr - xh[:-1]) / dt
+    assert _rel(inc, inc_r) < 1e-5
+    dA, dAr = _delta_A(A, prow, pcol, P.M), _delta_A(Ar, prow, pcol, P.M)
+    worst = max(_rel(dA[k], dAr[k]) for k in range(P.N))
+    assert worst < 1e-5, worst
+    assert _rel(B, Br) < 1e-5
+    assert np.abs(c - cr).max() < 1e-5 * (1 + np.abs(xh).max())
+    # nonzero B only within L hops of the actuators
+    assert np.abs(Br).sum() > 0
+
+
+@pytest.mark.parametrize("M,hops,L,Hd,n_act,N", [(23, 1, 1, 64, 2, 3), (31, 3, 2, 64, 3, 2),
+                                                 (17, 2, 3, 64, 1, 2)])
+def test_gnn_fp32_small_graphs_match_oracle(M, hops, L, Hd, n_act, N):
+    P = wl.make_problem("gnn_small", M=M, hops=hops, N=N, n_act=n_act, model="gnn", seed=M + L, Hd=Hd, L=L,
+                        x0_sigma=0.3, walk=0.05)
+    plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.F32)
+    prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, P.gnn, P.row_ptr, P.col, P.act)
+    assert np.all(np.isfinite(A)) and np.all(np.isfinite(B))
+    dA, dAr = _delta_A(A, prow, pcol, P.M), _delta_A(Ar, prow, pcol, P.M)
+    assert _rel(dA, dAr) < 1e-5
+    assert _rel(B, Br) < 1e-5
+    assert _rel((f - xh[:-1]), (fr - xh[:-1])) < 1e-5
+
+
+def test_gnn_bf16_paper_scale_sampled_against_bf16_weight_oracle():
+    """1000-node chain, Hd=128, L=3, BF16 MLPs with FP32 accumulation, N=20, on
+    sampled (stage, node) pairs against the FP64 oracle with the same
+    BF16-rounded weights.
+      next states: the exact FP64 model, rel-Frobenius of the increments per
+        stage <= 2e-2;
+      Jacobians: the ReLU decisions are floating-point-decided bits, so the
+        oracle takes them in BF16 (rounding='bf16'); the tangents are exact, so
+        the bound measures the kernel's tangent arithmetic: rel-Frobenius of
+        A - I and of B per stage <= 2e-2."""
+    P = wl.gnn1000_bf16()
+    plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.BF16)
+    assert np.all(np.isfinite(A)) and np.all(np.isfinite(B)) and np.all(np.isfinite(c))
+    Wr = P.gnn.rounded_bf16()
+    stages = [0, 9, 19]
+    nodes = [0, 1, 2, 247, 249, 251, 499, 500, 650, 998, 999]
+    prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes,
+                                               rounding="bf16")
+    _, _, _, _, _, fe = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes[:4])
+    dt = P.gnn.dt
+    dA, dAr = _delta_A(A, prow, pcol, P.M), _delta_A(Ar, prow, pcol, P.M)
+    report = []
+    for k in stages:
+        sel = np.concatenate([np.arange(prow[i], prow[i + 1]) for i in nodes])
+        ea = _rel(dA[k, sel], dAr[k, sel])
+        eb = _rel(B[k, nodes], Br[k, nodes])
+        ef = _rel((f[k, nodes[:4]] - xh[k, nodes[:4]]) / dt, (fe[k, nodes[:4]] - xh[k, nodes[:4]]) / dt)
+        worst = max(_rel(dA[k, prow[i]:prow[i + 1]], dAr[k, prow[i]:prow[i + 1]]) for i in nodes)
+        report.append((k, ea, eb, ef, worst))
+    print("stage, rel(A-I), rel(B), rel(increment), worst node rel(A-I):", report)
+    for k, ea, eb, ef, worst in report:
+        assert ea < 2e-2 and eb < 2e-2 and ef < 2e-2, report
+    # B is zero away from the actuators, exactly
+    for k in stages:
+        for i in nodes:
+            if np.abs(Br[k, i]).sum() == 0:
+                assert np.abs(B[k, i]).max() == 0

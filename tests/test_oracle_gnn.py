@@ -136,3 +136,21 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert r[3] == 1.0078125
     assert r[4] == -3.140625
     assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
+
+
+def test_bf16_mask_mode_leaves_tangents_exact():
+    """In 'bf16' mode only the values (hence the ReLU decisions) see rounded
+    operands.  With identity activations there are no decisions, so the
+    Jacobian must be bitwise the exact one; with ReLU the next state moves by
+    no more than bfloat16 rounding allows."""
+    from oracle.gnn import _round
+    rp, col, act, W, x, u = _small(M=9, L=2)
+    e = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity")
+    b = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity", rounding="bf16")
+    assert np.array_equal(e[2], b[2]) and np.array_equal(e[3], b[3])
+    fe = gnn_forward(x, u, W, rp, col, act)
+    fb = gnn_forward(x, u, W, rp, col, act, rounding="bf16")
+    inc_e, inc_b = (fe - x) / W.dt, (fb - x) / W.dt
+    assert 0 < np.linalg.norm(inc_b - inc_e) / np.linalg.norm(inc_e) < 3e-2
+    assert _round(np.array([1.00390625]), "bf16")[0] == 1.0
+    assert _round(np.array([1.005859375]), "bf16")[0] == 1.0078125
