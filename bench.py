@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Condensed MPC steps/s on one MI355X: 1000-node chain, horizon N = 20.
+
+One step is one pass of the whole hot path of Algorithm 1 on resident inputs:
+linearize the GNN (forward pass + forward-mode Jacobians, BF16 MLPs with FP32
+accumulation), condense (S_k / Gx_k recursion, H, g, 200 node-position rows,
+FP32) and solve the condensed box QP (ADMM, FP32).  The plain form (analytic
+mass-spring-damper Jacobians on the same graph) is timed beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "condensed MPC steps/s, 1000 nodes N=20 (GNN vs plain); % HBM roofline"
+BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+
+def jacobian_flops(P):
+    """Algorithmic FLOPs of one GNN linearization: exact forward mode restricted
+    to each seed's receptive support.  Per tangent column of seed s and round l:
+    [W_a; W_b] on every node of V_{l-1}(s) (4 Hd^2), W_n2 on every node of V_l(s)
+    and W_n1 on those also in V_{l-1}(s) (2 Hd^2 each), then the 3 used decoder
+    rows on V_L(s) (6 Hd); V_l(s) = nodes within l hops downstream of s."""
+    Hd, L, M = P.gnn.Hd, P.gnn.L, P.M
+    outn = [[] for _ in range(M)]
+    for i in range(M):
+        for j in P.col[P.row_ptr[i]:P.row_ptr[i + 1]]:
+            outn[j].append(i)
+    act = set(int(a) for a in P.act)
+    total = 0.0
+    for s in range(M):
+        V = [{s}]
+        for _ in range(L):
+            nxt = set(V[-1])
+            for j in V[-1]:
+                nxt.update(outn[j])
+            V.append(nxt)
+        per_col = sum(4 * Hd * Hd * len(V[l - 1]) + 2 * Hd * Hd * (len(V[l]) + len(V[l - 1]))
+                      for l in range(1, L + 1)) + 6 * Hd * len(V[L])
+        total += per_col * (6 + (3 if s in act else 0))
+    return total * P.N
+
+
+def cpu_baseline(P, Pm):
+    """The FP64 oracle on the host: a bounded sample of the GNN linearization
+    (node-stages), one full condensing with the GNN Jacobian pattern and one QP
+    solve; the step time is extrapolated from the per-node-stage cost."""
+    from threadpoolctl import threadpool_limits
+    from oracle.condense import condense_local
+    from oracle.gnn import gnn_linearize
+    from oracle.graph import jacobian_pattern
+    from oracle.qp import qp_ipm
+    Wr = P.gnn.rounded_bf16()
+    stages, nodes = [7], list(range(300, 500))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes, rounding="bf16")
+        t_lin = (time.perf_counter() - t0) / (len(stages) * len(nodes)) * P.N * P.M
+        prow, pcol = jacobian_pattern(P.row_ptr, P.col, P.M, P.gnn.L)
+        rng = np.random.default_rng(0)
+        A = rng.normal(0, 0.02, size=(P.N, len(pcol), 6, 6))
+        B = rng.normal(0, 1e-4, size=(P.N, P.M, 6, P.nu))
+        c = rng.normal(0, 1e-4, size=(P.N, P.M, 6))
+        t0 = time.perf_counter()
+        l = condense_local(A, B, c, prow, pcol, P.x0, P.costs.Q, P.costs.q, P.costs.R, P.costs.r, P.rows)
+        t_cond = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        qp_ipm(l["H"], l["g"], P.lb, P.ub, l["Ct"], np.full(P.rows.n, -np.inf), l["dt"] + 1.0)
+        t_qp = time.perf_counter() - t0
+    step = t_lin + t_cond + t_qp
+    return {"value": 1.0 / step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle, 1 thread: GNN linearization timed on {len(nodes)} node-stages "
+                       f"({t_lin / (P.N * P.M) * 1e3:.1f} ms each, extrapolated to {P.N * P.M}), "
+                       f"one full condensing ({t_cond:.2f} s) and one QP ({t_qp:.2f} s)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_17601_amd import gnmpc as gn
+    from paper_2602_17601_amd import workloads as wl
+
+    dev = "cuda"
+    P = wl.gnn1000_bf16()
+    Pm = wl.gnn1000_bf16(model="msd")
+    n = P.N * P.nu
+
+    def t(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev).contiguous()
+
+    def make(Pr, gnn):
+        plan = gn.Plan(Pr.M, Pr.nu, Pr.N, Pr.rows.n, gn.F32)
+        plan.graph_set(Pr.row_ptr, Pr.col, Pr.gnn.L if gnn else 1)
+        if gnn:
+            plan.model_set_gnn(Pr.gnn, Pr.act, dtype=gn.BF16)
+        else:
+            plan.model_set_msd(Pr.msd, Pr.act)
+        plan.rows_set(Pr.rows.node, Pr.rows.stage)
+        bufs = dict(xhat=t(Pr.xhat), uhat=t(Pr.uhat), x0=t(Pr.x0), Q=t(Pr.costs.Q), q=t(Pr.costs.q),
+                    R=t(Pr.costs.R), r=t(Pr.costs.r), rowC=t(Pr.rows.C), rowd=t(Pr.rows.d), lb=t(Pr.lb),
+                    ub=t(Pr.ub),
+                    A=torch.empty(Pr.N, plan.nnz, 6, 6, device=dev), B=torch.empty(Pr.N, Pr.M, 6, Pr.nu, device=dev),
+                    c=torch.empty(Pr.N, Pr.M, 6, device=dev), H=torch.empty(n, n, device=dev),
+                    g=torch.empty(n, device=dev), Ct=torch.empty(Pr.rows.n, n, device=dev),
+                    dt=torch.empty(Pr.rows.n, device=dev), u=torch.empty(n, device=dev),
+                    info=torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device=dev))
+        return plan, bufs
+
+    settings = gn.default_admm_settings()
+
+    def step(plan, b):
+        plan.linearize(b["xhat"], b["uhat"], b["A"], b["B"], b["c"])
+        plan.condense(b["A"], b["B"], b["c"], b["x0"], b["Q"], b["q"], b["R"], b["r"], b["rowC"], b["rowd"],
+                      b["H"], b["g"], b["Ct"], b["dt"])
+        plan.solve_box_qp(b["H"], b["g"], b["lb"], b["ub"], b["Ct"], None, b["dt"], b["u"], b["info"],
+                          settings=settings)
+
+    def timed(plan, b):
+        for _ in range(args.warmup):
+            step(plan, b)
+        torch.cuda.synchronize()
+        plan.timers_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(plan, b)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        phases = plan.timers_read()
+        plan.timers_enable(False)
+        return el, phases
+
+    plan_g, bg = make(P, True)
+    plan_m, bm = make(Pm, False)
+    el_g, ph_g = timed(plan_g, bg)
+    el_m, ph_m = timed(plan_m, bm)
+    qpi = gn.qp_info(bg["info"])
+    steps_g = args.steps / el_g
+    steps_m = args.steps / el_m
+
+    jac_ms, jac_n = ph_g["gnn_jacobian"]
+    jac_avg_s = jac_ms / max(jac_n, 1) * 1e-3
+    flops = jacobian_flops(P)
+    achieved = flops / jac_avg_s / 1e12 if jac_avg_s > 0 else 0.0
+    roofline = {"kernel": "gnn_jacobian", "bound": "mfma", "achieved": achieved,
+                "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / BF16_DENSE_PEAK_TFLOPS,
+                "traffic": None, "algorithmic_flops_per_launch": flops, "avg_launch_ms": jac_avg_s * 1e3}
+
+    def phase_avg(ph):
+        return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items() if v[1]}
+
+    out = {
+        "metric": METRIC,
+        "value": steps_g,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el_g / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": ("1000-node 1-2-hop chain, GNN Hd=128 L=3 (BF16 MLPs, FP32 accumulate), "
+                                "n_u=12 at 4 nodes, N=20, 200 node-position rows, FP32 condensing, ADMM box QP"),
+                   "M": P.M, "N": P.N, "nu": P.nu, "nnz_blocks": int(plan_g.nnz), "state_rows": P.rows.n},
+        "plain_steps_per_s": steps_m,
+        "plain_ms_per_step": el_m / args.steps * 1e3,
+        "phase_ms_gnn": phase_avg(ph_g),
+        "phase_ms_plain": phase_avg(ph_m),
+        "qp_iters_gnn": qpi.iters,
+        "qp_status_gnn": qpi.status,
+        "roofline": roofline,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(P, Pm),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -226,6 +226,29 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* plan, int32_t n, const void* H, cons
                                 const void* lc, const void* uc, const gnmpc_admm_settings* settings,
                                 void* u, gnmpc_qp_info* info, void* stream);
 
+/* ---------------- per-phase GPU timers ---------------- */
+
+/* Phases timed by gnmpc_timers_*: hipEvents are recorded on the caller's stream
+ * around the kernels of each phase while timers are enabled. */
+typedef enum {
+  GNMPC_PH_GNN_FORWARD = 0,       /* GNN forward pass at the N linearization points   */
+  GNMPC_PH_GNN_JACOBIAN = 1,      /* the forward-mode Jacobian kernel                  */
+  GNMPC_PH_GNN_ASSEMBLY = 2,      /* B zero fill and the offsets c                     */
+  GNMPC_PH_MSD_LINEARIZE = 3,     /* analytic mass-spring-damper linearization         */
+  GNMPC_PH_CONDENSE_PROPAGATE = 4,/* the stage recursion for S_k and Gx_k              */
+  GNMPC_PH_CONDENSE_GRAM = 5,     /* H and g                                           */
+  GNMPC_PH_CONDENSE_ROWS = 6,     /* condensed state rows                              */
+  GNMPC_PH_QP = 7,                /* the QP solve                                      */
+  GNMPC_PH_COUNT = 8
+} gnmpc_phase;
+
+/* Enable (1) or disable (0) the timers; enabling clears earlier records and
+ * creates the events (up to 1024 records per phase). */
+gnmpc_status gnmpc_timers_enable(gnmpc_plan* plan, int32_t enable);
+/* Wait for the recorded events and return, per phase, the summed elapsed
+ * milliseconds and the number of records (arrays of GNMPC_PH_COUNT). */
+gnmpc_status gnmpc_timers_read(gnmpc_plan* plan, double* total_ms, int32_t* count);
+
 /* Default ADMM settings (rho 0.1, sigma 1e-6, alpha 1.6, eps 1e-6, kappa_fp64 1e7,
  * 4000 iterations, convergence checked every 10). */
 void gnmpc_admm_default_settings(gnmpc_admm_settings* s);

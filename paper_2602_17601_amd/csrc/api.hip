@@ -172,9 +172,56 @@ gnmpc_status gnmpc_plan_create(gnmpc_plan** plan, const gnmpc_dims* dims, int32_
   return GNMPC_OK;
 }
 
+static void destroy_timers(gnmpc_plan* p) {
+  for (int ph = 0; ph < GNMPC_PH_COUNT; ++ph) {
+    for (hipEvent_t e : p->ev_start[ph]) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_stop[ph]) (void)hipEventDestroy(e);
+    p->ev_start[ph].clear();
+    p->ev_stop[ph].clear();
+    p->ev_used[ph] = 0;
+    p->ev_open[ph] = 0;
+  }
+  p->timers_on = false;
+}
+
+gnmpc_status gnmpc_timers_enable(gnmpc_plan* p, int32_t enable) {
+  if (!p) return GNMPC_INVALID_ARG;
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  destroy_timers(p);
+  if (!enable) return GNMPC_OK;
+  for (int ph = 0; ph < GNMPC_PH_COUNT; ++ph) {
+    p->ev_start[ph].resize(kTimerRecords);
+    p->ev_stop[ph].resize(kTimerRecords);
+    for (int t = 0; t < kTimerRecords; ++t) {
+      GNMPC_HIP_TRY(p, hipEventCreate(&p->ev_start[ph][t]));
+      GNMPC_HIP_TRY(p, hipEventCreate(&p->ev_stop[ph][t]));
+    }
+  }
+  p->timers_on = true;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_timers_read(gnmpc_plan* p, double* total_ms, int32_t* count) {
+  if (!p || !total_ms || !count) return GNMPC_INVALID_ARG;
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  for (int ph = 0; ph < GNMPC_PH_COUNT; ++ph) {
+    double sum = 0.0;
+    for (int t = 0; t < p->ev_used[ph]; ++t) {
+      GNMPC_HIP_TRY(p, hipEventSynchronize(p->ev_stop[ph][t]));
+      float ms = 0.f;
+      GNMPC_HIP_TRY(p, hipEventElapsedTime(&ms, p->ev_start[ph][t], p->ev_stop[ph][t]));
+      sum += ms;
+    }
+    total_ms[ph] = sum;
+    count[ph] = p->ev_used[ph];
+  }
+  return GNMPC_OK;
+}
+
 void gnmpc_plan_destroy(gnmpc_plan* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
+  destroy_timers(p);
   gnn_free(p);
   dfree(p->d_row_ptr);
   dfree(p->d_col);

@@ -278,6 +278,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   const int M = p->M, nu = p->dims.nu, N = p->dims.N;
   T* S = (T*)p->d_S;
   T* G = (T*)p->d_Gx;
+  phase_begin(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
   GNMPC_HIP_TRY(p, hipMemcpyAsync(G, x0, sizeof(T) * M * NBX, hipMemcpyDeviceToDevice, s));
   const int wmax = p->wmax;
   for (int k = 0; k < N; ++k) {
@@ -292,15 +293,21 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
         (const T*)B + (size_t)k * M * NBX * nu, (const T*)c + (size_t)k * M * NBX, S_in,
         S + S_offset(k + 1, M, nu), G + (size_t)k * M * NBX, G + (size_t)(k + 1) * M * NBX, wmax);
   }
+  phase_end(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
   GramShape sh = gram_shape(M, nu, N);
   dim3 grid(sh.ntiles + sh.nt, N, sh.nchunks);
+  phase_begin(p, GNMPC_PH_CONDENSE_GRAM, s);
   gram_kernel<T><<<grid, kGramThreads, 0, s>>>(sh, S, G, (const T*)Q, Q_full, (const T*)q, (T*)p->d_part);
   long nred = (long)sh.n * (sh.n + 1) / 2 + sh.n;
   gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, (const T*)p->d_part, (const T*)R, (const T*)r,
                                                             (T*)H, (T*)g);
-  if (p->n_c > 0)
+  phase_end(p, GNMPC_PH_CONDENSE_GRAM, s);
+  if (p->n_c > 0) {
+    phase_begin(p, GNMPC_PH_CONDENSE_ROWS, s);
     cons_kernel<T><<<p->n_c, 256, 0, s>>>(M, nu, N, p->d_row_node, p->d_row_stage, (const T*)rowC,
                                            (const T*)rowd, S, G, (T*)Ct, (T*)dt);
+    phase_end(p, GNMPC_PH_CONDENSE_ROWS, s);
+  }
   if (Gx)
     GNMPC_HIP_TRY(p, hipMemcpyAsync(Gx, G, sizeof(T) * (size_t)(N + 1) * M * NBX, hipMemcpyDeviceToDevice, s));
   GNMPC_HIP_TRY(p, hipGetLastError());

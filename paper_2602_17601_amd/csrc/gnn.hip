@@ -642,10 +642,12 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   fa.mask_node = g.mask_node;
   fa.mask_edge = g.mask_edge;
   fa.fnext = g.fnext;
+  phase_begin(p, GNMPC_PH_GNN_FORWARD, s);
   fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
   const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;
   for (int l = 0; l < g.L; ++l) fwd_layer_kernel<<<N * M, Hd, lds_fwd, s>>>(fa, l);
   fwd_dec_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa);
+  phase_end(p, GNMPC_PH_GNN_FORWARD, s);
   const long nB = (long)N * M * NBX * p->dims.nu;
   fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
   JvpArgs ja;
@@ -684,6 +686,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   ja.B = (float*)B;
   ja.nnz = p->nnz;
   dim3 grid(g.n_tiles, N);
+  phase_begin(p, GNMPC_PH_GNN_JACOBIAN, s);
   if (fa.bf16) {
     GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<uint16_t>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
@@ -693,10 +696,13 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
     jvp_valu_kernel<float><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);
   }
+  phase_end(p, GNMPC_PH_GNN_JACOBIAN, s);
+  phase_begin(p, GNMPC_PH_GNN_ASSEMBLY, s);
   gnn_offset_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(N, M, p->dims.nu, p->nnz, p->d_prow, p->d_pcol,
                                                                (const float*)xhat, (const float*)uhat,
                                                                (const float*)A, (const float*)B, g.fnext,
                                                                (float*)c, (float*)fnext);
+  phase_end(p, GNMPC_PH_GNN_ASSEMBLY, s);
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
 }

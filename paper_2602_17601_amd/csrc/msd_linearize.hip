@@ -247,12 +247,14 @@ gnmpc_status run(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, voi
   a.grav = (T)p->msd.gravity;
   a.anchor = p->msd.anchor;
   long nA = (long)a.N * a.nnz;
+  phase_begin(p, GNMPC_PH_MSD_LINEARIZE, s);
   msd_A_kernel<T><<<ceil_div(nA, kTile), kTile, 0, s>>>(a, (T*)A);
   long nB = (long)a.N * a.M * NBX * a.nu;
   int gB = (int)std::min<long>(ceil_div(nB, 256), 8192);
   msd_B_kernel<T><<<gB, 256, 0, s>>>(a, (T*)B);
   long nc = (long)a.N * a.M;
   msd_c_kernel<T><<<ceil_div(nc, kTile), kTile, 0, s>>>(a, (T*)c, (T*)fnext);
+  phase_end(p, GNMPC_PH_MSD_LINEARIZE, s);
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
 }

@@ -46,9 +46,30 @@ struct gnmpc_plan {
   void* d_qp = nullptr;
   size_t qp_bytes = 0;
   int32_t* d_qp_flag = nullptr;
+
+  // per-phase timers
+  bool timers_on = false;
+  std::vector<hipEvent_t> ev_start[GNMPC_PH_COUNT], ev_stop[GNMPC_PH_COUNT];
+  int ev_used[GNMPC_PH_COUNT] = {0};
+  int ev_open[GNMPC_PH_COUNT] = {0};
 };
 
 namespace gnmpc {
+
+constexpr int kTimerRecords = 1024;
+
+// Record the start / end of a phase on stream s when timers are enabled.
+inline void phase_begin(gnmpc_plan* p, int ph, hipStream_t s) {
+  if (!p->timers_on || p->ev_used[ph] >= kTimerRecords) return;
+  (void)hipEventRecord(p->ev_start[ph][p->ev_used[ph]], s);
+  p->ev_open[ph] = 1;
+}
+inline void phase_end(gnmpc_plan* p, int ph, hipStream_t s) {
+  if (!p->timers_on || !p->ev_open[ph]) return;
+  (void)hipEventRecord(p->ev_stop[ph][p->ev_used[ph]], s);
+  p->ev_open[ph] = 0;
+  ++p->ev_used[ph];
+}
 
 __host__ __device__ inline size_t S_offset(int k, int M, int nu) {  // element offset of S_k (k >= 1)
   return (size_t)NBX * M * nu * ((size_t)k * (k - 1) / 2);

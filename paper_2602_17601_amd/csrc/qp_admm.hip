@@ -624,6 +624,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.max_iter = st->max_iter;
   a.check_every = st->check_every;
   long nlow = (long)n * (n + 1) / 2;
+  phase_begin(p, GNMPC_PH_QP, s);
   qp_gram_kernel<Tin><<<ceil_div(nlow, 256), 256, 0, s>>>(a, (double*)ws);
   gnmpc_status rc;
   if (sizeof(Tin) == 8) {
@@ -632,6 +633,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
     rc = launch_pass<float, Tin>(p, a, 0, s);
     if (rc == GNMPC_OK) rc = launch_pass<double, Tin>(p, a, 1, s);
   }
+  phase_end(p, GNMPC_PH_QP, s);
   if (rc != GNMPC_OK) return rc;
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;

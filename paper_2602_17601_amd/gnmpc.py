@@ -18,6 +18,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgnmpc.s
 OK, INVALID_ARG, BAD_GRAPH, SHAPE, UNSUPPORTED, HIP_ERROR, BAD_CONSTRAINT, NOT_READY, NO_DEVICE = range(9)
 F64, F32, BF16 = 0, 1, 2
 QP_SOLVED, QP_MAXITER, QP_PRIMAL_INFEASIBLE, QP_NONFINITE, QP_NOT_PD = range(5)
+PHASES = ("gnn_forward", "gnn_jacobian", "gnn_assembly", "msd_linearize", "condense_propagate",
+          "condense_gram", "condense_rows", "qp")
 
 
 class GnmpcError(RuntimeError):
@@ -84,6 +86,8 @@ def lib():
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
+            "gnmpc_timers_enable": ([vp, i32], i32),
+            "gnmpc_timers_read": ([vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -261,6 +265,22 @@ class Plan:
                 C.byref(st), self._dev(u, (n,), "u"),
                 self._dev(info, (QP_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)]
         self._check(lib().gnmpc_solve_box_qp(self._h, n, *args, _stream(stream)), "solve_box_qp")
+
+
+def _timers_enable(self, on=True):
+    self._check(lib().gnmpc_timers_enable(self._h, 1 if on else 0), "timers_enable")
+
+
+def _timers_read(self):
+    """{phase: (total_ms, count)} for the records since timers were enabled (synchronizes)."""
+    tot = np.zeros(len(PHASES), np.float64)
+    cnt = np.zeros(len(PHASES), np.int32)
+    self._check(lib().gnmpc_timers_read(self._h, _hp(tot), _hp(cnt)), "timers_read")
+    return {name: (float(tot[i]), int(cnt[i])) for i, name in enumerate(PHASES)}
+
+
+Plan.timers_enable = _timers_enable
+Plan.timers_read = _timers_read
 
 
 def qp_info(t):
