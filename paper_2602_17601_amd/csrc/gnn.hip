@@ -47,6 +47,20 @@ struct GnnState {
   int32_t *meta = nullptr, *seed = nullptr, *seedcol = nullptr, *seedact = nullptr;
   int32_t *V = nullptr, *Vself = nullptr, *Vebeg = nullptr, *Vecnt = nullptr;
   int32_t *Eloc = nullptr, *Eid = nullptr, *out3 = nullptr, *bout2 = nullptr;
+  // MFMA Jacobian path (BF16): weights as bf16 row-major (out, in), sender lists
+  bool mfma = false;
+  int cap1 = 0, cap2 = 0;
+  size_t mfma_lds = 0;
+  uint16_t *Wa16 = nullptr, *Wb16 = nullptr, *Wn1_16 = nullptr, *Wn2_16 = nullptr;  // [L][Hd][Hd]
+  int32_t *prog = nullptr, *elist = nullptr;
+  int stage_cap = 0;
+  // matrix-core forward pass (BF16): hidden states as bf16, node column tiles
+  uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
+  int n_ftiles = 0, fedge_cap = 0;
+  int32_t *fcols = nullptr;       // [n_ftiles][16] node of each column (-1 = empty)
+  int32_t *fmeta = nullptr;       // [n_ftiles][4]: targets, edge begin, edge count, -
+  int32_t *fecnt = nullptr;       // [n_ftiles][16] in-edges of each target column
+  int32_t *fesrc = nullptr, *feid = nullptr;  // per edge: source column, CSR edge id
   std::vector<void*> allocs;
 };
 
@@ -350,6 +364,484 @@ __global__ void jvp_valu_kernel(JvpArgs a) {
   (void)sc;
 }
 
+
+// ---------------------------------------------------------------------------
+// Seed-centric forward-mode Jacobian on the matrix cores (BF16 operands, FP32
+// accumulation): v_mfma_f32_16x16x32_bf16.  Workgroup (tile, stage) of 4
+// waves; wave w owns the output features [w Hd/4, (w+1) Hd/4) of every GEMM,
+// so the 16 tangent columns are the MFMA N dimension and the nodes of a round
+// are processed one after another.
+//   R1: tangents of round l-1, bf16 [node][col][Hd+8]    (MFMA B operands)
+//   R2: edge aggregates of round l, fp32 [node][col][Hd+4]
+// Round l: for every node p of round l-1, Yb = W_b dh_p and P = W_a dh_p + Yb
+// (8 MFMA per 16x16 output tile); P enters p's own aggregate once per in-edge
+// whose ReLU is on (a per-feature count), and -Yb enters the aggregate of each
+// receiver r of p under the mask of edge (r <- p).  Then per node q of round l:
+// dh_q = mask_q (W_n1 dh_q + W_n2 bf16(agg_q)).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+struct MfmaArgs {
+  int N, M, E, L, nu, meta_stride, cap1, cap2;
+  float dt;
+  const float *encT, *decT;
+  const uint16_t *Wa, *Wb, *Wn1, *Wn2;
+  const uint32_t *mask_enc, *mask_node, *mask_edge;
+  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *prog, *elist, *out3, *bout2;
+  float *A, *B;
+  long nnz;
+};
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return (__float_as_uint(bf16r(lo)) >> 16) | (__float_as_uint(bf16r(hi)) & 0xFFFF0000u);
+}
+
+// LDS columns are XOR-swizzled in 16-byte chunks by (column & 7), so the 16
+// lanes that read one k-slice of 16 different columns hit different banks.
+__device__ inline int swz(int byte_in_col, int c) { return (((byte_in_col >> 4) ^ (c & 7)) << 4) | (byte_in_col & 15); }
+
+template <int MT>
+__global__ void __launch_bounds__(256) jvp_mfma_kernel(MfmaArgs a) {
+  constexpr int Hd = MT * 64;
+  constexpr int KB = Hd / 32;  // 32-deep k-blocks
+  constexpr int RW = Hd / 4;   // features per wave
+  constexpr int MAXV = 16;     // nodes per round held as output registers
+  constexpr int HW = Hd / 32;  // mask words per node or edge
+  constexpr int CB1 = Hd * 2;  // bytes per bf16 tangent column
+  constexpr int CB2 = Hd * 4;  // bytes per fp32 aggregate column
+  extern __shared__ unsigned char smem_raw[];
+  unsigned char* R1 = smem_raw;                                            // [cap1][16] bf16 columns
+  unsigned char* R2 = smem_raw + (size_t)a.cap1 * kCols * CB1;            // [cap2][16] fp32 columns
+  int32_t* SP = reinterpret_cast<int32_t*>(R2 + (size_t)a.cap2 * kCols * CB2);  // staged program + masks
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
+  const int sb = mt[0], ob = mt[2], oc = mt[3], bb = mt[4], bc = mt[5];
+
+  // ---- round 0: encoder tangents of the seeds (mask x weight, exact in bf16)
+  {
+    const int vb = mt[6], vc = mt[7];
+    for (int t = threadIdx.x; t < vc * kCols * Hd; t += 256) {
+      const int q = t / (kCols * Hd), c = (t / Hd) % kCols, f = t % Hd;
+      const int node = a.V[vb + q];
+      const int p = a.Vself[vb + q];
+      const int d = c - a.seedcol[sb + p];
+      const bool act = a.seedact[sb + p] >= 0;
+      float v = 0.f;
+      if (d >= 0 && (d < 6 || (act && d < 9)) && mbit(a.mask_enc + ((size_t)k * a.M + node) * HW, f))
+        v = a.encT[d * Hd + f];
+      *reinterpret_cast<uint16_t*>(R1 + ((size_t)q * kCols + c) * CB1 + swz(2 * f, c)) =
+          (uint16_t)(__float_as_uint(v) >> 16);
+    }
+  }
+
+  for (int l = 1; l <= a.L; ++l) {
+    const int vc0 = mt[7 + 2 * (l - 1)];
+    const int vb1 = mt[6 + 2 * l], vc1 = mt[7 + 2 * l];
+    const int* pm = mt + 6 + 2 * (a.L + 1) + 4 * (l - 1);
+    const int pbeg = pm[0], plen = pm[1], ebeg = pm[2], elen = pm[3];
+    const size_t woff = (size_t)(l - 1) * Hd * Hd;
+    // stage this round's sender program, the edge masks it reads and the node masks
+    const int plen4 = (plen + 3) / 4 * 4;
+    uint32_t* SM = reinterpret_cast<uint32_t*>(SP + plen4);   // [elen][HW]
+    uint32_t* SN = SM + elen * HW;                             // [vc1][HW]
+    {
+      for (int t = threadIdx.x; t < plen; t += 256) SP[t] = a.prog[pbeg + t];
+      const uint32_t* me = a.mask_edge + ((size_t)(l - 1) * a.N + k) * a.E * HW;
+      for (int t = threadIdx.x; t < elen * HW; t += 256) SM[t] = me[(size_t)a.elist[ebeg + t / HW] * HW + t % HW];
+      const uint32_t* mn = a.mask_node + ((size_t)(l - 1) * a.N + k) * a.M * HW;
+      for (int t = threadIdx.x; t < vc1 * HW; t += 256) SN[t] = mn[(size_t)a.V[vb1 + t / HW] * HW + t % HW];
+      for (int t = threadIdx.x; t < vc1 * kCols * CB2 / 16; t += 256)
+        reinterpret_cast<uint4*>(R2)[t] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    // ---- phase A: edge GEMMs per sender, masked scatter into the fp32 aggregates
+    {
+      bf16x8_t wa[MT][KB], wb[MT][KB];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int row = wave * RW + 16 * m + col;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          wa[m][kb] = *reinterpret_cast<const bf16x8_t*>(a.Wa + woff + (size_t)row * Hd + kb * 32 + grp * 8);
+          wb[m][kb] = *reinterpret_cast<const bf16x8_t*>(a.Wb + woff + (size_t)row * Hd + kb * 32 + grp * 8);
+        }
+      }
+      int po = 0, mo = 0;
+      for (int p = 0; p < vc0; ++p) {
+        const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB1;
+        bf16x8_t bfr[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+          bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swz(64 * kb + 16 * grp, col));
+        floatx4_t ay[MT], ap[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          ay[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) ay[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[m][kb], bfr[kb], ay[m], 0, 0, 0);
+          ap[m] = ay[m];
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) ap[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[m][kb], bfr[kb], ap[m], 0, 0, 0);
+        }
+        const int qp = SP[po], nin = SP[po + 1], nout = SP[po + 2];
+        po += 3;
+        // receiver term: P times the number of in-edges whose ReLU is on, per feature
+        float cnt[MT][4];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cnt[m][i] = 0.f;
+        for (int e = 0; e < nin; ++e) {
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            const int f0 = wave * RW + 16 * m + 4 * grp;
+            const uint32_t bits = SM[mo + e * HW + (f0 >> 5)] >> (f0 & 31);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cnt[m][i] += (float)((bits >> i) & 1u);
+          }
+        }
+        mo += nin * HW;
+        {
+          unsigned char* dq = R2 + ((size_t)qp * kCols + col) * CB2;
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            const int f0 = wave * RW + 16 * m + 4 * grp;
+            floatx4_t* ptr = reinterpret_cast<floatx4_t*>(dq + swz(4 * f0, col));
+            floatx4_t v = *ptr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] += cnt[m][i] * ap[m][i];
+            *ptr = v;
+          }
+        }
+        // sender term: -mask (r <- p) * Yb into each receiver's aggregate
+        for (int t = 0; t < nout; ++t) {
+          unsigned char* dr = R2 + ((size_t)SP[po + t] * kCols + col) * CB2;
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            const int f0 = wave * RW + 16 * m + 4 * grp;
+            const uint32_t bits = SM[mo + t * HW + (f0 >> 5)] >> (f0 & 31);
+            floatx4_t* ptr = reinterpret_cast<floatx4_t*>(dr + swz(4 * f0, col));
+            floatx4_t v = *ptr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] -= ((bits >> i) & 1u) ? ay[m][i] : 0.f;
+            *ptr = v;
+          }
+        }
+        po += nout;
+        mo += nout * HW;
+      }
+    }
+    __syncthreads();
+    // ---- phase B: node GEMMs, outputs held in registers until every wave is done reading
+    floatx4_t outv[MAXV][MT];
+    {
+      bf16x8_t w1[MT][KB], w2[MT][KB];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int row = wave * RW + 16 * m + col;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          w1[m][kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + woff + (size_t)row * Hd + kb * 32 + grp * 8);
+          w2[m][kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + woff + (size_t)row * Hd + kb * 32 + grp * 8);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < MAXV; ++q) {
+        if (q < vc1) {
+          floatx4_t acc[MT];
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+          const int self = a.Vself[vb1 + q];
+          if (self >= 0) {
+            const unsigned char* Ts = R1 + ((size_t)self * kCols + col) * CB1;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+              bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(Ts + swz(64 * kb + 16 * grp, col));
+#pragma unroll
+              for (int m = 0; m < MT; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m][kb], bfr, acc[m], 0, 0, 0);
+            }
+          }
+          const unsigned char* Gq = R2 + ((size_t)q * kCols + col) * CB2;
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const int byte = 4 * (kb * 32 + grp * 8);
+            floatx4_t lo = *reinterpret_cast<const floatx4_t*>(Gq + swz(byte, col));
+            floatx4_t hi = *reinterpret_cast<const floatx4_t*>(Gq + swz(byte + 16, col));
+            uint4 pk;
+            pk.x = pack_bf16x2(lo[0], lo[1]);
+            pk.y = pack_bf16x2(lo[2], lo[3]);
+            pk.z = pack_bf16x2(hi[0], hi[1]);
+            pk.w = pack_bf16x2(hi[2], hi[3]);
+            bf16x8_t bfr = __builtin_bit_cast(bf16x8_t, pk);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bfr, acc[m], 0, 0, 0);
+          }
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            const int f0 = wave * RW + 16 * m + 4 * grp;
+            const uint32_t bits = SN[q * HW + (f0 >> 5)] >> (f0 & 31);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) outv[q][m][i] = ((bits >> i) & 1u) ? acc[m][i] : 0.f;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    unsigned char* dst = (l < a.L) ? R1 : R2;  // the last round's tangents go where the aggregates were
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+      if (q < vc1) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int f0 = wave * RW + 16 * m + 4 * grp;
+          uint2 v;
+          v.x = pack_bf16x2(outv[q][m][0], outv[q][m][1]);
+          v.y = pack_bf16x2(outv[q][m][2], outv[q][m][3]);
+          *reinterpret_cast<uint2*>(dst + ((size_t)q * kCols + col) * CB1 + swz(2 * f0, col)) = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- decoder (3 used rows) and the Jacobian blocks
+  const int vbL = mt[6 + 2 * a.L];
+  for (int t = threadIdx.x; t < oc * 18; t += 256) {
+    const int o = t / 18, rem = t % 18, r = rem / 6, d = rem % 6;
+    const int q = a.out3[3 * (ob + o)], p = a.out3[3 * (ob + o) + 1];
+    const long e = a.out3[3 * (ob + o) + 2];
+    const int node = a.V[vbL + q];
+    const int cc = a.seedcol[sb + p] + d;
+    const unsigned char* tq = R2 + ((size_t)q * kCols + cc) * CB1;
+    float dov = 0.f;
+    for (int f = 0; f < Hd; ++f)
+      dov += a.decT[f * 6 + 3 + r] *
+             __uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t*>(tq + swz(2 * f, cc))) << 16);
+    const bool diag = node == a.seed[sb + p];
+    const float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
+    const float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
+    float* blk = a.A + ((size_t)k * a.nnz + e) * 36;
+    blk[r * 6 + d] = dp;
+    blk[(3 + r) * 6 + d] = dv;
+  }
+  for (int t = threadIdx.x; t < bc * 9; t += 256) {
+    const int o = t / 9, rem = t % 9, r = rem / 3, d = rem % 3;
+    const int q = a.bout2[2 * (bb + o)], p = a.bout2[2 * (bb + o) + 1];
+    const int node = a.V[vbL + q];
+    const int act = a.seedact[sb + p];
+    const int cc = a.seedcol[sb + p] + 6 + d;
+    const unsigned char* tq = R2 + ((size_t)q * kCols + cc) * CB1;
+    float dov = 0.f;
+    for (int f = 0; f < Hd; ++f)
+      dov += a.decT[f * 6 + 3 + r] *
+             __uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t*>(tq + swz(2 * f, cc))) << 16);
+    const float dv = a.dt * dov;
+    float* Bi = a.B + (((size_t)k * a.M + node) * NBX) * a.nu;
+    Bi[(3 + r) * a.nu + 3 * act + d] = dv;
+    Bi[r * a.nu + 3 * act + d] = a.dt * dv;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Forward pass on the matrix cores (BF16 operands, FP32 accumulation).  One
+// workgroup per (column tile, stage): a tile is 16 node columns -- the target
+// nodes whose next hidden state it produces plus the senders of their edges --
+// so each round is two 16-column GEMMs per tile: [W_a; W_b] h (edge terms) and
+// [W_n1 W_n2] [h; agg] (node update).  ReLU masks leave as 4-bit groups staged
+// in LDS bytes and packed into the same bit layout as the VALU path.
+__global__ void fwd_enc_bf16_kernel(FwdArgs a, uint16_t* h0) {
+  const int s = blockIdx.x;
+  const int k = s / a.M, i = s - k * a.M;
+  const int f = threadIdx.x;
+  float in[9];
+  const float* x = a.xhat + (size_t)s * NBX;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) in[d] = x[d];
+  const int act = a.act_of_node[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) in[6 + d] = act >= 0 ? a.uhat[(size_t)k * a.nu + 3 * act + d] : 0.f;
+  float z = a.benc[f];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) z += a.encT[d * a.Hd + f] * bf16r(in[d]);
+  const bool on = z > 0.f;
+  h0[(size_t)s * a.Hd + f] = (uint16_t)(__float_as_uint(bf16r(on ? z : 0.f)) >> 16);
+  store_mask(a.mask_enc + (size_t)s * (a.Hd / 32), f, on);
+}
+
+__global__ void fwd_dec_bf16_kernel(FwdArgs a, const uint16_t* hL) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.N * a.M) return;
+  const uint16_t* h = hL + (size_t)s * a.Hd;
+  float o[3] = {a.bdec[3], a.bdec[4], a.bdec[5]};
+  for (int q = 0; q < a.Hd; ++q) {
+    const float hv = __uint_as_float((uint32_t)h[q] << 16);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) o[r] += a.decT[q * 6 + 3 + r] * hv;
+  }
+  const float* x = a.xhat + (size_t)s * NBX;
+  float* fo = a.fnext + (size_t)s * NBX;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float vn = x[3 + r] + a.dt * o[r];
+    fo[3 + r] = vn;
+    fo[r] = x[r] + a.dt * vn;
+  }
+}
+
+struct FwdMfmaArgs {
+  int N, M, E, l, fedge_cap;
+  const uint16_t *hin;
+  uint16_t* hout;
+  const uint16_t *Wa, *Wb, *Wn1, *Wn2;  // this round's weights, bf16 row-major (out, in)
+  const float *be, *bn;                 // this round's biases
+  uint32_t *mask_edge, *mask_node;      // this round, all stages
+  const int32_t *fcols, *fmeta, *fecnt, *fesrc, *feid;
+};
+
+template <int MT>
+__global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
+  constexpr int Hd = MT * 64, KB = Hd / 32, RW = Hd / 4, CB = Hd * 2, HW = Hd / 32, NQ = Hd / 4;
+  __shared__ __attribute__((aligned(16))) unsigned char Hs[16 * CB];   // layer input, bf16 columns
+  __shared__ __attribute__((aligned(16))) unsigned char Ag[16 * CB];   // aggregates, bf16 columns
+  __shared__ __attribute__((aligned(16))) float Ybs[16 * Hd];          // W_b h per column, fp32
+  extern __shared__ unsigned char qmask[];                            // [edges + 16][NQ] 4-bit groups
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const int32_t* fm = a.fmeta + (size_t)tile * 4;
+  const int nt = fm[0], eb = fm[1], ec = fm[2];
+  const int32_t* cols = a.fcols + (size_t)tile * 16;
+  // ---- gather the 16 input columns
+  for (int t = threadIdx.x; t < 16 * CB / 16; t += 256) {
+    const int c = t / (CB / 16), ch = t % (CB / 16);
+    const int node = cols[c];
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (node >= 0) v = reinterpret_cast<const uint4*>(a.hin + ((size_t)k * a.M + node) * Hd)[ch];
+    *reinterpret_cast<uint4*>(Hs + c * CB + swz(16 * ch, c)) = v;
+  }
+  __syncthreads();
+  // ---- edge GEMMs: Yb = W_b h, P = W_a h + Yb
+  floatx4_t ap[MT], ay[MT];
+  {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      ap[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      ay[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(Hs + col * CB + swz(64 * kb + 16 * grp, col));
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int row = wave * RW + 16 * m + col;
+        const bf16x8_t wa = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)row * Hd + kb * 32 + grp * 8);
+        const bf16x8_t wb = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)row * Hd + kb * 32 + grp * 8);
+        ay[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, bfr, ay[m], 0, 0, 0);
+        ap[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, bfr, ap[m], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int f0 = wave * RW + 16 * m + 4 * grp;
+      *reinterpret_cast<floatx4_t*>(Ybs + col * Hd + f0) = ay[m];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ap[m][i] += ay[m][i] + a.be[f0 + i];
+    }
+  }
+  __syncthreads();
+  // ---- edge terms of the target columns: agg = sum_j relu(P_i - Yb_j)
+  {
+    int e0 = 0;
+    for (int c = 0; c < col; ++c) e0 += a.fecnt[(size_t)tile * 16 + c];
+    const int ne = col < nt ? a.fecnt[(size_t)tile * 16 + col] : 0;
+    float agg[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) agg[m][i] = 0.f;
+    for (int t = 0; t < ne; ++t) {
+      const int sc = a.fesrc[eb + e0 + t];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int f0 = wave * RW + 16 * m + 4 * grp;
+        const floatx4_t yb = *reinterpret_cast<const floatx4_t*>(Ybs + sc * Hd + f0);
+        uint32_t nib = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float z = ap[m][i] - yb[i];
+          const bool on = z > 0.f;
+          agg[m][i] += on ? z : 0.f;
+          nib |= (on ? 1u : 0u) << i;
+        }
+        qmask[(size_t)(e0 + t) * NQ + f0 / 4] = (unsigned char)nib;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int f0 = wave * RW + 16 * m + 4 * grp;
+      uint2 v;
+      v.x = pack_bf16x2(agg[m][0], agg[m][1]);
+      v.y = pack_bf16x2(agg[m][2], agg[m][3]);
+      *reinterpret_cast<uint2*>(Ag + col * CB + swz(2 * f0, col)) = v;
+    }
+  }
+  __syncthreads();
+  // ---- node update: h' = relu(W_n1 h + W_n2 agg + b_n)
+  {
+    floatx4_t acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(Hs + col * CB + swz(64 * kb + 16 * grp, col));
+      const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Ag + col * CB + swz(64 * kb + 16 * grp, col));
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int row = wave * RW + 16 * m + col;
+        const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + (size_t)row * Hd + kb * 32 + grp * 8);
+        const bf16x8_t w2 = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + (size_t)row * Hd + kb * 32 + grp * 8);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, bh, acc[m], 0, 0, 0);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2, bg, acc[m], 0, 0, 0);
+      }
+    }
+    if (col < nt) {
+      const int node = cols[col];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int f0 = wave * RW + 16 * m + 4 * grp;
+        float hv[4];
+        uint32_t nib = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float z = acc[m][i] + a.bn[f0 + i];
+          const bool on = z > 0.f;
+          hv[i] = on ? z : 0.f;
+          nib |= (on ? 1u : 0u) << i;
+        }
+        uint2 v;
+        v.x = pack_bf16x2(hv[0], hv[1]);
+        v.y = pack_bf16x2(hv[2], hv[3]);
+        *reinterpret_cast<uint2*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = v;
+        qmask[(size_t)(a.fedge_cap + col) * NQ + f0 / 4] = (unsigned char)nib;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- pack the staged 4-bit groups into mask words
+  for (int t = threadIdx.x; t < (ec + nt) * HW; t += 256) {
+    const int r = t / HW, wd = t % HW;
+    const int srow = r < ec ? r : a.fedge_cap + (r - ec);
+    uint32_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) word |= (uint32_t)(qmask[(size_t)srow * NQ + wd * 8 + q] & 0xF) << (4 * q);
+    if (r < ec) a.mask_edge[((size_t)k * a.E + a.feid[eb + r]) * HW + wd] = word;
+    else a.mask_node[((size_t)k * a.M + cols[r - ec]) * HW + wd] = word;
+  }
+}
+
 __global__ void fill_zero_kernel(float* p, long n) {
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = 0.f;
 }
@@ -401,7 +893,12 @@ gnmpc_status dupload(gnmpc_plan* p, T*& ptr, const std::vector<T>& v) {
 // Seed tiles and their per-round node lists (host).
 struct TilePlan {
   std::vector<int32_t> meta, seed, seedcol, seedact, V, Vself, Vebeg, Vecnt, Eloc, Eid, out3, bout2;
-  int bufX = 0, bufY = 0, n_tiles = 0;
+  // per entry of V (round l < L): its index in round l+1 and its out-edges (r <- node) with r's
+  // index in round l+1 and the CSR id of the edge in r's row
+  // per (tile, round l >= 1): the sender program {qp, n_in, n_out, qr...} of every node of
+  // round l-1 and the CSR ids of the edges whose masks it reads (in-edges, then out-edges)
+  std::vector<int32_t> prog, elist;
+  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0;
 };
 
 void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
@@ -411,7 +908,8 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
     for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) outn[p->h_col[e]].push_back(i);
   std::vector<int32_t> act_of(M, -1);
   for (int a = 0; a < (int)p->h_act.size(); ++a) act_of[p->h_act[a]] = a;
-  const int stride = 6 + 2 * (L + 1);
+  const int stride = 6 + 2 * (L + 1) + 4 * L;
+  const int HW = p->gnn ? p->gnn->Hd / 32 : 4;
   std::vector<int32_t> where(M, -1);
   int i = 0;
   while (i < M) {
@@ -446,6 +944,9 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
     for (int l = 0; l <= L; ++l) {
       m[6 + 2 * l] = (int32_t)tp.V.size();
       m[7 + 2 * l] = (int32_t)Vl[l].size();
+      if (l < L) tp.cap1 = std::max(tp.cap1, (int)Vl[l].size());
+      if (l > 0) tp.cap2 = std::max(tp.cap2, (int)Vl[l].size());
+
       if (l % 2 == 0) tp.bufX = std::max(tp.bufX, (int)Vl[l].size());
       else tp.bufY = std::max(tp.bufY, (int)Vl[l].size());
       if (l > 0) {
@@ -480,6 +981,32 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
       }
       if (l > 0)
         for (int32_t n : Vl[l - 1]) where[n] = -1;
+    }
+    // sender programs for the matrix-core kernel
+    for (int l = 1; l <= L; ++l) {
+      const std::vector<int32_t>& prv = Vl[l - 1];
+      const std::vector<int32_t>& nx = Vl[l];
+      const int pb = (int32_t)tp.prog.size(), eb = (int32_t)tp.elist.size();
+      for (int32_t node : prv) {
+        tp.prog.push_back((int32_t)(std::lower_bound(nx.begin(), nx.end(), node) - nx.begin()));
+        const int nin = p->h_row_ptr[node + 1] - p->h_row_ptr[node];
+        tp.prog.push_back(nin);
+        tp.prog.push_back((int32_t)outn[node].size());
+        for (int e = p->h_row_ptr[node]; e < p->h_row_ptr[node + 1]; ++e) tp.elist.push_back(e);
+        for (int32_t r : outn[node]) {
+          tp.prog.push_back((int32_t)(std::lower_bound(nx.begin(), nx.end(), r) - nx.begin()));
+          const int32_t* rb = p->h_col.data() + p->h_row_ptr[r];
+          const int32_t* re = p->h_col.data() + p->h_row_ptr[r + 1];
+          tp.elist.push_back((int32_t)(std::lower_bound(rb, re, node) - p->h_col.data()));
+        }
+      }
+      const int base = 6 + 2 * (L + 1) + 4 * (l - 1);
+      m[base] = pb;
+      m[base + 1] = (int32_t)tp.prog.size() - pb;
+      m[base + 2] = eb;
+      m[base + 3] = (int32_t)tp.elist.size() - eb;
+      const int words = (m[base + 1] + 3) / 4 * 4 + m[base + 3] * HW + (int)nx.size() * HW;
+      tp.stage_cap = std::max(tp.stage_cap, words);
     }
     // output blocks: (node of the last round, seed) pairs inside the pattern
     m[2] = (int32_t)(tp.out3.size() / 3);
@@ -599,9 +1126,87 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     return GNMPC_UNSUPPORTED;
   }
   g.n_tiles = tp.n_tiles;
-  g.meta_stride = 6 + 2 * (L + 1);
+  g.meta_stride = 6 + 2 * (L + 1) + 4 * L;
   g.bufX = tp.bufX;
   g.bufY = tp.bufY;
+  // The matrix-core path needs BF16, a supported width and the round buffers in LDS.
+  g.cap1 = tp.cap1;
+  g.cap2 = tp.cap2;
+  g.stage_cap = tp.stage_cap;
+  g.mfma_lds = (size_t)tp.cap1 * kCols * Hd * 2 + (size_t)tp.cap2 * kCols * Hd * 4 + (size_t)tp.stage_cap * 4;
+  g.mfma = bf && (Hd == 64 || Hd == 128 || Hd == 256) && tp.cap2 <= 16 && g.mfma_lds <= 160 * 1024;
+  if (g.mfma) {
+    std::vector<uint16_t> wa16((size_t)L * Hd * Hd), wb16(wa16.size()), w1_16(wa16.size()), w2_16(wa16.size());
+    auto b16 = [](float v) {
+      uint32_t u;
+      std::memcpy(&u, &v, 4);
+      return (uint16_t)(u >> 16);  // values are already bf16-representable
+    };
+    for (int l = 0; l < L; ++l)
+      for (int f = 0; f < Hd; ++f)
+        for (int q = 0; q < Hd; ++q) {
+          const size_t src = ((size_t)l * Hd + q) * Hd + f, dst = ((size_t)l * Hd + f) * Hd + q;
+          wa16[dst] = b16(WaT[src]);
+          wb16[dst] = b16(WbT[src]);
+          w1_16[dst] = b16(Wn1T[src]);
+          w2_16[dst] = b16(Wn2T[src]);
+        }
+    UP(Wa16, wa16) UP(Wb16, wb16) UP(Wn1_16, w1_16) UP(Wn2_16, w2_16)
+    UP(prog, tp.prog) UP(elist, tp.elist)
+    // forward column tiles: greedily add target nodes while targets plus their
+    // senders fit in 16 columns; targets occupy the first columns
+    std::vector<int32_t> fcols, fmeta, fecnt, fesrc, feid;
+    int i = 0;
+    g.fedge_cap = 0;
+    while (i < g.M) {
+      std::vector<int32_t> tg, hal;
+      while (i < g.M) {
+        std::vector<int32_t> cand_t = tg, cand_h = hal;
+        cand_t.push_back(i);
+        for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) cand_h.push_back(p->h_col[e]);
+        std::vector<int32_t> all = cand_h;
+        all.erase(std::remove_if(all.begin(), all.end(),
+                                 [&](int32_t v) { return std::find(cand_t.begin(), cand_t.end(), v) != cand_t.end(); }),
+                  all.end());
+        std::sort(all.begin(), all.end());
+        all.erase(std::unique(all.begin(), all.end()), all.end());
+        if (cand_t.size() + all.size() > 16) break;
+        tg = cand_t;
+        hal = all;
+        ++i;
+      }
+      if (tg.empty()) {
+        p->last_error = "model_set_gnn: a node has more than 15 in-neighbours (forward tiles hold 16 columns)";
+        gnn_free(p);
+        return GNMPC_UNSUPPORTED;
+      }
+      std::vector<int32_t> colv = tg;
+      colv.insert(colv.end(), hal.begin(), hal.end());
+      const int eb = (int)fesrc.size();
+      for (size_t c = 0; c < 16; ++c) {
+        fcols.push_back(c < colv.size() ? colv[c] : -1);
+        if (c < tg.size()) {
+          const int node = tg[c];
+          fecnt.push_back(p->h_row_ptr[node + 1] - p->h_row_ptr[node]);
+          for (int e = p->h_row_ptr[node]; e < p->h_row_ptr[node + 1]; ++e) {
+            fesrc.push_back((int32_t)(std::find(colv.begin(), colv.end(), p->h_col[e]) - colv.begin()));
+            feid.push_back(e);
+          }
+        } else {
+          fecnt.push_back(0);
+        }
+      }
+      const int ec = (int)fesrc.size() - eb;
+      g.fedge_cap = std::max(g.fedge_cap, ec);
+      fmeta.push_back((int32_t)tg.size());
+      fmeta.push_back(eb);
+      fmeta.push_back(ec);
+      fmeta.push_back(0);
+      ++g.n_ftiles;
+    }
+    UP(fcols, fcols) UP(fmeta, fmeta) UP(fecnt, fecnt) UP(fesrc, fesrc) UP(feid, feid)
+    if ((s = dalloc(p, g.h16, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
+  }
   UP(meta, tp.meta) UP(seed, tp.seed) UP(seedcol, tp.seedcol) UP(seedact, tp.seedact) UP(V, tp.V)
   UP(Vself, tp.Vself) UP(Vebeg, tp.Vebeg) UP(Vecnt, tp.Vecnt) UP(Eloc, tp.Eloc) UP(Eid, tp.Eid)
   UP(out3, tp.out3) UP(bout2, tp.bout2)
@@ -643,10 +1248,45 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   fa.mask_edge = g.mask_edge;
   fa.fnext = g.fnext;
   phase_begin(p, GNMPC_PH_GNN_FORWARD, s);
-  fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
-  const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;
-  for (int l = 0; l < g.L; ++l) fwd_layer_kernel<<<N * M, Hd, lds_fwd, s>>>(fa, l);
-  fwd_dec_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa);
+  if (g.mfma) {
+    const size_t NM = (size_t)N * M;
+    fwd_enc_bf16_kernel<<<N * M, Hd, 0, s>>>(fa, g.h16);
+    for (int l = 0; l < g.L; ++l) {
+      FwdMfmaArgs f;
+      f.N = N;
+      f.M = M;
+      f.E = g.E;
+      f.l = l;
+      f.fedge_cap = g.fedge_cap;
+      f.hin = g.h16 + (size_t)l * NM * Hd;
+      f.hout = g.h16 + (size_t)(l + 1) * NM * Hd;
+      const size_t wo = (size_t)l * Hd * Hd;
+      f.Wa = g.Wa16 + wo;
+      f.Wb = g.Wb16 + wo;
+      f.Wn1 = g.Wn1_16 + wo;
+      f.Wn2 = g.Wn2_16 + wo;
+      f.be = g.be + (size_t)l * Hd;
+      f.bn = g.bn + (size_t)l * Hd;
+      f.mask_edge = g.mask_edge + (size_t)l * N * g.E * (Hd / 32);
+      f.mask_node = g.mask_node + (size_t)l * NM * (Hd / 32);
+      f.fcols = g.fcols;
+      f.fmeta = g.fmeta;
+      f.fecnt = g.fecnt;
+      f.fesrc = g.fesrc;
+      f.feid = g.feid;
+      const size_t qbytes = (size_t)(g.fedge_cap + 16) * (Hd / 4);
+      dim3 fg(g.n_ftiles, N);
+      if (Hd == 64) fwd_mfma_layer_kernel<1><<<fg, 256, qbytes, s>>>(f);
+      else if (Hd == 128) fwd_mfma_layer_kernel<2><<<fg, 256, qbytes, s>>>(f);
+      else fwd_mfma_layer_kernel<4><<<fg, 256, qbytes, s>>>(f);
+    }
+    fwd_dec_bf16_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa, g.h16 + (size_t)g.L * NM * Hd);
+  } else {
+    fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
+    const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;
+    for (int l = 0; l < g.L; ++l) fwd_layer_kernel<<<N * M, Hd, lds_fwd, s>>>(fa, l);
+    fwd_dec_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa);
+  }
   phase_end(p, GNMPC_PH_GNN_FORWARD, s);
   const long nB = (long)N * M * NBX * p->dims.nu;
   fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
@@ -687,7 +1327,46 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   ja.nnz = p->nnz;
   dim3 grid(g.n_tiles, N);
   phase_begin(p, GNMPC_PH_GNN_JACOBIAN, s);
-  if (fa.bf16) {
+  if (g.mfma) {
+    MfmaArgs ma;
+    ma.N = N;
+    ma.M = M;
+    ma.E = g.E;
+    ma.L = g.L;
+    ma.nu = p->dims.nu;
+    ma.meta_stride = g.meta_stride;
+    ma.cap1 = g.cap1;
+    ma.cap2 = g.cap2;
+    ma.dt = g.dt;
+    ma.encT = g.encT;
+    ma.decT = g.decT;
+    ma.Wa = g.Wa16;
+    ma.Wb = g.Wb16;
+    ma.Wn1 = g.Wn1_16;
+    ma.Wn2 = g.Wn2_16;
+    ma.mask_enc = g.mask_enc;
+    ma.mask_node = g.mask_node;
+    ma.mask_edge = g.mask_edge;
+    ma.meta = g.meta;
+    ma.seed = g.seed;
+    ma.seedcol = g.seedcol;
+    ma.seedact = g.seedact;
+    ma.V = g.V;
+    ma.Vself = g.Vself;
+    ma.prog = g.prog;
+    ma.elist = g.elist;
+    ma.out3 = g.out3;
+    ma.bout2 = g.bout2;
+    ma.A = (float*)A;
+    ma.B = (float*)B;
+    ma.nnz = p->nnz;
+    const void* kfn = Hd == 64 ? (const void*)jvp_mfma_kernel<1>
+                    : Hd == 128 ? (const void*)jvp_mfma_kernel<2> : (const void*)jvp_mfma_kernel<4>;
+    GNMPC_HIP_TRY(p, hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma_lds));
+    if (Hd == 64) jvp_mfma_kernel<1><<<grid, 256, g.mfma_lds, s>>>(ma);
+    else if (Hd == 128) jvp_mfma_kernel<2><<<grid, 256, g.mfma_lds, s>>>(ma);
+    else jvp_mfma_kernel<4><<<grid, 256, g.mfma_lds, s>>>(ma);
+  } else if (fa.bf16) {
     GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<uint16_t>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
     jvp_valu_kernel<uint16_t><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);

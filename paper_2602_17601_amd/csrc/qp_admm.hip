@@ -24,7 +24,7 @@
 namespace gnmpc {
 namespace {
 
-constexpr int kQpThreads = 1024;
+constexpr int kQpThreads = 512;
 constexpr int kWaves = kQpThreads / 64;
 
 template <typename Tin>
@@ -69,7 +69,17 @@ __global__ void qp_gram_kernel(QpArgs<Tin> a, double* G) {
   G[(size_t)j * n + i] = s;
 }
 
-__device__ inline size_t pk(int i, int j) { return (size_t)i * (i + 1) / 2 + j; }  // packed lower, j <= i
+// K, L and W = L^{-1} are kept as the lower triangle of 16x16 blocks, block
+// (I, J <= I) row-major at bo(I, J); the order is padded to 16 nb with identity.
+constexpr int kBS = 16;
+__host__ __device__ inline int nblocks(int n) { return (n + kBS - 1) / kBS; }
+__host__ __device__ inline size_t bo(int I, int J) { return ((size_t)I * (I + 1) / 2 + J) * (kBS * kBS); }
+// per-wave partial sums of Ct' v, also the staging area of the block inverse
+__host__ __device__ inline size_t part_elems(int n) {
+  const size_t a = (size_t)(kQpThreads / 64) * n, b = (size_t)(nblocks(n) - 1) * kBS * kBS;
+  return a > b ? a : b;
+}
+__device__ inline size_t ep(int i, int j) { return bo(i >> 4, j >> 4) + (i & 15) * kBS + (j & 15); }
 
 template <typename T>
 __device__ inline T wave_sum(T v) {
@@ -118,23 +128,50 @@ struct Work {
   T* scal;  // [8]
 };
 
-// out = W v (W packed lower), 4 lanes per row.
+typedef float qfloatx4 __attribute__((ext_vector_type(4)));
+
+// 16x16 block products in the MFMA C layout (lane l holds rows 4 (l >> 4) + i,
+// column l & 15): acc[i] += (A op(B))[row][col], op(B) = B^T if TRANS else B.
+// FP32 uses v_mfma_f32_16x16x4f32 (4 k-steps); FP64 uses the VALU.
+template <bool TRANS>
+__device__ inline void bmma(float acc[4], const float* A, const float* B) {
+  const int l = threadIdx.x & 63, r = l & 15, kq = l >> 4;
+  qfloatx4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) {
+    const float av = A[r * 16 + kk + kq];
+    const float bv = TRANS ? B[r * 16 + kk + kq] : B[(kk + kq) * 16 + r];
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = c[i];
+}
+template <bool TRANS>
+__device__ inline void bmma(double acc[4], const double* A, const double* B) {
+  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const double bv = TRANS ? B[c * 16 + k] : B[k * 16 + c];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += A[(4 * g + i) * 16 + k] * bv;
+  }
+}
+
+// out = W v over the first n rows, 4 lanes per row.
 template <typename T>
 __device__ void tri_mv(const Work<T>& w, int n, const T* v, T* out) {
   for (int base = 0; base < n; base += kQpThreads / 4) {
     int i = base + threadIdx.x / 4;
     int q = threadIdx.x & 3;
     T s = T(0);
-    if (i < n) {
-      const T* row = w.mat + pk(i, 0);
-      for (int p = q; p <= i; p += 4) s += row[p] * v[p];
-    }
+    if (i < n)
+      for (int j = q; j <= i; j += 4) s += w.mat[ep(i, j)] * v[j];
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (i < n && q == 0) out[i] = s;
   }
 }
-// out = W' v, 4 lanes per output.
+// out = W' v over the first n rows, 4 lanes per output.
 template <typename T>
 __device__ void tri_mv_t(const Work<T>& w, int n, const T* v, T* out) {
   for (int base = 0; base < n; base += kQpThreads / 4) {
@@ -142,7 +179,7 @@ __device__ void tri_mv_t(const Work<T>& w, int n, const T* v, T* out) {
     int q = threadIdx.x & 3;
     T s = T(0);
     if (p < n)
-      for (int i = p + q; i < n; i += 4) s += w.mat[pk(i, p)] * v[i];
+      for (int i = p + q; i < n; i += 4) s += w.mat[ep(i, p)] * v[i];
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (p < n && q == 0) out[p] = s;
@@ -157,74 +194,155 @@ __device__ void kinv_apply(const Work<T>& w, int n, const T* v, T* out) {
   __syncthreads();
 }
 
-// K = H + sigma I + s * G into the packed storage; returns ||K||_1.
+// K = H + sigma I + s * G into the block storage (identity padding); returns ||K||_1.
 template <typename T, typename Tin>
 __device__ T form_K(const QpArgs<Tin>& a, const Work<T>& w, T s) {
-  const int n = a.n;
-  const long nlow = (long)n * (n + 1) / 2;
-  for (long t = threadIdx.x; t < nlow; t += kQpThreads) {
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((long)(i + 1) * (i + 2) / 2 <= t) ++i;
-    while ((long)i * (i + 1) / 2 > t) --i;
-    int j = (int)(t - (long)i * (i + 1) / 2);
-    T v = (T)a.H[(size_t)i * n + j] + s * (T)a.G[(size_t)i * n + j] + (i == j ? (T)a.sigma : T(0));
+  const int n = a.n, nb = nblocks(n);
+  const long total = (long)nb * (nb + 1) / 2 * 256;
+  for (long t = threadIdx.x; t < total; t += kQpThreads) {
+    const int b = (int)(t >> 8), e = (int)(t & 255);
+    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int J = b - I * (I + 1) / 2;
+    const int i = 16 * I + (e >> 4), j = 16 * J + (e & 15);
+    T v;
+    if (j > i) v = T(0);
+    else if (i < n && j < n) v = (T)a.H[(size_t)i * n + j] + s * (T)a.G[(size_t)i * n + j] + (i == j ? (T)a.sigma : T(0));
+    else v = (i == j) ? T(1) : T(0);
     w.mat[t] = v;
   }
   __syncthreads();
-  // ||K||_1 = max column abs sum (K symmetric)
   T nrm = T(0);
   for (int c = threadIdx.x; c < n; c += kQpThreads) {
     T cs = T(0);
-    for (int r = 0; r < n; ++r) cs += fabs(r >= c ? w.mat[pk(r, c)] : w.mat[pk(c, r)]);
+    for (int r = 0; r < n; ++r) cs += fabs(r >= c ? w.mat[ep(r, c)] : w.mat[ep(c, r)]);
     nrm = max(nrm, cs);
   }
   return block_max(nrm, w.red);
 }
 
-// In-place Cholesky of the packed matrix; returns false on a nonpositive pivot.
+// Right-looking blocked Cholesky of the block storage; false on a nonpositive pivot.
+// Per block column J: one wave factors the diagonal block in registers, one
+// lane per panel row solves against it, then the waves share the trailing
+// updates A_IK -= L_IJ L_KJ' (one 16x16 product per wave at a time).
 template <typename T>
-__device__ bool cholesky(const Work<T>& w, int n) {
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      T d = w.mat[pk(j, j)];
-      w.scal[0] = (d > T(0) && isfinite(d)) ? sqrt(d) : T(-1);
-      if (w.scal[0] > T(0)) w.mat[pk(j, j)] = w.scal[0];
+__device__ bool cholesky(const Work<T>& w, int nb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int J = 0; J < nb; ++J) {
+    T* D = w.mat + bo(J, J);
+    if (wave == 0) {
+      T row[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) row[c] = lane < 16 ? D[lane * 16 + c] : T(0);
+      bool ok = true;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const T piv = __shfl(row[j], j, 64);
+        ok = ok && piv > T(0) && isfinite(piv);
+        const T d = sqrt(piv > T(0) ? piv : T(1));
+        if (lane == j) row[j] = d;
+        else if (lane > j) row[j] = row[j] / d;
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) {
+          const T lcj = __shfl(row[j], c, 64);
+          if (lane >= c) row[c] -= row[j] * lcj;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) D[lane * 16 + c] = c <= lane ? row[c] : T(0);
+      }
+      if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
     }
     __syncthreads();
-    T piv = w.scal[0];
-    if (piv <= T(0)) return false;
-    for (int i = j + 1 + threadIdx.x; i < n; i += kQpThreads) w.mat[pk(i, j)] /= piv;
+    if (w.scal[0] < T(0)) return false;
+    const int m = nb - J - 1;
+    // panel: L_IJ = A_IJ L_JJ^{-T}, one lane per row
+    for (int t = threadIdx.x; t < m * 16; t += kQpThreads) {
+      T* rowp = w.mat + bo(J + 1 + t / 16, J) + (t % 16) * 16;
+      T x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) x[c] = rowp[c];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        T sum = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) sum -= x[k] * D[c * 16 + k];
+        x[c] = sum / D[c * 16 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) rowp[c] = x[c];
+    }
     __syncthreads();
-    // trailing update: 4 lanes per row i, lane q takes columns l = j+1+q, j+5+q, ...
-    for (int i = j + 1 + (int)(threadIdx.x >> 2); i < n; i += kQpThreads / 4) {
-      T* rowi = w.mat + pk(i, 0);
-      const T lij = rowi[j];
-      for (int l = j + 1 + (int)(threadIdx.x & 3); l <= i; l += 4) rowi[l] -= lij * w.mat[pk(l, j)];
+    // trailing update over the block pairs (I, K), J < K <= I
+    const int npairs = m * (m + 1) / 2;
+    for (int t = wave; t < npairs; t += kWaves) {
+      int ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      while (ii * (ii + 1) / 2 > t) --ii;
+      const int kk = t - ii * (ii + 1) / 2;
+      const int I = J + 1 + ii, K = J + 1 + kk;
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      bmma<true>(acc, w.mat + bo(I, J), w.mat + bo(K, J));
+      T* C = w.mat + bo(I, K);
+      const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) C[(4 * g + i) * 16 + c] -= acc[i];
     }
     __syncthreads();
   }
   return true;
 }
 
-// In-place inverse of the packed lower-triangular factor: column j (right to
-// left) of W = L^{-1}: W_jj = 1/L_jj, W_ij = -W_jj sum_{p=j+1..i} W_ip L_pj.
+// In-place W = L^{-1} on the block storage.  First every diagonal block is
+// inverted (one wave each, a column per lane); then block columns from the
+// right: W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, staged through w.part.
 template <typename T>
-__device__ void tri_invert(const Work<T>& w, int n) {
-  for (int j = n - 1; j >= 0; --j) {
-    T wjj = T(1) / w.mat[pk(j, j)];
-    for (int base = j + 1; base < n; base += kQpThreads / 4) {
-      int i = base + threadIdx.x / 4;
-      int q = threadIdx.x & 3;
-      T s = T(0);
-      if (i < n)
-        for (int p = j + 1 + q; p <= i; p += 4) s += w.mat[pk(i, p)] * w.mat[pk(p, j)];
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      if (i < n && q == 0) w.tv[i] = -wjj * s;
+__device__ void tri_invert(const Work<T>& w, int nb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int J = wave; J < nb; J += kWaves) {
+    T* D = w.mat + bo(J, J);
+    T col[16];
+    const int c = lane;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      T sum = (r == c) ? T(1) : T(0);
+#pragma unroll
+      for (int k = 0; k < r; ++k) sum -= D[r * 16 + k] * ((k >= c) ? col[k] : T(0));
+      col[r] = (r >= c) ? sum / D[r * 16 + r] : T(0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (c < 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) D[r * 16 + c] = col[r];
+    }
+  }
+  __syncthreads();
+  T* tmp = w.part;
+  for (int J = nb - 2; J >= 0; --J) {
+    const int m = nb - J - 1;
+    for (int t = wave; t < m; t += kWaves) {
+      const int I = J + 1 + t;
+      T x[4] = {T(0), T(0), T(0), T(0)};
+      for (int K = J + 1; K <= I; ++K) bmma<false>(x, w.mat + bo(I, K), w.mat + bo(K, J));
+      // stage X, then W_IJ = -X W_JJ
+      T* X = tmp + (size_t)t * 256;
+      const int cc = lane & 15, g = lane >> 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X[(4 * g + i) * 16 + cc] = x[i];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      T y[4] = {T(0), T(0), T(0), T(0)};
+      bmma<false>(y, X, w.mat + bo(J, J));
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X[(4 * g + i) * 16 + cc] = -y[i];
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += kQpThreads) w.mat[pk(i, j)] = w.tv[i];
-    if (threadIdx.x == 0) w.mat[pk(j, j)] = wjj;
+    for (int t = threadIdx.x; t < m * 256; t += kQpThreads) w.mat[bo(J + 1 + t / 256, J) + (t & 255)] = tmp[t];
     __syncthreads();
   }
 }
@@ -248,7 +366,6 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
     kinv_apply(w, n, w.rhs, y);  // z = K^{-1} sign(y)
     T zmax = T(0), ztx = T(0);
     int jmax = 0;
-    // argmax |z| (first index on ties), z'v
     for (int i = threadIdx.x; i < n; i += kQpThreads) ztx += y[i] * v[i];
     ztx = block_sum(ztx, w.red);
     if (threadIdx.x == 0) {
@@ -276,8 +393,8 @@ template <typename T, typename Tin>
 __device__ bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
   *knorm = form_K(a, w, s);
   __syncthreads();
-  if (!cholesky(w, a.n)) return false;
-  tri_invert(w, a.n);
+  if (!cholesky(w, nblocks(a.n))) return false;
+  tri_invert(w, nblocks(a.n));
   return true;
 }
 
@@ -298,10 +415,11 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   };
   w.x = take(n); w.xt = take(n); w.rhs = take(n); w.tv = take(n); w.ctv = take(n); w.gv = take(n); w.hx = take(n);
   w.z = take(m); w.y = take(m); w.lo = take(m); w.hi = take(m); w.rho = take(m); w.yprev = take(m);
-  w.part = take((size_t)kWaves * n);
+  w.part = take(part_elems(n));
   w.red = take(64);
   w.scal = take(8);
-  w.mat = mat_in_lds ? take((size_t)n * (n + 1) / 2) : reinterpret_cast<T*>(a.gmat);
+  const size_t mat_elems = bo(nblocks(n), 0);
+  w.mat = mat_in_lds ? take(mat_elems) : reinterpret_cast<T*>(a.gmat);
 
   // ---- load problem vectors
   for (int i = threadIdx.x; i < m; i += kQpThreads) {
@@ -574,8 +692,8 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
 size_t lds_bytes(int n, int nc, size_t elem, bool mat) {
   const int m = n + nc;
   auto r2 = [](size_t c) { return (c + 1) & ~(size_t)1; };
-  size_t e = 7 * r2(n) + 6 * r2(m) + r2((size_t)kWaves * n) + 64 + 8;
-  if (mat) e += r2((size_t)n * (n + 1) / 2);
+  size_t e = 7 * r2(n) + 6 * r2(m) + r2(part_elems(n)) + 64 + 8;
+  if (mat) e += r2(bo(nblocks(n), 0));
   return e * elem;
 }
 
@@ -643,7 +761,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
 
 size_t qp_workspace_bytes(int n, int n_c) {
   (void)n_c;
-  return sizeof(double) * ((size_t)n * n + (size_t)n * (n + 1) / 2 + 64);
+  return sizeof(double) * ((size_t)n * n + bo(nblocks(n), 0) + 64);
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
