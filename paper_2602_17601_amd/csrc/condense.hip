@@ -8,9 +8,9 @@
 // gradient and constraint kernels read it afterwards.
 //
 // Hessian / gradient (eqs. H and g): H = Rbar + sum_k sum_i S^i_k' Q^i_k S^i_k,
-// g = rbar + sum_k sum_i S^i_k' (Q^i_k Gx^i_k + q^i_k), computed as a split-K
-// Gram product over 16x16 tiles of H's lower triangle with one partial per
-// (tile, stage, node chunk), then reduced in a fixed order (bitwise repeatable).
+// g = rbar + sum_k sum_i S^i_k' (Q^i_k Gx^i_k + q^i_k), computed as split-K
+// reductions with one partial per (tile, stage, row chunk), summed in a fixed
+// order (bitwise repeatable).
 //
 // Constraint rows (stacked-constraint formula of Sec. V-B):
 // Ct[t] = C_t S^{i_t}_{k_t}, dt[t] = d_t - C_t Gx^{i_t}_{k_t}.
@@ -22,10 +22,6 @@ namespace gnmpc {
 namespace {
 
 constexpr int kPropThreads = 256;
-constexpr int kTileH = 16;        // Gram output tile edge
-constexpr int kGramThreads = 256; // one lane per tile element
-constexpr int kChunkNodes = 128;  // nodes per split-K chunk
-constexpr int kRowsStaged = 48;   // rows (8 nodes) staged in LDS per step
 
 // ---------------------------------------------------------------- propagation
 template <typename T>
@@ -35,15 +31,19 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
              const T* __restrict__ S_in, T* __restrict__ S_out, const T* __restrict__ Gx_in,
              T* __restrict__ Gx_out, int wmax) {
   extern __shared__ unsigned char smem_raw[];
-  T* As = reinterpret_cast<T*>(smem_raw);  // [npw][wmax][36]
+  T* As = reinterpret_cast<T*>(smem_raw);  // the pattern rows of this workgroup's nodes, contiguous
   const int node0 = blockIdx.x * npw;
   const int nn = min(npw, M - node0);
-  // stage the pattern rows of this workgroup's nodes
-  for (int ln = 0; ln < nn; ++ln) {
-    int i = node0 + ln;
-    int e0 = prow[i], w = prow[i + 1] - e0;
-    const T* src = A_k + (size_t)e0 * 36;
-    for (int t = threadIdx.x; t < w * 36; t += kPropThreads) As[(ln * wmax) * 36 + t] = src[t];
+  const int ebase = prow[node0];
+  int32_t* Ps = reinterpret_cast<int32_t*>(As + (size_t)npw * wmax * 36);  // pattern columns
+  int32_t* Rs = Ps + npw * wmax;                                            // row starts (relative)
+  {
+    // the rows of consecutive nodes are consecutive in A and in the pattern: flat copies
+    const T* src = A_k + (size_t)ebase * 36;
+    const int ne = prow[node0 + nn] - ebase;
+    for (int t = threadIdx.x; t < ne * 36; t += kPropThreads) As[t] = src[t];
+    for (int t = threadIdx.x; t < ne; t += kPropThreads) Ps[t] = pcol[ebase + t];
+    for (int t = threadIdx.x; t <= nn; t += kPropThreads) Rs[t] = prow[node0 + t] - ebase;
   }
   __syncthreads();
   const int cin = k * nu;             // live columns of S_k
@@ -53,12 +53,13 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
     int ln = it / ncol;
     int col = it - ln * ncol;
     int i = node0 + ln;
-    int e0 = prow[i], w = prow[i + 1] - e0;
-    const T* Ab = As + (size_t)(ln * wmax) * 36;
+    const int e0 = Rs[ln], w = Rs[ln + 1] - e0;
+    const T* Ab = As + (size_t)e0 * 36;
+    const int32_t* pc = Ps + e0;
     T o[6] = {0, 0, 0, 0, 0, 0};
     if (col < cin) {
       for (int e = 0; e < w; ++e) {
-        const T* Sj = S_in + (size_t)pcol[e0 + e] * NBX * cin + col;
+        const T* Sj = S_in + (size_t)pc[e] * NBX * cin + col;
         T sv[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) sv[s] = Sj[(size_t)s * cin];
@@ -75,7 +76,7 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
       for (int r = 0; r < 6; ++r) S_out[((size_t)i * NBX + r) * cout + col] = Bi[r * nu];
     } else {
       for (int e = 0; e < w; ++e) {
-        const T* xj = Gx_in + (size_t)pcol[e0 + e] * NBX;
+        const T* xj = Gx_in + (size_t)pc[e] * NBX;
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
@@ -88,13 +89,21 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
 }
 
 // ---------------------------------------------------------------- Gram + gradient
+// H: 32x32 output tiles of the lower triangle, one workgroup per (tile, stage,
+// row chunk); each of the 4 waves owns a 16x16 quarter and runs
+// v_mfma_f32_16x16x4f32 down the rows of S_k (A = S_k columns, B = Q_k S_k
+// columns).  g: one workgroup per (stage, row chunk), one lane per column.
+// Partials are summed by gram_reduce_kernel in a fixed order.
+typedef float cfloatx4 __attribute__((ext_vector_type(4)));
+constexpr int kT = 64;             // H output tile edge
+constexpr int kChunkRows = 768;    // rows of S_k per split-K chunk (128 nodes)
+
 struct GramShape {
-  int M, nu, N, n, nt, ntiles, nchunks;
+  int M, nu, N, n, nt, ntiles, nchunks, ngchunks;
 };
 
-__host__ __device__ inline int first_stage(int ta, int nu) { return (kTileH * ta) / nu + 1; }
+__host__ __device__ inline int first_stage(int ta, int nu) { return (kT * ta) / nu + 1; }
 
-// Decode the linear lower-triangle tile index into (ta, tb), ta >= tb.
 __device__ inline void tile_coords(int t, int& ta, int& tb) {
   int a = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
   while ((a + 1) * (a + 2) / 2 <= t) ++a;
@@ -103,102 +112,158 @@ __device__ inline void tile_coords(int t, int& ta, int& tb) {
   tb = t - a * (a + 1) / 2;
 }
 
-// grid: x = H tiles then g tiles, y = stage k-1, z = node chunk
 template <typename T>
-__global__ void __launch_bounds__(kGramThreads)
-gram_kernel(GramShape sh, const T* __restrict__ S_all, const T* __restrict__ Gx_all, const T* __restrict__ Q,
-            int Q_full, const T* __restrict__ q, T* __restrict__ part) {
-  __shared__ T Sa[kRowsStaged][kTileH];
-  __shared__ T Sb[kRowsStaged][kTileH];  // Q-weighted b operand (or the g vector)
-  __shared__ T red[kGramThreads];
-  const int k = blockIdx.y + 1;
-  const int chunk = blockIdx.z;
-  const bool is_g = blockIdx.x >= sh.ntiles;
+__device__ inline T qs_value(const T* Sk, const T* Qk, int Q_full, int cols, int row, int cb) {
+  const int node = row / NBX, r = row - node * NBX;
+  if (!Q_full) return Qk[row] * Sk[(size_t)row * cols + cb];
+  const T* Qn = Qk + ((size_t)node * NBX + r) * NBX;
+  const T* Sn = Sk + (size_t)node * NBX * cols + cb;
+  T v = T(0);
+#pragma unroll
+  for (int s = 0; s < NBX; ++s) v += Qn[s] * Sn[(size_t)s * cols];
+  return v;
+}
+
+// FP32: matrix cores.  grid: x = H tile, y = stage k-1, z = row chunk.  Rows
+// are staged 32 at a time (the a strip and the Q-weighted b strip, 64 columns
+// each) with independent loads; each wave owns a 32x32 quarter of the tile
+// (2 x 2 MFMA tiles) and runs 8 k-steps per staged block.
+constexpr int kRB = 32;
+__global__ void __launch_bounds__(256)
+gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __restrict__ Q, int Q_full,
+                float* __restrict__ part) {
+  __shared__ float As[kRB][kT + 4];
+  __shared__ float Bs[kRB][kT + 4];
+  const int k = blockIdx.y + 1, chunk = blockIdx.z;
   int ta, tb;
-  if (is_g) {
-    ta = blockIdx.x - sh.ntiles;
-    tb = 0;
-  } else {
-    tile_coords(blockIdx.x, ta, tb);
+  tile_coords(blockIdx.x, ta, tb);
+  if (k < first_stage(ta, sh.nu)) return;
+  const int cols = k * sh.nu, rows = NBX * sh.M;
+  const float* Sk = S_all + S_offset(k, sh.M, sh.nu);
+  const float* Qk = Q + (size_t)k * sh.M * NBX * (Q_full ? NBX : 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qa = 32 * (wave >> 1), qb = 32 * (wave & 1);
+  const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
+  cfloatx4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = cfloatx4{0.f, 0.f, 0.f, 0.f};
+  // this wave's quarter may lie entirely past the live columns
+  const bool live = kT * ta + qa < cols && kT * tb + qb < cols;
+  for (int rb = r0; rb < r1; rb += kRB) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRB * kT; t += 256) {
+      const int rr = t / kT, cc = t % kT, r = rb + rr;
+      const int ca = kT * ta + cc, cb = kT * tb + cc;
+      const bool vr = r < r1;
+      As[rr][cc] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
+      Bs[rr][cc] = (vr && cb < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb) : 0.f;
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < kRB; kk += 4) {
+        float av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = As[kk + (lane >> 4)][qa + 16 * x + (lane & 15)];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + (lane >> 4)][qb + 16 * y + (lane & 15)];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+      }
+    }
   }
-  if (k < first_stage(ta, sh.nu)) return;  // S_k has no live column in this tile
-  const int cols = k * sh.nu;
+  // C layout: lane holds rows 4 (lane >> 4) + i of each 16x16 tile, column lane & 15
+  float* out = part + (((size_t)blockIdx.x * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out[(qa + 16 * x + 4 * (lane >> 4) + i) * kT + qb + 16 * y + (lane & 15)] = acc[x][y][i];
+}
+
+// FP64: the same tiling on the VALU (one lane per output element).
+__global__ void __launch_bounds__(256)
+gram_kernel_f64(GramShape sh, const double* __restrict__ S_all, const double* __restrict__ Q, int Q_full,
+                double* __restrict__ part) {
+  const int k = blockIdx.y + 1, chunk = blockIdx.z;
+  int ta, tb;
+  tile_coords(blockIdx.x, ta, tb);
+  if (k < first_stage(ta, sh.nu)) return;
+  const int cols = k * sh.nu, rows = NBX * sh.M;
+  const double* Sk = S_all + S_offset(k, sh.M, sh.nu);
+  const double* Qk = Q + (size_t)k * sh.M * NBX * (Q_full ? NBX : 1);
+  const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
+  double* out = part + (((size_t)blockIdx.x * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
+  for (int e = threadIdx.x; e < kT * kT; e += 256) {
+    const int ca = kT * ta + e / kT, cb = kT * tb + e % kT;
+    double acc = 0.0;
+    if (ca < cols && cb < cols)
+      for (int r = r0; r < r1; ++r) acc += Sk[(size_t)r * cols + ca] * qs_value(Sk, Qk, Q_full, cols, r, cb);
+    out[e] = acc;
+  }
+}
+
+// g partials: one lane per column of S_k.  grid: x = stage k-1, y = row chunk
+// of kGRows rows (16 nodes), so there are enough workgroups to cover the chip.
+constexpr int kGRows = 96;
+template <typename T>
+__global__ void __launch_bounds__(256)
+gvec_kernel(GramShape sh, const T* __restrict__ S_all, const T* __restrict__ Gx_all, const T* __restrict__ Q,
+            int Q_full, const T* __restrict__ q, T* __restrict__ gpart) {
+  __shared__ T wv[kGRows];
+  const int k = blockIdx.x + 1, chunk = blockIdx.y;
+  const int cols = k * sh.nu, rows = NBX * sh.M;
   const T* Sk = S_all + S_offset(k, sh.M, sh.nu);
   const T* Gxk = Gx_all + (size_t)k * sh.M * NBX;
   const T* Qk = Q + (size_t)k * sh.M * NBX * (Q_full ? NBX : 1);
   const T* qk = q + (size_t)k * sh.M * NBX;
-  const int a0 = kTileH * ta, b0 = kTileH * tb;
-  const int n0 = chunk * kChunkNodes;
-  const int n1 = min(sh.M, n0 + kChunkNodes);
-  const int la = threadIdx.x / kTileH, lb = threadIdx.x % kTileH;
-  T acc = T(0);
-  for (int nb = n0; nb < n1; nb += kRowsStaged / NBX) {
-    const int nodes = min(kRowsStaged / NBX, n1 - nb);
-    const int rows = nodes * NBX;
-    __syncthreads();
-    // a operand: S_k rows x a-columns
-    for (int t = threadIdx.x; t < rows * kTileH; t += kGramThreads) {
-      int rr = t / kTileH, cc = t % kTileH;
-      int ca = a0 + cc;
-      Sa[rr][cc] = (ca < cols) ? Sk[((size_t)nb * NBX + rr) * cols + ca] : T(0);
-    }
-    // b operand: Q_k S_k (or the gradient weight Q_k Gx_k + q_k in column 0)
-    for (int t = threadIdx.x; t < rows * kTileH; t += kGramThreads) {
-      int rr = t / kTileH, cc = t % kTileH;
-      int node = nb + rr / NBX, r = rr % NBX;
-      T v = T(0);
-      if (is_g) {
-        if (cc == 0) {
-          const T* gx = Gxk + (size_t)node * NBX;
-          if (Q_full) {
-            const T* Qn = Qk + ((size_t)node * NBX + r) * NBX;
-            for (int s = 0; s < NBX; ++s) v += Qn[s] * gx[s];
-          } else {
-            v = Qk[(size_t)node * NBX + r] * gx[r];
-          }
-          v += qk[(size_t)node * NBX + r];
-        }
-      } else {
-        int cb = b0 + cc;
-        if (cb < cols) {
-          if (Q_full) {
-            const T* Qn = Qk + ((size_t)node * NBX + r) * NBX;
-            const T* Sn = Sk + (size_t)node * NBX * cols + cb;
-            for (int s = 0; s < NBX; ++s) v += Qn[s] * Sn[(size_t)s * cols];
-          } else {
-            v = Qk[(size_t)node * NBX + r] * Sk[((size_t)node * NBX + r) * cols + cb];
-          }
-        }
-      }
-      Sb[rr][cc] = v;
-    }
-    __syncthreads();
-    if (is_g) {
-      // lane (la, lb): column a = la, rows lb, lb+16, ...
-      for (int rr = lb; rr < rows; rr += kTileH) acc += Sa[rr][la] * Sb[rr][0];
+  const int r0 = chunk * kGRows, r1 = min(rows, r0 + kGRows);
+  for (int r = r0 + threadIdx.x; r < r1; r += 256) {  // w = Q_k Gx_k + q_k
+    const int node = r / NBX, rr = r - node * NBX;
+    T v;
+    if (Q_full) {
+      v = T(0);
+      const T* Qn = Qk + ((size_t)node * NBX + rr) * NBX;
+      for (int s2 = 0; s2 < NBX; ++s2) v += Qn[s2] * Gxk[(size_t)node * NBX + s2];
     } else {
-      for (int rr = 0; rr < rows; ++rr) acc += Sa[rr][la] * Sb[rr][lb];
+      v = Qk[r] * Gxk[r];
     }
+    wv[r - r0] = v + qk[r];
   }
-  const size_t slot = (((size_t)blockIdx.x * sh.N) + (k - 1)) * sh.nchunks + chunk;
-  if (is_g) {
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (lb == 0) {
-      T s = T(0);
-      for (int t = 0; t < kTileH; ++t) s += red[la * kTileH + t];
-      part[slot * (kTileH * kTileH) + la] = s;
-    }
-  } else {
-    part[slot * (kTileH * kTileH) + threadIdx.x] = acc;
+  __syncthreads();
+  T* out = gpart + ((size_t)(k - 1) * sh.ngchunks + chunk) * sh.n;
+  for (int c = threadIdx.x; c < sh.n; c += 256) {
+    T acc = T(0);
+    if (c < cols)
+      for (int r = r0; r < r1; ++r) acc += Sk[(size_t)r * cols + c] * wv[r - r0];
+    out[c] = acc;
   }
+}
+
+// Fold the gradient partials of all row chunks of one stage (fixed order):
+// gstage[k-1][c] = sum over chunks.  One lane per (stage, column).
+template <typename T>
+__global__ void gvec_fold_kernel(GramShape sh, const T* __restrict__ gpart, T* __restrict__ gstage) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= sh.N * sh.n) return;
+  const int k1 = t / sh.n, c = t % sh.n;
+  T s = T(0);
+  for (int ch = 0; ch < sh.ngchunks; ++ch) s += gpart[((size_t)k1 * sh.ngchunks + ch) * sh.n + c];
+  gstage[t] = s;
 }
 
 // One lane per element of the lower triangle (and g): fixed-order sum of the
 // partials over stages and chunks, plus R (or r), mirrored to the upper triangle.
 template <typename T>
-__global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, const T* __restrict__ R,
-                                   const T* __restrict__ r, T* __restrict__ H, T* __restrict__ g) {
+__global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, const T* __restrict__ gstage,
+                                   const T* __restrict__ R, const T* __restrict__ r, T* __restrict__ H,
+                                   T* __restrict__ g) {
   const int n = sh.n;
   const long nlow = (long)n * (n + 1) / 2;
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -207,27 +272,28 @@ __global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, con
     while ((long)(a + 1) * (a + 2) / 2 <= t) ++a;
     while ((long)a * (a + 1) / 2 > t) --a;
     int b = (int)(t - (long)a * (a + 1) / 2);
-    int ta = a / kTileH, tb = b / kTileH;
+    int ta = a / kT, tb = b / kT;
     int tile = ta * (ta + 1) / 2 + tb;
-    int e = (a % kTileH) * kTileH + (b % kTileH);
+    int e = (a % kT) * kT + (b % kT);
     T s = T(0);
-    for (int k = first_stage(ta, sh.nu); k <= sh.N; ++k)
+    for (int k = a / sh.nu + 1; k <= sh.N; ++k)
       for (int ch = 0; ch < sh.nchunks; ++ch)
-        s += part[((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks + ch) * (kTileH * kTileH) + e];
+        s += part[((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks + ch) * (kT * kT) + e];
     int ka = a / sh.nu, kb = b / sh.nu;
     if (ka == kb) s += R[((size_t)ka * sh.nu + (a % sh.nu)) * sh.nu + (b % sh.nu)];
     H[(size_t)a * n + b] = s;
     H[(size_t)b * n + a] = s;
   } else if (t < nlow + n) {
     int a = (int)(t - nlow);
-    int ta = a / kTileH;
-    int tile = sh.ntiles + ta;
     T s = T(0);
-    for (int k = first_stage(ta, sh.nu); k <= sh.N; ++k)
-      for (int ch = 0; ch < sh.nchunks; ++ch)
-        s += part[((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks + ch) * (kTileH * kTileH) + (a % kTileH)];
+    for (int k = a / sh.nu + 1; k <= sh.N; ++k) s += gstage[(size_t)(k - 1) * n + a];
     g[a] = s + r[a];
   }
+}
+
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, long n) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) dst[t] = src[t];
 }
 
 // ---------------------------------------------------------------- constraint rows
@@ -265,9 +331,10 @@ GramShape gram_shape(int M, int nu, int N) {
   sh.nu = nu;
   sh.N = N;
   sh.n = N * nu;
-  sh.nt = ceil_div(sh.n, kTileH);
+  sh.nt = ceil_div(sh.n, kT);
   sh.ntiles = sh.nt * (sh.nt + 1) / 2;
-  sh.nchunks = ceil_div(M, kChunkNodes);
+  sh.nchunks = ceil_div((long)NBX * M, kChunkRows);
+  sh.ngchunks = ceil_div((long)NBX * M, kGRows);
   return sh;
 }
 
@@ -279,14 +346,14 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   T* S = (T*)p->d_S;
   T* G = (T*)p->d_Gx;
   phase_begin(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
-  GNMPC_HIP_TRY(p, hipMemcpyAsync(G, x0, sizeof(T) * M * NBX, hipMemcpyDeviceToDevice, s));
+  copy_kernel<T><<<ceil_div((long)M * NBX, 256), 256, 0, s>>>((const T*)x0, G, (long)M * NBX);
   const int wmax = p->wmax;
   for (int k = 0; k < N; ++k) {
     int ncol = (k + 1) * nu + 1;
     int npw = std::max(1, kPropThreads / ncol);
     int lds_cap = (int)(48 * 1024 / (sizeof(T) * 36 * wmax));
     npw = std::max(1, std::min(npw, lds_cap));
-    size_t lds = sizeof(T) * 36 * (size_t)wmax * npw;
+    size_t lds = sizeof(T) * 36 * (size_t)wmax * npw + sizeof(int32_t) * ((size_t)wmax * npw + npw + 1);
     const T* S_in = k ? S + S_offset(k, M, nu) : nullptr;
     sprop_kernel<T><<<ceil_div(M, npw), kPropThreads, lds, s>>>(
         k, M, nu, npw, p->d_prow, p->d_pcol, (const T*)A + (size_t)k * p->nnz * 36,
@@ -295,12 +362,20 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   }
   phase_end(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
   GramShape sh = gram_shape(M, nu, N);
-  dim3 grid(sh.ntiles + sh.nt, N, sh.nchunks);
   phase_begin(p, GNMPC_PH_CONDENSE_GRAM, s);
-  gram_kernel<T><<<grid, kGramThreads, 0, s>>>(sh, S, G, (const T*)Q, Q_full, (const T*)q, (T*)p->d_part);
+  T* part = (T*)p->d_part;
+  T* gpart = part + (size_t)sh.ntiles * N * sh.nchunks * kT * kT;
+  dim3 grid(sh.ntiles, N, sh.nchunks);
+  if (sizeof(T) == 4)
+    gram_kernel_f32<<<grid, 256, 0, s>>>(sh, (const float*)S, (const float*)Q, Q_full, (float*)part);
+  else
+    gram_kernel_f64<<<grid, 256, 0, s>>>(sh, (const double*)S, (const double*)Q, Q_full, (double*)part);
+  gvec_kernel<T><<<dim3(N, sh.ngchunks), 256, 0, s>>>(sh, S, G, (const T*)Q, Q_full, (const T*)q, gpart);
+  T* gstage = gpart + (size_t)N * sh.ngchunks * sh.n;
+  gvec_fold_kernel<T><<<ceil_div((long)N * sh.n, 256), 256, 0, s>>>(sh, gpart, gstage);
   long nred = (long)sh.n * (sh.n + 1) / 2 + sh.n;
-  gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, (const T*)p->d_part, (const T*)R, (const T*)r,
-                                                            (T*)H, (T*)g);
+  gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, part, gstage, (const T*)R, (const T*)r, (T*)H,
+                                                            (T*)g);
   phase_end(p, GNMPC_PH_CONDENSE_GRAM, s);
   if (p->n_c > 0) {
     phase_begin(p, GNMPC_PH_CONDENSE_ROWS, s);
@@ -308,8 +383,10 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
                                            (const T*)rowd, S, G, (T*)Ct, (T*)dt);
     phase_end(p, GNMPC_PH_CONDENSE_ROWS, s);
   }
-  if (Gx)
-    GNMPC_HIP_TRY(p, hipMemcpyAsync(Gx, G, sizeof(T) * (size_t)(N + 1) * M * NBX, hipMemcpyDeviceToDevice, s));
+  if (Gx) {
+    const long ng = (long)(N + 1) * M * NBX;
+    copy_kernel<T><<<(int)std::min<long>(ceil_div(ng, 256), 2048), 256, 0, s>>>(G, (T*)Gx, ng);
+  }
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
 }
@@ -318,7 +395,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
 
 size_t condense_partial_elems(int M, int nu, int N) {
   GramShape sh = gram_shape(M, nu, N);
-  return (size_t)(sh.ntiles + sh.nt) * N * sh.nchunks * kTileH * kTileH;
+  return (size_t)sh.ntiles * N * sh.nchunks * kT * kT + (size_t)N * sh.ngchunks * sh.n + (size_t)N * sh.n;
 }
 
 gnmpc_status launch_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,

@@ -1362,16 +1362,16 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.nnz = p->nnz;
     const void* kfn = Hd == 64 ? (const void*)jvp_mfma_kernel<1>
                     : Hd == 128 ? (const void*)jvp_mfma_kernel<2> : (const void*)jvp_mfma_kernel<4>;
-    GNMPC_HIP_TRY(p, hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma_lds));
+    GNMPC_HIP_TRY(p, set_max_lds(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma_lds));
     if (Hd == 64) jvp_mfma_kernel<1><<<grid, 256, g.mfma_lds, s>>>(ma);
     else if (Hd == 128) jvp_mfma_kernel<2><<<grid, 256, g.mfma_lds, s>>>(ma);
     else jvp_mfma_kernel<4><<<grid, 256, g.mfma_lds, s>>>(ma);
   } else if (fa.bf16) {
-    GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<uint16_t>,
+    GNMPC_HIP_TRY(p, set_max_lds((const void*)jvp_valu_kernel<uint16_t>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
     jvp_valu_kernel<uint16_t><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);
   } else {
-    GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)jvp_valu_kernel<float>,
+    GNMPC_HIP_TRY(p, set_max_lds((const void*)jvp_valu_kernel<float>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.jvp_lds));
     jvp_valu_kernel<float><<<grid, 2 * Hd, g.jvp_lds, s>>>(ja);
   }

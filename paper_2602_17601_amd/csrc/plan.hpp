@@ -58,6 +58,26 @@ namespace gnmpc {
 
 constexpr int kTimerRecords = 1024;
 
+// Raise a kernel's dynamic-LDS limit once per (kernel, size): the attribute
+// call is slow, so it is not repeated on every launch.
+inline hipError_t set_max_lds(const void* fn, hipFuncAttribute attr, int bytes) {
+  struct Entry { const void* fn; int bytes; };
+  static Entry cache[64];
+  static int used = 0;
+  for (int t = 0; t < used; ++t)
+    if (cache[t].fn == fn && cache[t].bytes >= bytes) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, attr, bytes);
+  if (e == hipSuccess) {
+    for (int t = 0; t < used; ++t)
+      if (cache[t].fn == fn) {
+        cache[t].bytes = bytes;
+        return e;
+      }
+    if (used < 64) cache[used++] = Entry{fn, bytes};
+  }
+  return e;
+}
+
 // Record the start / end of a phase on stream s when timers are enabled.
 inline void phase_begin(gnmpc_plan* p, int ph, hipStream_t s) {
   if (!p->timers_on || p->ev_used[ph] >= kTimerRecords) return;

@@ -35,7 +35,8 @@ struct QpArgs {
   gnmpc_qp_info* info;
   const double* G;   // [n][n]: diag(rho_rel box) + Ct' diag(rho_rel rows) Ct
   double* gmat;      // global fallback storage for the packed factor (doubles)
-  int32_t* flag;     // set by the FP32 pass when FP64 is required
+  double* Kp;        // K = H + sigma I + rho G in the block storage, written by qp_prep_kernel
+  int32_t* flag;     // [0]: FP64 pass required; [1]: non-finite H or Ct seen by qp_prep_kernel
   double rho, sigma, alpha, eps_abs, eps_rel, kappa_fp64;
   int max_iter, check_every;
 };
@@ -44,29 +45,6 @@ __device__ inline double rho_rel(double l, double u) {
   if (!isfinite(l) && !isfinite(u)) return 1e-6;  // free row
   if (l == u) return 1e3;                          // equality row
   return 1.0;
-}
-
-// G = diag(rho_rel of the box rows) + Ct' diag(rho_rel of the state rows) Ct, in
-// double, fixed summation order.  One lane per element of the lower triangle.
-template <typename Tin>
-__global__ void qp_gram_kernel(QpArgs<Tin> a, double* G) {
-  const int n = a.n;
-  const long nlow = (long)n * (n + 1) / 2;
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nlow) return;
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((long)(i + 1) * (i + 2) / 2 <= t) ++i;
-  while ((long)i * (i + 1) / 2 > t) --i;
-  int j = (int)(t - (long)i * (i + 1) / 2);
-  double s = 0.0;
-  for (int r = 0; r < a.n_c; ++r) {
-    double l = a.lc ? (double)a.lc[r] : -INFINITY;
-    double u = a.uc ? (double)a.uc[r] : INFINITY;
-    s += rho_rel(l, u) * (double)a.Ct[(size_t)r * n + i] * (double)a.Ct[(size_t)r * n + j];
-  }
-  if (i == j) s += rho_rel((double)a.lb[i], (double)a.ub[i]);
-  G[(size_t)i * n + j] = s;
-  G[(size_t)j * n + i] = s;
 }
 
 // K, L and W = L^{-1} are kept as the lower triangle of 16x16 blocks, block
@@ -155,6 +133,46 @@ __device__ inline void bmma(double acc[4], const double* A, const double* B) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] += A[(4 * g + i) * 16 + k] * bv;
   }
+}
+
+
+// Set-up over many workgroups, one lane per element of the block storage:
+// G = diag(rho_rel of the box rows) + Ct' diag(rho_rel of the state rows) Ct
+// (FP64, fixed summation order, full symmetric, kept for refactorizations) and
+// the first K = H + sigma I + rho G in the block storage; non-finite H or Ct
+// raise flag[1].
+template <typename Tin>
+__global__ void qp_prep_kernel(QpArgs<Tin> a, double* G) {
+  const int n = a.n, nb = nblocks(n);
+  const long total = (long)bo(nb, 0);
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int b = (int)(t >> 8), e = (int)(t & 255);
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  const int i = kBS * I + (e >> 4), j = kBS * J + (e & 15);
+  double kv;
+  if (j > i) {
+    kv = 0.0;
+  } else if (i >= n || j >= n) {
+    kv = (i == j) ? 1.0 : 0.0;
+  } else {
+    double sg = 0.0;
+    for (int r = 0; r < a.n_c; ++r) {
+      const double l = a.lc ? (double)a.lc[r] : -INFINITY;
+      const double u = a.uc ? (double)a.uc[r] : INFINITY;
+      sg += rho_rel(l, u) * (double)a.Ct[(size_t)r * n + i] * (double)a.Ct[(size_t)r * n + j];
+    }
+    if (i == j) sg += rho_rel((double)a.lb[i], (double)a.ub[i]);
+    G[(size_t)i * n + j] = sg;
+    G[(size_t)j * n + i] = sg;
+    const double h = (double)a.H[(size_t)i * n + j];
+    kv = h + a.rho * sg + (i == j ? a.sigma : 0.0);
+    if (!isfinite(kv)) __hip_atomic_fetch_or(a.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  a.Kp[t] = kv;
 }
 
 // out = W v over the first n rows, 4 lanes per row.
@@ -355,7 +373,7 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
   for (int i = threadIdx.x; i < n; i += kQpThreads) v[i] = T(1) / T(n);
   __syncthreads();
   T est = T(0);
-  for (int it = 0; it < 5; ++it) {
+  for (int it = 0; it < 2; ++it) {
     kinv_apply(w, n, v, y);
     T y1 = T(0);
     for (int i = threadIdx.x; i < n; i += kQpThreads) y1 += fabs(y[i]);
@@ -388,6 +406,31 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
   return est;
 }
 
+// ||K||_1 (K symmetric: max column abs sum) from the block storage.
+template <typename T>
+__device__ T knorm1(const Work<T>& w, int n) {
+  T nrm = T(0);
+  for (int c = threadIdx.x; c < n; c += kQpThreads) {
+    T cs = T(0);
+    for (int r = 0; r < n; ++r) cs += fabs(r >= c ? w.mat[ep(r, c)] : w.mat[ep(c, r)]);
+    nrm = max(nrm, cs);
+  }
+  return block_max(nrm, w.red);
+}
+
+// Factor the K prepared by qp_prep_kernel and invert; false if not positive definite.
+template <typename T, typename Tin>
+__device__ bool factor_prepared(const QpArgs<Tin>& a, const Work<T>& w, T* knorm) {
+  const long total = (long)bo(nblocks(a.n), 0);
+  for (long t = threadIdx.x; t < total; t += kQpThreads) w.mat[t] = (T)a.Kp[t];
+  __syncthreads();
+  *knorm = knorm1(w, a.n);
+  __syncthreads();
+  if (!cholesky(w, nblocks(a.n))) return false;
+  tri_invert(w, nblocks(a.n));
+  return true;
+}
+
 // Factor K(s) and invert; false if K is not positive definite.
 template <typename T, typename Tin>
 __device__ bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
@@ -398,11 +441,75 @@ __device__ bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
   return true;
 }
 
+
+// ---------------------------------------------------------------------------
+// Row passes over a row-major global matrix (Ct or H) for FP32 instances with
+// n, rows <= 256: every wave takes 4 rows at a time (16 lanes per row, lane
+// columns c = (lane & 15) + 16 j), and all of a lane's values are loaded into
+// registers at once, so a pass pays one memory latency instead of one per row.
+constexpr int kMG = 4;   // row groups per wave held at once
+constexpr int kMH = 2;   // passes: kMG * kMH groups cover 4 * kWaves * kMG * kMH rows
+constexpr int kMJ = 16;  // 16-column slices per lane
+
+__device__ inline int rp_row(int g, int h) {
+  return 4 * ((threadIdx.x >> 6) + kWaves * (g + kMG * h)) + ((threadIdx.x & 63) >> 4);
+}
+__device__ inline int rp_col(int j) { return (threadIdx.x & 15) + 16 * j; }
+
+template <typename Tin>
+__device__ inline void rp_load(float (&R)[kMG][kMJ], const Tin* Mat, int nr, int n, int h) {
+#pragma unroll
+  for (int g = 0; g < kMG; ++g) {
+    const int r = rp_row(g, h);
+#pragma unroll
+    for (int j = 0; j < kMJ; ++j) {
+      const int c = rp_col(j);
+      R[g][j] = (r < nr && c < n) ? (float)Mat[(size_t)r * n + c] : 0.f;
+    }
+  }
+}
+__device__ inline float seg16_sum(float v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+// dot of row g with vec (LDS, n entries), the same value in all 16 lanes of the row
+__device__ inline float rp_dot(const float (&R)[kMG][kMJ], int g, const float* vec, int n) {
+  float sum = 0.f;
+#pragma unroll
+  for (int j = 0; j < kMJ; ++j) {
+    const int c = rp_col(j);
+    sum += R[g][j] * vec[c < n ? c : 0];
+  }
+  return seg16_sum(sum);
+}
+// contrib (per lane, its columns) += row g * w ; then rp_flush writes the wave's partial Mat' w
+__device__ inline void rp_axpy(float (&acc)[kMJ], const float (&R)[kMG][kMJ], int g, float wv) {
+#pragma unroll
+  for (int j = 0; j < kMJ; ++j) acc[j] += R[g][j] * wv;
+}
+__device__ inline void rp_flush(float (&acc)[kMJ], float* part, int n) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kMJ; ++j) {
+    float v = acc[j];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    const int c = rp_col(j);
+    if (lane < 16 && c < n) part[(size_t)wave * n + c] = v;
+  }
+}
+
 template <typename T, typename Tin>
 __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int mode, int mat_in_lds) {
   // mode 0: primary pass in T (may hand over to FP64); 1: FP64 pass, runs only
   // if the primary pass raised the flag; 2: the only pass.
-  if (mode == 1 && *(volatile int32_t*)a.flag == 0) return;
+  if (mode == 1 && *(volatile int32_t*)a.flag == 0) {
+    if (threadIdx.x == 0) a.flag[1] = 0;
+    return;
+  }
   extern __shared__ unsigned char smem_raw[];
   const int n = a.n, nc = a.n_c, m = n + nc;
   T* sp = reinterpret_cast<T*>(smem_raw);
@@ -444,13 +551,13 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
     w.ctv[i] = T(0);
   }
   __syncthreads();
-  // ---- finiteness of the data
+  // ---- finiteness of the data (H and Ct were checked by qp_prep_kernel; the
+  // last pass of a solve clears that flag for the next call)
   {
-    int bad = 0;
-    for (long t = threadIdx.x; t < (long)n * n; t += kQpThreads) bad |= !isfinite((T)a.H[t]);
-    for (long t = threadIdx.x; t < (long)nc * n; t += kQpThreads) bad |= !isfinite((T)a.Ct[t]);
+    int bad = *(volatile int32_t*)(a.flag + 1);
     for (int i = threadIdx.x; i < n; i += kQpThreads) bad |= !isfinite(w.gv[i]);
     T b = block_max((T)bad, w.red);
+    if (mode != 0 && threadIdx.x == 0) a.flag[1] = 0;
     if (b > T(0)) {
       if (mode == 0 && threadIdx.x == 0) *a.flag = 0;
       if (threadIdx.x == 0 && a.info) {
@@ -464,7 +571,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
 
   T scale = T(1);  // rho = scale * rho_rel * a.rho
   T knorm;
-  bool ok = factor(a, w, (T)a.rho * scale, &knorm);
+  bool ok = factor_prepared(a, w, &knorm);
   if (!ok) {
     if (mode == 0 && sizeof(T) == 4) {  // let the FP64 pass try
       if (threadIdx.x == 0) *a.flag = 1;
@@ -486,6 +593,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   if (mode == 0 && threadIdx.x == 0) *a.flag = 0;
 
   const T sigma = (T)a.sigma, alpha = (T)a.alpha;
+  const bool use_regs = n <= 16 * kMJ && nc <= 4 * kWaves * kMG * kMH;
   int status = GNMPC_QP_MAXITER;
   int iter = 0;
   T prim = T(0), dual = T(0);
@@ -506,7 +614,45 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
       w.z[i] = zn;
     }
     // state rows: z~ = Ct x~, updates, and the next Ct'(rho z - y)
-    {
+    bool done_rows = false;
+    if constexpr (sizeof(T) == 4) {
+      if (use_regs) {
+        float R[kMG][kMJ], acc[kMJ];
+#pragma unroll
+        for (int j = 0; j < kMJ; ++j) acc[j] = 0.f;
+        _Pragma("unroll 1") for (int h = 0; h < kMH; ++h) {
+        rp_load(R, a.Ct, nc, n, h);
+#pragma unroll
+        for (int g = 0; g < kMG; ++g) {
+          const int r = rp_row(g, h);
+          const float sdot = rp_dot(R, g, w.xt, n);
+          float v = 0.f;
+          if (r < nc) {
+            const int ri = n + r;
+            const float zh = alpha * sdot + (1.f - alpha) * w.z[ri];
+            const float zn = min(max(zh + w.y[ri] / w.rho[ri], w.lo[ri]), w.hi[ri]);
+            const float yn = w.y[ri] + w.rho[ri] * (zh - zn);
+            v = w.rho[ri] * zn - yn;
+            if ((threadIdx.x & 15) == 0) {
+              w.z[ri] = zn;
+              w.y[ri] = yn;
+            }
+          }
+          rp_axpy(acc, R, g, v);
+        }
+        }
+        rp_flush(acc, w.part, n);
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += kQpThreads) {
+          T sum = T(0);
+          for (int q = 0; q < kWaves; ++q) sum += w.part[(size_t)q * n + c];
+          w.ctv[c] = sum;
+        }
+        __syncthreads();
+        done_rows = true;
+      }
+    }
+    if (!done_rows) {
       const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
       T* pw = w.part + (size_t)wid * n;
       for (int c = lane; c < n; c += 64) pw[c] = T(0);
@@ -543,7 +689,44 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
       ax_max = max(ax_max, fabs(w.x[i]));
       z_max = max(z_max, fabs(w.z[i]));
     }
-    {
+    bool done_res = false;
+    if constexpr (sizeof(T) == 4) {
+      if (use_regs) {
+        float R[kMG][kMJ], acc[kMJ];
+#pragma unroll
+        for (int j = 0; j < kMJ; ++j) acc[j] = 0.f;
+        _Pragma("unroll 1") for (int h = 0; h < kMH; ++h) {
+        rp_load(R, a.Ct, nc, n, h);
+#pragma unroll
+        for (int g = 0; g < kMG; ++g) {
+          const int r = rp_row(g, h);
+          const float sdot = rp_dot(R, g, w.x, n);
+          float yv = 0.f;
+          if (r < nc) {
+            const int ri = n + r;
+            pr = max(pr, fabs(sdot - w.z[ri]));
+            ax_max = max(ax_max, fabs(sdot));
+            z_max = max(z_max, fabs(w.z[ri]));
+            yv = w.y[ri];
+          }
+          rp_axpy(acc, R, g, yv);
+        }
+        }
+        rp_flush(acc, w.part, n);
+        // H x into w.hx, one row per 16 lanes
+        _Pragma("unroll 1") for (int h = 0; h < kMH; ++h) {
+          rp_load(R, a.H, n, n, h);
+#pragma unroll
+          for (int g = 0; g < kMG; ++g) {
+            const int r = rp_row(g, h);
+            const float hv = rp_dot(R, g, w.x, n);
+            if (r < n && (threadIdx.x & 15) == 0) w.hx[r] = hv;
+          }
+        }
+        done_res = true;
+      }
+    }
+    if (!done_res) {
       const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
       T* pw = w.part + (size_t)wid * n;
       for (int c = lane; c < n; c += 64) pw[c] = T(0);
@@ -561,15 +744,20 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
         T yv = w.y[ri];
         for (int c = lane; c < n; c += 64) pw[c] += (T)crow[c] * yv;
       }
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += kQpThreads) {
+        T hx = T(0);
+        const Tin* hrow = a.H + (size_t)i * n;
+        for (int c = 0; c < n; ++c) hx += (T)hrow[c] * w.x[c];
+        w.hx[i] = hx;
+      }
     }
     __syncthreads();
     T du = T(0), hx_max = T(0), aty_max = T(0), g_max = T(0);
     for (int i = threadIdx.x; i < n; i += kQpThreads) {
       T aty = w.y[i];
       for (int q = 0; q < kWaves; ++q) aty += w.part[(size_t)q * n + i];
-      T hx = T(0);
-      const Tin* hrow = a.H + (size_t)i * n;
-      for (int c = 0; c < n; ++c) hx += (T)hrow[c] * w.x[c];
+      const T hx = w.hx[i];
       du = max(du, fabs(hx + w.gv[i] + aty));
       hx_max = max(hx_max, fabs(hx));
       aty_max = max(aty_max, fabs(aty));
@@ -607,13 +795,33 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
       dy_max = block_max(dy_max, w.red);
       support = block_sum(support, w.red);
       // A' dy: box part plus Ct' dy_rows
-      const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-      T* pw = w.part + (size_t)wid * n;
-      for (int c = lane; c < n; c += 64) pw[c] = T(0);
-      for (int r = wid; r < nc; r += kWaves) {
-        const Tin* crow = a.Ct + (size_t)r * n;
-        T dy = w.y[n + r] - w.yprev[n + r];
-        for (int c = lane; c < n; c += 64) pw[c] += (T)crow[c] * dy;
+      bool done_inf = false;
+      if constexpr (sizeof(T) == 4) {
+        if (use_regs) {
+          float R[kMG][kMJ], acc[kMJ];
+#pragma unroll
+          for (int j = 0; j < kMJ; ++j) acc[j] = 0.f;
+          _Pragma("unroll 1") for (int h = 0; h < kMH; ++h) {
+            rp_load(R, a.Ct, nc, n, h);
+#pragma unroll
+            for (int g = 0; g < kMG; ++g) {
+              const int r = rp_row(g, h);
+              rp_axpy(acc, R, g, r < nc ? w.y[n + r] - w.yprev[n + r] : 0.f);
+            }
+          }
+          rp_flush(acc, w.part, n);
+          done_inf = true;
+        }
+      }
+      if (!done_inf) {
+        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        T* pw = w.part + (size_t)wid * n;
+        for (int c = lane; c < n; c += 64) pw[c] = T(0);
+        for (int r = wid; r < nc; r += kWaves) {
+          const Tin* crow = a.Ct + (size_t)r * n;
+          T dy = w.y[n + r] - w.yprev[n + r];
+          for (int c = lane; c < n; c += 64) pw[c] += (T)crow[c] * dy;
+        }
       }
       __syncthreads();
       T atdy = T(0);
@@ -669,12 +877,34 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   }
   __syncthreads();
   // ---- outputs
+  bool done_obj = false;
+  if constexpr (sizeof(T) == 4) {
+    if (use_regs) {
+      float R[kMG][kMJ];
+      _Pragma("unroll 1") for (int h = 0; h < kMH; ++h) {
+        rp_load(R, a.H, n, n, h);
+#pragma unroll
+        for (int g = 0; g < kMG; ++g) {
+          const int r = rp_row(g, h);
+          const float hv = rp_dot(R, g, w.x, n);
+          if (r < n && (threadIdx.x & 15) == 0) w.hx[r] = hv;
+        }
+      }
+      done_obj = true;
+    }
+  }
+  if (!done_obj) {
+    for (int i = threadIdx.x; i < n; i += kQpThreads) {
+      T hx = T(0);
+      const Tin* hrow = a.H + (size_t)i * n;
+      for (int c = 0; c < n; ++c) hx += (T)hrow[c] * w.x[c];
+      w.hx[i] = hx;
+    }
+  }
+  __syncthreads();
   T obj = T(0);
   for (int i = threadIdx.x; i < n; i += kQpThreads) {
-    T hx = T(0);
-    const Tin* hrow = a.H + (size_t)i * n;
-    for (int c = 0; c < n; ++c) hx += (T)hrow[c] * w.x[c];
-    obj += w.x[i] * (T(0.5) * hx + w.gv[i]);
+    obj += w.x[i] * (T(0.5) * w.hx[i] + w.gv[i]);
     a.u[i] = (Tin)w.x[i];
   }
   obj = block_sum(obj, w.red);
@@ -707,7 +937,7 @@ gnmpc_status launch_pass(gnmpc_plan* p, const QpArgs<Tin>& a, int mode, hipStrea
     p->last_error = "QP too large for one workgroup's LDS";
     return GNMPC_UNSUPPORTED;
   }
-  GNMPC_HIP_TRY(p, hipFuncSetAttribute((const void*)qp_solve_kernel<T, Tin>,
+  GNMPC_HIP_TRY(p, set_max_lds((const void*)qp_solve_kernel<T, Tin>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   qp_solve_kernel<T, Tin><<<1, kQpThreads, lds, s>>>(a, mode, in_lds ? 1 : 0);
   return GNMPC_OK;
@@ -730,8 +960,10 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.u = (Tin*)u;
   a.info = info;
   unsigned char* ws = (unsigned char*)p->d_qp;
+  const size_t nbo = bo(nblocks(n), 0);
   a.G = (const double*)ws;
   a.gmat = (double*)(ws + sizeof(double) * (size_t)n * n);
+  a.Kp = a.gmat + nbo;
   a.flag = p->d_qp_flag;
   a.rho = st->rho;
   a.sigma = st->sigma;
@@ -741,9 +973,8 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.kappa_fp64 = st->kappa_fp64;
   a.max_iter = st->max_iter;
   a.check_every = st->check_every;
-  long nlow = (long)n * (n + 1) / 2;
   phase_begin(p, GNMPC_PH_QP, s);
-  qp_gram_kernel<Tin><<<ceil_div(nlow, 256), 256, 0, s>>>(a, (double*)ws);
+  qp_prep_kernel<Tin><<<ceil_div((long)nbo, 256), 256, 0, s>>>(a, (double*)ws);
   gnmpc_status rc;
   if (sizeof(Tin) == 8) {
     rc = launch_pass<double, Tin>(p, a, 2, s);
@@ -761,7 +992,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
 
 size_t qp_workspace_bytes(int n, int n_c) {
   (void)n_c;
-  return sizeof(double) * ((size_t)n * n + bo(nblocks(n), 0) + 64);
+  return sizeof(double) * ((size_t)n * n + 2 * bo(nblocks(n), 0) + 64);
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
