@@ -54,8 +54,14 @@ struct GnnState {
   uint16_t *Wa16 = nullptr, *Wb16 = nullptr, *Wn1_16 = nullptr, *Wn2_16 = nullptr;  // [L][Hd][Hd]
   int32_t *prog = nullptr, *elist = nullptr;
   int stage_cap = 0;
+  // register-aggregate Jacobian kernel (Hd 64 or 128)
+  bool mfma2 = false;
+  size_t mfma2_lds = 0;
+  int stage2_words = 0;
+  int32_t* glist = nullptr;
   // matrix-core forward pass (BF16): hidden states as bf16, node column tiles
   uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
+  uint8_t* cnt = nullptr;         // [L][N][M][Hd] active in-edges of each node per feature
   int n_ftiles = 0, fedge_cap = 0;
   int32_t *fcols = nullptr;       // [n_ftiles][16] node of each column (-1 = empty)
   int32_t *fmeta = nullptr;       // [n_ftiles][4]: targets, edge begin, edge count, -
@@ -68,6 +74,17 @@ namespace gnmpc {
 namespace {
 
 constexpr int kCols = 16;  // tangent columns per seed tile
+
+// Stage layout of the register-aggregate Jacobian kernel, per round l >= 1
+// (32-bit words): one record per node p of round l-1 -- [0] index of p in
+// round l, [1] bit set of p's receivers in round l, [2..3] unused,
+// [4 + 16 w + q] word w of the ReLU mask of edge (receiver q <- p) or 0,
+// [4 + 16 HW + g] four byte counters of p's active in-edges for features
+// 4g..4g+3 -- then the node-update masks of the nodes of round l ([q][HW]),
+// padded to 4 words.  The host builds, per round, a list of (word, source)
+// pairs that fills it from the forward pass.
+enum GatherKind { kGEdgeMask = 0, kGNodeMask = 1, kGCount = 2, kGConst = 3 };
+__host__ __device__ constexpr int stage_record_words(int Hd) { return 4 + 16 * (Hd / 32) + Hd / 4; }
 
 __device__ inline float bf16r(float x) {
   uint32_t u = __float_as_uint(x);
@@ -646,6 +663,282 @@ __global__ void __launch_bounds__(256) jvp_mfma_kernel(MfmaArgs a) {
 
 
 // ---------------------------------------------------------------------------
+// Seed-centric forward-mode Jacobian with the edge aggregates in registers
+// (Hd = 64 or 128).  Workgroup (tile, stage) of Hd/16 waves; wave w owns the 16
+// output features [16w, 16w + 16) of every GEMM, so each SIMD runs two waves.
+// Round l:
+//   A. per node p of round l-1 (tangent dh_p in LDS, bf16): Yb = W_b dh_p and
+//      P = W_a dh_p + Yb on the matrix cores; then, in registers, the aggregate
+//      of every receiver q of p takes -mask(q <- p) * Yb and p's own aggregate
+//      takes cnt_p * P, cnt_p being the number of p's in-edges whose ReLU is on
+//      (per feature, from the forward pass).  The aggregates of all nodes of
+//      round l (at most 16) stay in registers until every sender is done.
+//   B. aggregates go to LDS as bf16 (the GEMM operand precision); per node q of
+//      round l: dh_q = mask_q (W_n1 dh_q + W_n2 agg_q).
+// Masks, counts and the sender records of every round are gathered from the
+// forward pass into an LDS stage, one round ahead.  The decoder's three
+// velocity rows are applied to the last round's FP32 tangents in registers and
+// reduced across lanes and waves.
+struct Mfma2Args {
+  int N, M, E, L, nu, meta_stride, cap1, cap2, stage_words;
+  float dt;
+  const float *encT, *decT;
+  const uint16_t *Wa, *Wb, *Wn1, *Wn2;
+  const uint32_t *mask_enc, *mask_node, *mask_edge, *cnt;
+  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *glist, *out3, *bout2;
+  float *A, *B;
+  long nnz;
+};
+
+constexpr int kGatherPerThread = 4;
+
+template <int Hd>
+__device__ inline void gather_load(const Mfma2Args& a, int l, int k, const int32_t* mt, uint32_t (&gv)[kGatherPerThread],
+                                   int (&gd)[kGatherPerThread]) {
+  constexpr int NT = Hd * 4, HW = Hd / 32;
+  const int* gm = mt + 6 + 2 * (a.L + 1) + 4 * a.L + 2 * (l - 1);
+  const int gb = gm[0], gc = gm[1];
+  const uint32_t* be = a.mask_edge + ((size_t)(l - 1) * a.N + k) * a.E * HW;
+  const uint32_t* bn = a.mask_node + ((size_t)(l - 1) * a.N + k) * a.M * HW;
+  const uint32_t* bc = a.cnt + ((size_t)(l - 1) * a.N + k) * a.M * (Hd / 4);
+#pragma unroll
+  for (int j = 0; j < kGatherPerThread; ++j) {
+    const int t = threadIdx.x + j * NT;
+    gd[j] = -1;
+    gv[j] = 0u;
+    if (t < gc) {
+      const int x = a.glist[2 * (gb + t)], src = a.glist[2 * (gb + t) + 1];
+      const int kind = (int)((uint32_t)x >> 28);
+      gd[j] = x & 0x0FFFFFFF;
+      gv[j] = kind == kGConst ? (uint32_t)src : kind == kGEdgeMask ? be[src] : kind == kGNodeMask ? bn[src] : bc[src];
+    }
+  }
+}
+
+template <int Hd>
+__global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
+  constexpr int NW = Hd / 16;   // waves
+  constexpr int NT = NW * 64;   // threads
+  constexpr int KB = Hd / 32;   // 32-deep k-blocks
+  constexpr int HW = Hd / 32;   // mask words per node or edge
+  constexpr int CB = Hd * 2;    // bytes per bf16 column
+  constexpr int MAXV = 16;      // nodes per round
+  const int SREC = stage_record_words(Hd);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem2[];
+  unsigned char* R1 = smem2;                                         // [cap1][16] bf16 tangent columns
+  unsigned char* AG = R1 + (size_t)a.cap1 * kCols * CB;             // [cap2][16] bf16 aggregate columns
+  uint32_t* ST = reinterpret_cast<uint32_t*>(AG + (size_t)a.cap2 * kCols * CB);  // stage words
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int f0 = wave * 16 + 4 * grp;                   // this lane's 4 features
+  const int mw = wave >> 1, msh = 16 * (wave & 1) + 4 * grp;  // their mask word and bit offset
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
+  const int sb = mt[0], ob = mt[2], oc = mt[3], bb = mt[4], bc = mt[5];
+
+  uint32_t gv[kGatherPerThread];
+  int gd[kGatherPerThread];
+  gather_load<Hd>(a, 1, k, mt, gv, gd);
+  for (int t = threadIdx.x; t < a.stage_words / 4; t += NT)
+    reinterpret_cast<uint4*>(ST)[t] = make_uint4(0u, 0u, 0u, 0u);
+  // round 0: encoder tangents of the seeds (mask x weight, exact in bf16)
+  {
+    const int vb = mt[6], vc = mt[7];
+    for (int t = threadIdx.x; t < vc * kCols * Hd; t += NT) {
+      const int q = t / (kCols * Hd), c = (t / Hd) % kCols, f = t % Hd;
+      const int node = a.V[vb + q];
+      const int p = a.Vself[vb + q];
+      const int d = c - a.seedcol[sb + p];
+      const bool act = a.seedact[sb + p] >= 0;
+      float v = 0.f;
+      if (d >= 0 && (d < 6 || (act && d < 9)) && mbit(a.mask_enc + ((size_t)k * a.M + node) * HW, f))
+        v = a.encT[d * Hd + f];
+      *reinterpret_cast<uint16_t*>(R1 + ((size_t)q * kCols + c) * CB + swz(2 * f, c)) =
+          (uint16_t)(__float_as_uint(v) >> 16);
+    }
+  }
+  // weights of the first round's edge GEMMs
+  const int wrow = wave * 16 + col;
+  bf16x8_t wa[KB], wb[KB], w1[KB], w2[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    wa[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)wrow * Hd + kb * 32 + grp * 8);
+    wb[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)wrow * Hd + kb * 32 + grp * 8);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kGatherPerThread; ++j)
+    if (gd[j] >= 0) ST[gd[j]] = gv[j];
+  __syncthreads();
+
+  floatx4_t acc[MAXV];
+  int so = 0;  // stage offset of the current round
+  for (int l = 1; l <= a.L; ++l) {
+    const int vc0 = mt[7 + 2 * (l - 1)];
+    const int vb1 = mt[6 + 2 * l], vc1 = mt[7 + 2 * l];
+    const int nbase = so + vc0 * SREC;
+    const size_t woff = (size_t)(l - 1) * Hd * Hd;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      w1[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + woff + (size_t)wrow * Hd + kb * 32 + grp * 8);
+      w2[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + woff + (size_t)wrow * Hd + kb * 32 + grp * 8);
+    }
+    if (l < a.L) gather_load<Hd>(a, l + 1, k, mt, gv, gd);
+    // ---- phase A
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) acc[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < vc0; ++p) {
+      const uint32_t* rec = ST + so + p * SREC;
+      const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB;
+      bf16x8_t bfr[KB];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swz(64 * kb + 16 * grp, col));
+      const uint4 t0 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[0];
+      const uint4 t1 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[1];
+      const uint4 t2 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[2];
+      const uint4 t3 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[3];
+      const uint32_t cw = rec[4 + 16 * HW + (f0 >> 2)];
+      const int qp = __builtin_amdgcn_readfirstlane((int)rec[0]);
+      const uint32_t rcv = (uint32_t)__builtin_amdgcn_readfirstlane((int)rec[1]);
+      floatx4_t ay = floatx4_t{0.f, 0.f, 0.f, 0.f}, aa = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        ay = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[kb], bfr[kb], ay, 0, 0, 0);
+        aa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kb], bfr[kb], aa, 0, 0, 0);
+      }
+      const uint32_t tbl[16] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w,
+                                t2.x, t2.y, t2.z, t2.w, t3.x, t3.y, t3.z, t3.w};
+#pragma unroll
+      for (int q = 0; q < MAXV; ++q) {
+        if ((rcv >> q) & 1u) {
+          const uint32_t bits = tbl[q] >> msh;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[q][i] -= ((bits >> i) & 1u) ? ay[i] : 0.f;
+        }
+        if (q == qp) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[q][i] += (float)((cw >> (8 * i)) & 0xFFu) * (aa[i] + ay[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+      if (q < vc1) {
+        uint2 v;
+        v.x = pack_bf16x2(acc[q][0], acc[q][1]);
+        v.y = pack_bf16x2(acc[q][2], acc[q][3]);
+        *reinterpret_cast<uint2*>(AG + ((size_t)q * kCols + col) * CB + swz(2 * f0, col)) = v;
+      }
+    }
+    __syncthreads();
+    if (l < a.L) {
+      const size_t wn = (size_t)l * Hd * Hd;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        wa[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wa + wn + (size_t)wrow * Hd + kb * 32 + grp * 8);
+        wb[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wb + wn + (size_t)wrow * Hd + kb * 32 + grp * 8);
+      }
+    }
+    // ---- phase B: node GEMMs; results stay in registers until every wave is done reading
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+      if (q < vc1) {
+        floatx4_t c1 = floatx4_t{0.f, 0.f, 0.f, 0.f}, c2 = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        const int self = a.Vself[vb1 + q];
+        if (self >= 0) {
+          const unsigned char* Ts = R1 + ((size_t)self * kCols + col) * CB;
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb)
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                w1[kb], *reinterpret_cast<const bf16x8_t*>(Ts + swz(64 * kb + 16 * grp, col)), c1, 0, 0, 0);
+        }
+        const unsigned char* Gq = AG + ((size_t)q * kCols + col) * CB;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              w2[kb], *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col)), c2, 0, 0, 0);
+        const uint32_t bits = ST[nbase + q * HW + mw] >> msh;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[q][i] = ((bits >> i) & 1u) ? c1[i] + c2[i] : 0.f;
+      }
+    }
+    __syncthreads();
+    if (l < a.L) {
+#pragma unroll
+      for (int q = 0; q < MAXV; ++q) {
+        if (q < vc1) {
+          uint2 v;
+          v.x = pack_bf16x2(acc[q][0], acc[q][1]);
+          v.y = pack_bf16x2(acc[q][2], acc[q][3]);
+          *reinterpret_cast<uint2*>(R1 + ((size_t)q * kCols + col) * CB + swz(2 * f0, col)) = v;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kGatherPerThread; ++j)
+        if (gd[j] >= 0) ST[gd[j]] = gv[j];
+      __syncthreads();
+    }
+    so = nbase + (vc1 * HW + 3) / 4 * 4;
+  }
+
+  // ---- decoder: velocity rows 3..5 of W_dec on the last round's FP32 tangents
+  float* red = reinterpret_cast<float*>(AG);  // [q][wave][3][16]
+  {
+    const int vcL = mt[7 + 2 * a.L];
+    float dct[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dct[r][i] = a.decT[(f0 + i) * 6 + 3 + r];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+      if (q < vcL) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          float v = dct[r][0] * acc[q][0] + dct[r][1] * acc[q][1] + dct[r][2] * acc[q][2] + dct[r][3] * acc[q][3];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          if (grp == 0) red[((q * NW + wave) * 3 + r) * kCols + col] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int vbL = mt[6 + 2 * a.L];
+  for (int t = threadIdx.x; t < oc * 18; t += NT) {
+    const int o = t / 18, rem = t % 18, r = rem / 6, d = rem % 6;
+    const int q = a.out3[3 * (ob + o)], p = a.out3[3 * (ob + o) + 1];
+    const long e = a.out3[3 * (ob + o) + 2];
+    const int node = a.V[vbL + q];
+    const int cc = a.seedcol[sb + p] + d;
+    float dov = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) dov += red[((q * NW + w) * 3 + r) * kCols + cc];
+    const bool diag = node == a.seed[sb + p];
+    const float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
+    const float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
+    float* blk = a.A + ((size_t)k * a.nnz + e) * 36;
+    blk[r * 6 + d] = dp;
+    blk[(3 + r) * 6 + d] = dv;
+  }
+  for (int t = threadIdx.x; t < bc * 9; t += NT) {
+    const int o = t / 9, rem = t % 9, r = rem / 3, d = rem % 3;
+    const int q = a.bout2[2 * (bb + o)], p = a.bout2[2 * (bb + o) + 1];
+    const int node = a.V[vbL + q];
+    const int act = a.seedact[sb + p];
+    const int cc = a.seedcol[sb + p] + 6 + d;
+    float dov = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) dov += red[((q * NW + w) * 3 + r) * kCols + cc];
+    const float dv = a.dt * dov;
+    float* Bi = a.B + (((size_t)k * a.M + node) * NBX) * a.nu;
+    Bi[(3 + r) * a.nu + 3 * act + d] = dv;
+    Bi[r * a.nu + 3 * act + d] = a.dt * dv;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // Forward pass on the matrix cores (BF16 operands, FP32 accumulation).  One
 // workgroup per (column tile, stage): a tile is 16 node columns -- the target
 // nodes whose next hidden state it produces plus the senders of their edges --
@@ -698,6 +991,7 @@ struct FwdMfmaArgs {
   const uint16_t *Wa, *Wb, *Wn1, *Wn2;  // this round's weights, bf16 row-major (out, in)
   const float *be, *bn;                 // this round's biases
   uint32_t *mask_edge, *mask_node;      // this round, all stages
+  uint8_t* cnt;                         // this round, all stages: active in-edges per (node, feature)
   const int32_t *fcols, *fmeta, *fecnt, *fesrc, *feid;
 };
 
@@ -758,10 +1052,13 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
     for (int c = 0; c < col; ++c) e0 += a.fecnt[(size_t)tile * 16 + c];
     const int ne = col < nt ? a.fecnt[(size_t)tile * 16 + col] : 0;
     float agg[MT][4];
+    uint32_t ncnt[MT];  // 4 byte counters: in-edges whose ReLU is on, per feature
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m) {
+      ncnt[m] = 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) agg[m][i] = 0.f;
+    }
     for (int t = 0; t < ne; ++t) {
       const int sc = a.fesrc[eb + e0 + t];
 #pragma unroll
@@ -775,8 +1072,17 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
           const bool on = z > 0.f;
           agg[m][i] += on ? z : 0.f;
           nib |= (on ? 1u : 0u) << i;
+          ncnt[m] += (on ? 1u : 0u) << (8 * i);
         }
         qmask[(size_t)(e0 + t) * NQ + f0 / 4] = (unsigned char)nib;
+      }
+    }
+    if (col < nt) {
+      const int node = cols[col];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int f0 = wave * RW + 16 * m + 4 * grp;
+        *reinterpret_cast<uint32_t*>(a.cnt + ((size_t)k * a.M + node) * Hd + f0) = ncnt[m];
       }
     }
 #pragma unroll
@@ -898,8 +1204,12 @@ struct TilePlan {
   // per (tile, round l >= 1): the sender program {qp, n_in, n_out, qr...} of every node of
   // round l-1 and the CSR ids of the edges whose masks it reads (in-edges, then out-edges)
   std::vector<int32_t> prog, elist;
-  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0;
+  // per (tile, round l >= 1): gather list that fills the LDS stage of the
+  // register-aggregate kernel, pairs (destination word | kind << 28, source)
+  std::vector<int32_t> glist;
+  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0, stage2_cap = 0, gmax = 0;
 };
+
 
 void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
   const int M = p->M;
@@ -908,8 +1218,9 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
     for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) outn[p->h_col[e]].push_back(i);
   std::vector<int32_t> act_of(M, -1);
   for (int a = 0; a < (int)p->h_act.size(); ++a) act_of[p->h_act[a]] = a;
-  const int stride = 6 + 2 * (L + 1) + 4 * L;
-  const int HW = p->gnn ? p->gnn->Hd / 32 : 4;
+  const int stride = 6 + 2 * (L + 1) + 4 * L + 2 * L;
+  const int Hd = p->gnn ? p->gnn->Hd : 128;
+  const int HW = Hd / 32;
   std::vector<int32_t> where(M, -1);
   int i = 0;
   while (i < M) {
@@ -1007,6 +1318,46 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
       m[base + 3] = (int32_t)tp.elist.size() - eb;
       const int words = (m[base + 1] + 3) / 4 * 4 + m[base + 3] * HW + (int)nx.size() * HW;
       tp.stage_cap = std::max(tp.stage_cap, words);
+    }
+    // gather lists of the register-aggregate kernel
+    {
+      const int SREC = stage_record_words(Hd);
+      int so = 0;
+      for (int l = 1; l <= L; ++l) {
+        const std::vector<int32_t>& prv = Vl[l - 1];
+        const std::vector<int32_t>& nx = Vl[l];
+        const int gb = (int)tp.glist.size() / 2;
+        auto item = [&](int dst, int kind, int32_t src) {
+          tp.glist.push_back(dst | (kind << 28));
+          tp.glist.push_back(src);
+        };
+        for (size_t pp = 0; pp < prv.size(); ++pp) {
+          const int32_t node = prv[pp];
+          const int rec = so + (int)pp * SREC;
+          uint32_t rcv = 0;
+          for (int32_t r : outn[node]) {
+            const int q = (int)(std::lower_bound(nx.begin(), nx.end(), r) - nx.begin());
+            if (q >= 16) continue;  // more than 16 nodes in a round: this kernel is not used
+            rcv |= 1u << q;
+            const int32_t* rb = p->h_col.data() + p->h_row_ptr[r];
+            const int32_t* re = p->h_col.data() + p->h_row_ptr[r + 1];
+            const int32_t e = (int32_t)(std::lower_bound(rb, re, node) - p->h_col.data());
+            for (int w = 0; w < HW; ++w) item(rec + 4 + 16 * w + q, kGEdgeMask, e * HW + w);
+          }
+          item(rec, kGConst, (int32_t)(std::lower_bound(nx.begin(), nx.end(), node) - nx.begin()));
+          item(rec + 1, kGConst, (int32_t)rcv);
+          for (int g4 = 0; g4 < Hd / 4; ++g4) item(rec + 4 + 16 * HW + g4, kGCount, node * (Hd / 4) + g4);
+        }
+        const int nb = so + (int)prv.size() * SREC;
+        for (size_t q = 0; q < nx.size(); ++q)
+          for (int w = 0; w < HW; ++w) item(nb + (int)q * HW + w, kGNodeMask, nx[q] * HW + w);
+        so = nb + ((int)nx.size() * HW + 3) / 4 * 4;
+        const int gc = (int)tp.glist.size() / 2 - gb;
+        m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1)] = gb;
+        m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1) + 1] = gc;
+        tp.gmax = std::max(tp.gmax, gc);
+      }
+      tp.stage2_cap = std::max(tp.stage2_cap, so);
     }
     // output blocks: (node of the last round, seed) pairs inside the pattern
     m[2] = (int32_t)(tp.out3.size() / 3);
@@ -1126,7 +1477,7 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     return GNMPC_UNSUPPORTED;
   }
   g.n_tiles = tp.n_tiles;
-  g.meta_stride = 6 + 2 * (L + 1) + 4 * L;
+  g.meta_stride = 6 + 2 * (L + 1) + 4 * L + 2 * L;
   g.bufX = tp.bufX;
   g.bufY = tp.bufY;
   // The matrix-core path needs BF16, a supported width and the round buffers in LDS.
@@ -1135,6 +1486,10 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   g.stage_cap = tp.stage_cap;
   g.mfma_lds = (size_t)tp.cap1 * kCols * Hd * 2 + (size_t)tp.cap2 * kCols * Hd * 4 + (size_t)tp.stage_cap * 4;
   g.mfma = bf && (Hd == 64 || Hd == 128 || Hd == 256) && tp.cap2 <= 16 && g.mfma_lds <= 160 * 1024;
+  g.stage2_words = (tp.stage2_cap + 3) / 4 * 4;
+  g.mfma2_lds = (size_t)(tp.cap1 + tp.cap2) * kCols * Hd * 2 + (size_t)g.stage2_words * 4;
+  g.mfma2 = g.mfma && (Hd == 64 || Hd == 128) && tp.cap2 <= 16 && g.mfma2_lds <= 160 * 1024 &&
+            tp.gmax <= Hd * 4 * kGatherPerThread;
   if (g.mfma) {
     std::vector<uint16_t> wa16((size_t)L * Hd * Hd), wb16(wa16.size()), w1_16(wa16.size()), w2_16(wa16.size());
     auto b16 = [](float v) {
@@ -1152,7 +1507,7 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
           w2_16[dst] = b16(Wn2T[src]);
         }
     UP(Wa16, wa16) UP(Wb16, wb16) UP(Wn1_16, w1_16) UP(Wn2_16, w2_16)
-    UP(prog, tp.prog) UP(elist, tp.elist)
+    UP(prog, tp.prog) UP(elist, tp.elist) UP(glist, tp.glist)
     // forward column tiles: greedily add target nodes while targets plus their
     // senders fit in 16 columns; targets occupy the first columns
     std::vector<int32_t> fcols, fmeta, fecnt, fesrc, feid;
@@ -1206,6 +1561,7 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     }
     UP(fcols, fcols) UP(fmeta, fmeta) UP(fecnt, fecnt) UP(fesrc, fesrc) UP(feid, feid)
     if ((s = dalloc(p, g.h16, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
+    if ((s = dalloc(p, g.cnt, (size_t)L * NM * Hd)) != GNMPC_OK) return s;
   }
   UP(meta, tp.meta) UP(seed, tp.seed) UP(seedcol, tp.seedcol) UP(seedact, tp.seedact) UP(V, tp.V)
   UP(Vself, tp.Vself) UP(Vebeg, tp.Vebeg) UP(Vecnt, tp.Vecnt) UP(Eloc, tp.Eloc) UP(Eid, tp.Eid)
@@ -1269,6 +1625,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       f.bn = g.bn + (size_t)l * Hd;
       f.mask_edge = g.mask_edge + (size_t)l * N * g.E * (Hd / 32);
       f.mask_node = g.mask_node + (size_t)l * NM * (Hd / 32);
+      f.cnt = g.cnt + (size_t)l * NM * Hd;
       f.fcols = g.fcols;
       f.fmeta = g.fmeta;
       f.fecnt = g.fecnt;
@@ -1327,7 +1684,45 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   ja.nnz = p->nnz;
   dim3 grid(g.n_tiles, N);
   phase_begin(p, GNMPC_PH_GNN_JACOBIAN, s);
-  if (g.mfma) {
+  if (g.mfma2) {
+    Mfma2Args ma;
+    ma.N = N;
+    ma.M = M;
+    ma.E = g.E;
+    ma.L = g.L;
+    ma.nu = p->dims.nu;
+    ma.meta_stride = g.meta_stride;
+    ma.cap1 = g.cap1;
+    ma.cap2 = g.cap2;
+    ma.stage_words = g.stage2_words;
+    ma.dt = g.dt;
+    ma.encT = g.encT;
+    ma.decT = g.decT;
+    ma.Wa = g.Wa16;
+    ma.Wb = g.Wb16;
+    ma.Wn1 = g.Wn1_16;
+    ma.Wn2 = g.Wn2_16;
+    ma.mask_enc = g.mask_enc;
+    ma.mask_node = g.mask_node;
+    ma.mask_edge = g.mask_edge;
+    ma.cnt = reinterpret_cast<const uint32_t*>(g.cnt);
+    ma.meta = g.meta;
+    ma.seed = g.seed;
+    ma.seedcol = g.seedcol;
+    ma.seedact = g.seedact;
+    ma.V = g.V;
+    ma.Vself = g.Vself;
+    ma.glist = g.glist;
+    ma.out3 = g.out3;
+    ma.bout2 = g.bout2;
+    ma.A = (float*)A;
+    ma.B = (float*)B;
+    ma.nnz = p->nnz;
+    const void* kfn = Hd == 64 ? (const void*)jvp_mfma2_kernel<64> : (const void*)jvp_mfma2_kernel<128>;
+    GNMPC_HIP_TRY(p, set_max_lds(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma2_lds));
+    if (Hd == 64) jvp_mfma2_kernel<64><<<grid, 256, g.mfma2_lds, s>>>(ma);
+    else jvp_mfma2_kernel<128><<<grid, 512, g.mfma2_lds, s>>>(ma);
+  } else if (g.mfma) {
     MfmaArgs ma;
     ma.N = N;
     ma.M = M;

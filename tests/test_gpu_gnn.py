@@ -122,3 +122,37 @@ def test_gnn_bf16_paper_scale_sampled_against_bf16_weight_oracle():
         for i in nodes:
             if np.abs(Br[k, i]).sum() == 0:
                 assert np.abs(B[k, i]).max() == 0
+
+
+@pytest.mark.parametrize("M,hops,L,Hd,n_act,N", [(40, 2, 3, 64, 2, 2), (29, 3, 2, 64, 3, 2), (33, 1, 1, 128, 2, 2),
+                                                 (37, 2, 2, 128, 3, 3), (26, 1, 2, 256, 2, 2),
+                                                 (21, 2, 2, 256, 1, 2)])
+def test_gnn_bf16_small_graphs_against_bf16_weight_oracle(M, hops, L, Hd, n_act, N):
+    """BF16 MLPs on small chains (every matrix-core Jacobian variant: 64/128
+    features with register aggregates, 256 with LDS aggregates, and the vector
+    fallback when the round buffers exceed LDS), every stage and node, against
+    the FP64 oracle with BF16-rounded weights and ReLU decisions taken in BF16:
+    rel-Frobenius of A - I and of B per stage <= 2e-2, as at full scale."""
+    P = wl.make_problem("gnn_bf16_small", M=M, hops=hops, N=N, n_act=n_act, model="gnn", seed=3 * M + L, Hd=Hd,
+                        L=L, x0_sigma=0.3, walk=0.05)
+    plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.BF16)
+    assert np.all(np.isfinite(A)) and np.all(np.isfinite(B)) and np.all(np.isfinite(c))
+    Wr = P.gnn.rounded_bf16()
+    prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, rounding="bf16")
+    dA, dAr = _delta_A(A, prow, pcol, P.M), _delta_A(Ar, prow, pcol, P.M)
+    for k in range(P.N):
+        assert _rel(dA[k], dAr[k]) < 2e-2, (k, _rel(dA[k], dAr[k]))
+        assert _rel(B[k], Br[k]) < 2e-2, (k, _rel(B[k], Br[k]))
+    # B is exactly zero on the nodes the actuators do not reach within L hops
+    far = np.abs(Br).sum(axis=(2, 3)) == 0
+    assert np.all(B[far] == 0)
+
+
+def test_gnn_bf16_linearize_is_deterministic():
+    """Two BF16 linearizations of the same inputs are bitwise identical (fixed
+    reduction orders everywhere, no atomics)."""
+    P = wl.make_problem("gnn_bf16_det", M=64, hops=2, N=3, n_act=2, model="gnn", seed=11, Hd=128, L=3,
+                        x0_sigma=0.3, walk=0.05)
+    _, _, _, A1, B1, c1, f1 = _gpu_linearize(P, gn.BF16)
+    _, _, _, A2, B2, c2, f2 = _gpu_linearize(P, gn.BF16)
+    assert np.array_equal(A1, A2) and np.array_equal(B1, B2) and np.array_equal(c1, c2)
