@@ -81,8 +81,10 @@ constexpr int kCols = 16;  // tangent columns per seed tile
 // [4 + 16 w + q] word w of the ReLU mask of edge (receiver q <- p) or 0,
 // [4 + 16 HW + g] four byte counters of p's active in-edges for features
 // 4g..4g+3 -- then the node-update masks of the nodes of round l ([q][HW]),
-// padded to 4 words.  The host builds, per round, a list of (word, source)
-// pairs that fills it from the forward pass.
+// then the index of each node of round l in round l-1 (or -1), each padded
+// to 4 words; after the last round, one 4-word record per output block.  The
+// host builds, per round, a list of (word, source) pairs that fills it from
+// the forward pass.
 enum GatherKind { kGEdgeMask = 0, kGNodeMask = 1, kGCount = 2, kGConst = 3 };
 __host__ __device__ constexpr int stage_record_words(int Hd) { return 4 + 16 * (Hd / 32) + Hd / 4; }
 
@@ -690,29 +692,50 @@ struct Mfma2Args {
   long nnz;
 };
 
-constexpr int kGatherPerThread = 4;
+constexpr int kGatherPerThread = 8;
 
-template <int Hd>
-__device__ inline void gather_load(const Mfma2Args& a, int l, int k, const int32_t* mt, uint32_t (&gv)[kGatherPerThread],
-                                   int (&gd)[kGatherPerThread]) {
-  constexpr int NT = Hd * 4, HW = Hd / 32;
-  const int* gm = mt + 6 + 2 * (a.L + 1) + 4 * a.L + 2 * (l - 1);
-  const int gb = gm[0], gc = gm[1];
-  const uint32_t* be = a.mask_edge + ((size_t)(l - 1) * a.N + k) * a.E * HW;
-  const uint32_t* bn = a.mask_node + ((size_t)(l - 1) * a.N + k) * a.M * HW;
-  const uint32_t* bc = a.cnt + ((size_t)(l - 1) * a.N + k) * a.M * (Hd / 4);
+// Gather of every round's stage words at the start of the workgroup: all list
+// entries are fetched first, then all values (no branches on the loads:
+// out-of-range slots read entry 0 and are dropped), then stored to LDS.
+template <int Hd, int NT>
+__device__ inline void gather_all(const Mfma2Args& a, int k, const int32_t* mt, uint32_t* ST) {
+  constexpr int HW = Hd / 32;
+  const int* gm = mt + 6 + 2 * (a.L + 1) + 4 * a.L;
+  const int gb = gm[0];
+  int gc = 0;
+  for (int l = 1; l <= a.L; ++l) gc += gm[2 * (l - 1) + 1];
+  const int2* gl = reinterpret_cast<const int2*>(a.glist);
+  int2 it[kGatherPerThread];
 #pragma unroll
   for (int j = 0; j < kGatherPerThread; ++j) {
     const int t = threadIdx.x + j * NT;
-    gd[j] = -1;
-    gv[j] = 0u;
-    if (t < gc) {
-      const int x = a.glist[2 * (gb + t)], src = a.glist[2 * (gb + t) + 1];
-      const int kind = (int)((uint32_t)x >> 28);
-      gd[j] = x & 0x0FFFFFFF;
-      gv[j] = kind == kGConst ? (uint32_t)src : kind == kGEdgeMask ? be[src] : kind == kGNodeMask ? bn[src] : bc[src];
-    }
+    it[j] = gl[t < gc ? gb + t : 0];
   }
+  // round of each entry: the lists of consecutive rounds are contiguous
+  uint32_t v[kGatherPerThread];
+#pragma unroll
+  for (int j = 0; j < kGatherPerThread; ++j) {
+    const int t = threadIdx.x + j * NT;
+    int l = 1, end = gm[1];
+    while (l < a.L && t >= end) {
+      end += gm[2 * l + 1];
+      ++l;
+    }
+    const int kind = (int)((uint32_t)it[j].x >> 28);
+    const size_t slab = (size_t)(l - 1) * a.N + k;
+    const uint32_t* base = kind == kGEdgeMask ? a.mask_edge + slab * a.E * HW
+                         : kind == kGNodeMask ? a.mask_node + slab * a.M * HW : a.cnt + slab * a.M * (Hd / 4);
+    const bool load = t < gc && kind != kGConst;
+    const uint32_t x = base[load ? it[j].y : 0];
+    v[j] = kind == kGConst ? (uint32_t)it[j].y : x;
+  }
+#pragma unroll
+  for (int j = 0; j < kGatherPerThread; ++j)
+    if ((int)threadIdx.x + j * NT < gc) ST[it[j].x & 0x0FFFFFFF] = v[j];
+}
+
+__device__ inline bf16x8_t ldw(const uint16_t* base, uint32_t off) {
+  return *reinterpret_cast<const bf16x8_t*>(base + off);
 }
 
 template <int Hd>
@@ -723,83 +746,92 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   constexpr int HW = Hd / 32;   // mask words per node or edge
   constexpr int CB = Hd * 2;    // bytes per bf16 column
   constexpr int MAXV = 16;      // nodes per round
-  const int SREC = stage_record_words(Hd);
+  constexpr int GW = NW / 2;    // waves per node group in phase B
+  constexpr int SREC = stage_record_words(Hd);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem2[];
   unsigned char* R1 = smem2;                                         // [cap1][16] bf16 tangent columns
   unsigned char* AG = R1 + (size_t)a.cap1 * kCols * CB;             // [cap2][16] bf16 aggregate columns
   uint32_t* ST = reinterpret_cast<uint32_t*>(AG + (size_t)a.cap2 * kCols * CB);  // stage words
+  float* DT = reinterpret_cast<float*>(ST + a.stage_words);                    // decoder rows 3..5, [3][Hd]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int f0 = wave * 16 + 4 * grp;                   // this lane's 4 features
-  const int mw = wave >> 1, msh = 16 * (wave & 1) + 4 * grp;  // their mask word and bit offset
+  // phase A: wave w owns output features [16 w, 16 w + 16) of every node
+  const int f0 = wave * 16 + 4 * grp;
+  const int mw = wave >> 1, msh = 16 * (wave & 1) + 4 * grp;
+  // phase B: node group ng takes nodes q = 2 j + ng; its wave wg owns features [32 wg, 32 wg + 32)
+  const int ng = wave / GW, wg = wave % GW;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
-  const int sb = mt[0], ob = mt[2], oc = mt[3], bb = mt[4], bc = mt[5];
+  const int sb = mt[0], oc = mt[3], bc = mt[5];
 
-  uint32_t gv[kGatherPerThread];
-  int gd[kGatherPerThread];
-  gather_load<Hd>(a, 1, k, mt, gv, gd);
-  for (int t = threadIdx.x; t < a.stage_words / 4; t += NT)
-    reinterpret_cast<uint4*>(ST)[t] = make_uint4(0u, 0u, 0u, 0u);
-  // round 0: encoder tangents of the seeds (mask x weight, exact in bf16)
+  // lane offsets of the weight fragments (rows of the A operands): phase A, then phase B's two row tiles
+  const uint32_t woA = (uint32_t)((wave * 16 + col) * Hd + grp * 8);
+  const uint32_t woB = (uint32_t)((wg * 32 + col) * Hd + grp * 8);
+  bf16x8_t wa[KB], wb[KB], w1[2][KB], w2[2][KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    wa[kb] = ldw(a.Wa, woA + kb * 32);
+    wb[kb] = ldw(a.Wb, woA + kb * 32);
+  }
+  // round 0: encoder tangents of the seeds (mask x weight, exact in bf16), 8 features per item
   {
     const int vb = mt[6], vc = mt[7];
-    for (int t = threadIdx.x; t < vc * kCols * Hd; t += NT) {
-      const int q = t / (kCols * Hd), c = (t / Hd) % kCols, f = t % Hd;
+    for (int t = threadIdx.x; t < vc * kCols * (Hd / 8); t += NT) {
+      const int q = t / (kCols * (Hd / 8)), c = (t / (Hd / 8)) % kCols, fc = t % (Hd / 8);
       const int node = a.V[vb + q];
       const int p = a.Vself[vb + q];
       const int d = c - a.seedcol[sb + p];
-      const bool act = a.seedact[sb + p] >= 0;
-      float v = 0.f;
-      if (d >= 0 && (d < 6 || (act && d < 9)) && mbit(a.mask_enc + ((size_t)k * a.M + node) * HW, f))
-        v = a.encT[d * Hd + f];
-      *reinterpret_cast<uint16_t*>(R1 + ((size_t)q * kCols + c) * CB + swz(2 * f, c)) =
-          (uint16_t)(__float_as_uint(v) >> 16);
+      const bool valid = d >= 0 && (d < 6 || (a.seedact[sb + p] >= 0 && d < 9));
+      const uint32_t bits = (a.mask_enc[((size_t)k * a.M + node) * HW + (fc >> 2)] >> (8 * (fc & 3))) & 0xFFu;
+      const float4* e4 = reinterpret_cast<const float4*>(a.encT + (size_t)(valid ? d : 0) * Hd + 8 * fc);
+      const float4 lo = e4[0], hi = e4[1];
+      const float ev[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      uint32_t pk[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint32_t b0 = (valid && ((bits >> (2 * h)) & 1u)) ? (__float_as_uint(ev[2 * h]) >> 16) : 0u;
+        const uint32_t b1 = (valid && ((bits >> (2 * h + 1)) & 1u)) ? (__float_as_uint(ev[2 * h + 1]) & 0xFFFF0000u) : 0u;
+        pk[h] = b0 | b1;
+      }
+      *reinterpret_cast<uint4*>(R1 + ((size_t)q * kCols + c) * CB + swz(16 * fc, c)) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
   }
-  // weights of the first round's edge GEMMs
-  const int wrow = wave * 16 + col;
-  bf16x8_t wa[KB], wb[KB], w1[KB], w2[KB];
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    wa[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)wrow * Hd + kb * 32 + grp * 8);
-    wb[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)wrow * Hd + kb * 32 + grp * 8);
-  }
+  for (int t = threadIdx.x; t < a.stage_words / 4; t += NT)
+    reinterpret_cast<uint4*>(ST)[t] = make_uint4(0u, 0u, 0u, 0u);
+  for (int t = threadIdx.x; t < 3 * Hd; t += NT) DT[t] = a.decT[(t % Hd) * 6 + 3 + t / Hd];
   __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kGatherPerThread; ++j)
-    if (gd[j] >= 0) ST[gd[j]] = gv[j];
+  gather_all<Hd, NT>(a, k, mt, ST);
   __syncthreads();
 
   floatx4_t acc[MAXV];
-  int so = 0;  // stage offset of the current round
+  int so = 0;          // stage offset of the current round
   for (int l = 1; l <= a.L; ++l) {
     const int vc0 = mt[7 + 2 * (l - 1)];
     const int vb1 = mt[6 + 2 * l], vc1 = mt[7 + 2 * l];
     const int nbase = so + vc0 * SREC;
+    const int sfbase = nbase + (vc1 * HW + 3) / 4 * 4;
     const size_t woff = (size_t)(l - 1) * Hd * Hd;
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      w1[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + woff + (size_t)wrow * Hd + kb * 32 + grp * 8);
-      w2[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + woff + (size_t)wrow * Hd + kb * 32 + grp * 8);
-    }
-    if (l < a.L) gather_load<Hd>(a, l + 1, k, mt, gv, gd);
-    // ---- phase A
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        w1[m][kb] = ldw(a.Wn1 + woff, woB + 16 * m * Hd + kb * 32);
+        w2[m][kb] = ldw(a.Wn2 + woff, woB + 16 * m * Hd + kb * 32);
+      }
+    // ---- phase A: edge GEMMs per sender, aggregates of every receiver in registers
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     for (int p = 0; p < vc0; ++p) {
-      const uint32_t* rec = ST + so + p * SREC;
+      const uint4* rec4 = reinterpret_cast<const uint4*>(ST) + (so >> 2) + p * (SREC / 4);
       const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB;
       bf16x8_t bfr[KB];
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swz(64 * kb + 16 * grp, col));
-      const uint4 t0 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[0];
-      const uint4 t1 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[1];
-      const uint4 t2 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[2];
-      const uint4 t3 = reinterpret_cast<const uint4*>(rec + 4 + 16 * mw)[3];
-      const uint32_t cw = rec[4 + 16 * HW + (f0 >> 2)];
-      const int qp = __builtin_amdgcn_readfirstlane((int)rec[0]);
-      const uint32_t rcv = (uint32_t)__builtin_amdgcn_readfirstlane((int)rec[1]);
+      const uint4 hd = rec4[0];
+      const uint4 t0 = rec4[1 + 4 * mw], t1 = rec4[2 + 4 * mw], t2 = rec4[3 + 4 * mw], t3 = rec4[4 + 4 * mw];
+      const uint32_t cw = reinterpret_cast<const uint32_t*>(rec4)[4 + 16 * HW + (f0 >> 2)];
+      const int qp = __builtin_amdgcn_readfirstlane((int)hd.x);
+      const uint32_t rcv = (uint32_t)__builtin_amdgcn_readfirstlane((int)hd.y);
       floatx4_t ay = floatx4_t{0.f, 0.f, 0.f, 0.f}, aa = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
@@ -811,9 +843,9 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
 #pragma unroll
       for (int q = 0; q < MAXV; ++q) {
         if ((rcv >> q) & 1u) {
-          const uint32_t bits = tbl[q] >> msh;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[q][i] -= ((bits >> i) & 1u) ? ay[i] : 0.f;
+          for (int i = 0; i < 4; ++i)
+            acc[q][i] -= __uint_as_float(__float_as_uint(ay[i]) & (uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], msh + i, 1));
         }
         if (q == qp) {
 #pragma unroll
@@ -821,13 +853,16 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         }
       }
     }
+    {
+      unsigned char* AGw = AG + (size_t)col * CB + swz(2 * f0, col);
 #pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
-      if (q < vc1) {
-        uint2 v;
-        v.x = pack_bf16x2(acc[q][0], acc[q][1]);
-        v.y = pack_bf16x2(acc[q][2], acc[q][3]);
-        *reinterpret_cast<uint2*>(AG + ((size_t)q * kCols + col) * CB + swz(2 * f0, col)) = v;
+      for (int q = 0; q < MAXV; ++q) {
+        if (q < vc1) {
+          uint2 v;
+          v.x = pack_bf16x2(acc[q][0], acc[q][1]);
+          v.y = pack_bf16x2(acc[q][2], acc[q][3]);
+          *reinterpret_cast<uint2*>(AGw + (size_t)q * kCols * CB) = v;
+        }
       }
     }
     __syncthreads();
@@ -835,105 +870,124 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       const size_t wn = (size_t)l * Hd * Hd;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        wa[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wa + wn + (size_t)wrow * Hd + kb * 32 + grp * 8);
-        wb[kb] = *reinterpret_cast<const bf16x8_t*>(a.Wb + wn + (size_t)wrow * Hd + kb * 32 + grp * 8);
+        wa[kb] = ldw(a.Wa + wn, woA + kb * 32);
+        wb[kb] = ldw(a.Wb + wn, woA + kb * 32);
       }
     }
-    // ---- phase B: node GEMMs; results stay in registers until every wave is done reading
+    // ---- phase B: node GEMMs, two node groups; results stay in registers until every wave is done reading
+    const unsigned char* AGg = AG + ((size_t)ng * kCols + col) * CB;  // node 2 j + ng at + 2 j * kCols * CB
 #pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
+    for (int j = 0; j < MAXV / 2; ++j) {
+      const int q = 2 * j + ng;
       if (q < vc1) {
-        floatx4_t c1 = floatx4_t{0.f, 0.f, 0.f, 0.f}, c2 = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        const int self = a.Vself[vb1 + q];
-        if (self >= 0) {
-          const unsigned char* Ts = R1 + ((size_t)self * kCols + col) * CB;
+        floatx4_t c1[2], c2[2];
 #pragma unroll
-          for (int kb = 0; kb < KB; ++kb)
-            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                w1[kb], *reinterpret_cast<const bf16x8_t*>(Ts + swz(64 * kb + 16 * grp, col)), c1, 0, 0, 0);
+        for (int m = 0; m < 2; ++m) {
+          c1[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+          c2[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         }
-        const unsigned char* Gq = AG + ((size_t)q * kCols + col) * CB;
+        const int self = __builtin_amdgcn_readfirstlane((int)ST[sfbase + q]);
+        const unsigned char* Ts = R1 + ((size_t)(self >= 0 ? self : 0) * kCols + col) * CB;
+        const unsigned char* Gq = AGg + (size_t)(2 * j) * kCols * CB;
+        if (self >= 0) {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              w2[kb], *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col)), c2, 0, 0, 0);
-        const uint32_t bits = ST[nbase + q * HW + mw] >> msh;
+          for (int kb = 0; kb < KB; ++kb) {
+            const bf16x8_t bs = *reinterpret_cast<const bf16x8_t*>(Ts + swz(64 * kb + 16 * grp, col));
+            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[q][i] = ((bits >> i) & 1u) ? c1[i] + c2[i] : 0.f;
+            for (int m = 0; m < 2; ++m) {
+              c1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m][kb], bs, c1[m], 0, 0, 0);
+              c2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c2[m], 0, 0, 0);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col));
+#pragma unroll
+            for (int m = 0; m < 2; ++m) c2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c2[m], 0, 0, 0);
+          }
+        }
+        const int bits = (int)ST[nbase + q * HW + wg];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc[2 * j + m][i] = __uint_as_float(__float_as_uint(c1[m][i] + c2[m][i]) &
+                                                (uint32_t)__builtin_amdgcn_sbfe(bits, 16 * m + 4 * grp + i, 1));
       }
     }
     __syncthreads();
     if (l < a.L) {
+      unsigned char* R1g = R1 + ((size_t)ng * kCols + col) * CB;
+      const int sw0 = swz(2 * (wg * 32 + 4 * grp), col), sw1 = swz(2 * (wg * 32 + 16 + 4 * grp), col);
 #pragma unroll
-      for (int q = 0; q < MAXV; ++q) {
+      for (int j = 0; j < MAXV / 2; ++j) {
+        const int q = 2 * j + ng;
         if (q < vc1) {
-          uint2 v;
-          v.x = pack_bf16x2(acc[q][0], acc[q][1]);
-          v.y = pack_bf16x2(acc[q][2], acc[q][3]);
-          *reinterpret_cast<uint2*>(R1 + ((size_t)q * kCols + col) * CB + swz(2 * f0, col)) = v;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            uint2 v;
+            v.x = pack_bf16x2(acc[2 * j + m][0], acc[2 * j + m][1]);
+            v.y = pack_bf16x2(acc[2 * j + m][2], acc[2 * j + m][3]);
+            *reinterpret_cast<uint2*>(R1g + (size_t)(2 * j) * kCols * CB + (m ? sw1 : sw0)) = v;
+          }
         }
       }
-#pragma unroll
-      for (int j = 0; j < kGatherPerThread; ++j)
-        if (gd[j] >= 0) ST[gd[j]] = gv[j];
       __syncthreads();
     }
-    so = nbase + (vc1 * HW + 3) / 4 * 4;
+    so = sfbase + (vc1 + 3) / 4 * 4;
   }
 
   // ---- decoder: velocity rows 3..5 of W_dec on the last round's FP32 tangents
-  float* red = reinterpret_cast<float*>(AG);  // [q][wave][3][16]
+  float* red = reinterpret_cast<float*>(AG);  // [q][GW][3][16]
   {
     const int vcL = mt[7 + 2 * a.L];
-    float dct[3][4];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dct[r][i] = a.decT[(f0 + i) * 6 + 3 + r];
-#pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
+    for (int j = 0; j < MAXV / 2; ++j) {
+      const int q = 2 * j + ng;
       if (q < vcL) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          float v = dct[r][0] * acc[q][0] + dct[r][1] * acc[q][1] + dct[r][2] * acc[q][2] + dct[r][3] * acc[q][3];
+          float v = 0.f;
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v += DT[r * Hd + wg * 32 + 16 * m + 4 * grp + i] * acc[2 * j + m][i];
           v += __shfl_xor(v, 16);
           v += __shfl_xor(v, 32);
-          if (grp == 0) red[((q * NW + wave) * 3 + r) * kCols + col] = v;
+          if (grp == 0) red[((q * GW + wg) * 3 + r) * kCols + col] = v;
         }
       }
     }
   }
   __syncthreads();
-  const int vbL = mt[6 + 2 * a.L];
+  const int4* orec = reinterpret_cast<const int4*>(ST) + (so >> 2);
   for (int t = threadIdx.x; t < oc * 18; t += NT) {
     const int o = t / 18, rem = t % 18, r = rem / 6, d = rem % 6;
-    const int q = a.out3[3 * (ob + o)], p = a.out3[3 * (ob + o) + 1];
-    const long e = a.out3[3 * (ob + o) + 2];
-    const int node = a.V[vbL + q];
-    const int cc = a.seedcol[sb + p] + d;
+    const int4 rc = orec[o];  // {block, q, first column, diagonal}
+    const int cc = rc.z + d;
     float dov = 0.f;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) dov += red[((q * NW + w) * 3 + r) * kCols + cc];
-    const bool diag = node == a.seed[sb + p];
+    for (int w = 0; w < GW; ++w) dov += red[((rc.y * GW + w) * 3 + r) * kCols + cc];
+    const bool diag = rc.w != 0;
     const float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
     const float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
-    float* blk = a.A + ((size_t)k * a.nnz + e) * 36;
+    float* blk = a.A + ((size_t)k * a.nnz + rc.x) * 36;
     blk[r * 6 + d] = dp;
     blk[(3 + r) * 6 + d] = dv;
   }
   for (int t = threadIdx.x; t < bc * 9; t += NT) {
     const int o = t / 9, rem = t % 9, r = rem / 3, d = rem % 3;
-    const int q = a.bout2[2 * (bb + o)], p = a.bout2[2 * (bb + o) + 1];
-    const int node = a.V[vbL + q];
-    const int act = a.seedact[sb + p];
-    const int cc = a.seedcol[sb + p] + 6 + d;
+    const int4 rc = orec[oc + o];  // {node, q, first force column, actuator}
+    const int cc = rc.z + d;
     float dov = 0.f;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) dov += red[((q * NW + w) * 3 + r) * kCols + cc];
+    for (int w = 0; w < GW; ++w) dov += red[((rc.y * GW + w) * 3 + r) * kCols + cc];
     const float dv = a.dt * dov;
-    float* Bi = a.B + (((size_t)k * a.M + node) * NBX) * a.nu;
-    Bi[(3 + r) * a.nu + 3 * act + d] = dv;
-    Bi[r * a.nu + 3 * act + d] = a.dt * dv;
+    float* Bi = a.B + (((size_t)k * a.M + rc.x) * NBX) * a.nu;
+    Bi[(3 + r) * a.nu + 3 * rc.w + d] = dv;
+    Bi[r * a.nu + 3 * rc.w + d] = a.dt * dv;
   }
 }
 
@@ -1351,12 +1405,47 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
         const int nb = so + (int)prv.size() * SREC;
         for (size_t q = 0; q < nx.size(); ++q)
           for (int w = 0; w < HW; ++w) item(nb + (int)q * HW + w, kGNodeMask, nx[q] * HW + w);
-        so = nb + ((int)nx.size() * HW + 3) / 4 * 4;
+        const int sfb = nb + ((int)nx.size() * HW + 3) / 4 * 4;
+        for (size_t q = 0; q < nx.size(); ++q) {
+          auto it = std::lower_bound(prv.begin(), prv.end(), nx[q]);
+          item(sfb + (int)q, kGConst, (it != prv.end() && *it == nx[q]) ? (int32_t)(it - prv.begin()) : -1);
+        }
+        so = sfb + ((int)nx.size() + 3) / 4 * 4;
+        if (l == L) {
+          // output records: A blocks {CSR block id, node index q, first column, diagonal?},
+          // then B blocks {node, q, first force column, actuator}
+          for (size_t q = 0; q < nx.size(); ++q) {
+            const int32_t node = nx[q];
+            const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
+            const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
+            for (size_t sd = 0; sd < seeds.size(); ++sd) {
+              const int32_t* it = std::lower_bound(rb, re, seeds[sd]);
+              if (it == re || *it != seeds[sd]) continue;
+              item(so++, kGConst, (int32_t)(it - p->h_pcol.data()));
+              item(so++, kGConst, (int32_t)q);
+              item(so++, kGConst, cols[sd]);
+              item(so++, kGConst, node == seeds[sd] ? 1 : 0);
+            }
+          }
+          for (size_t q = 0; q < nx.size(); ++q)
+            for (size_t sd = 0; sd < seeds.size(); ++sd) {
+              if (act_of[seeds[sd]] < 0) continue;
+              const int32_t node = nx[q];
+              const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
+              const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
+              const int32_t* it = std::lower_bound(rb, re, seeds[sd]);
+              if (it == re || *it != seeds[sd]) continue;
+              item(so++, kGConst, node);
+              item(so++, kGConst, (int32_t)q);
+              item(so++, kGConst, cols[sd] + 6);
+              item(so++, kGConst, act_of[seeds[sd]]);
+            }
+        }
         const int gc = (int)tp.glist.size() / 2 - gb;
         m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1)] = gb;
         m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1) + 1] = gc;
-        tp.gmax = std::max(tp.gmax, gc);
       }
+      tp.gmax = std::max(tp.gmax, (int)tp.glist.size() / 2 - m[6 + 2 * (L + 1) + 4 * L]);
       tp.stage2_cap = std::max(tp.stage2_cap, so);
     }
     // output blocks: (node of the last round, seed) pairs inside the pattern
@@ -1487,9 +1576,9 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   g.mfma_lds = (size_t)tp.cap1 * kCols * Hd * 2 + (size_t)tp.cap2 * kCols * Hd * 4 + (size_t)tp.stage_cap * 4;
   g.mfma = bf && (Hd == 64 || Hd == 128 || Hd == 256) && tp.cap2 <= 16 && g.mfma_lds <= 160 * 1024;
   g.stage2_words = (tp.stage2_cap + 3) / 4 * 4;
-  g.mfma2_lds = (size_t)(tp.cap1 + tp.cap2) * kCols * Hd * 2 + (size_t)g.stage2_words * 4;
+  g.mfma2_lds = (size_t)(tp.cap1 + tp.cap2) * kCols * Hd * 2 + (size_t)g.stage2_words * 4 + (size_t)3 * Hd * 4;
   g.mfma2 = g.mfma && (Hd == 64 || Hd == 128) && tp.cap2 <= 16 && g.mfma2_lds <= 160 * 1024 &&
-            tp.gmax <= Hd * 4 * kGatherPerThread;
+            tp.gmax <= Hd * 4 * kGatherPerThread;  // gmax: stage words gathered per tile, all rounds
   if (g.mfma) {
     std::vector<uint16_t> wa16((size_t)L * Hd * Hd), wb16(wa16.size()), w1_16(wa16.size()), w2_16(wa16.size());
     auto b16 = [](float v) {
