@@ -840,16 +840,19 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       }
       const uint32_t tbl[16] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w,
                                 t2.x, t2.y, t2.z, t2.w, t3.x, t3.y, t3.z, t3.w};
+      const uint32_t touch = rcv | (1u << qp);
 #pragma unroll
       for (int q = 0; q < MAXV; ++q) {
-        if ((rcv >> q) & 1u) {
+        if ((touch >> q) & 1u) {
+          if ((rcv >> q) & 1u) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            acc[q][i] -= __uint_as_float(__float_as_uint(ay[i]) & (uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], msh + i, 1));
-        }
-        if (q == qp) {
+            for (int i = 0; i < 4; ++i)
+              acc[q][i] -= __uint_as_float(__float_as_uint(ay[i]) & (uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], msh + i, 1));
+          }
+          if (q == qp) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[q][i] += (float)((cw >> (8 * i)) & 0xFFu) * (aa[i] + ay[i]);
+            for (int i = 0; i < 4; ++i) acc[q][i] += (float)((cw >> (8 * i)) & 0xFFu) * (aa[i] + ay[i]);
+          }
         }
       }
     }
@@ -940,24 +943,35 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   }
 
   // ---- decoder: velocity rows 3..5 of W_dec on the last round's FP32 tangents
-  float* red = reinterpret_cast<float*>(AG);  // [q][GW][3][16]
+  // per-lane partial sums over this lane's 8 features, [q][GW * 4 lanes groups][16 columns][4]
+  float4* red = reinterpret_cast<float4*>(AG);
   {
     const int vcL = mt[7 + 2 * a.L];
+    float dct[3][2][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const float4 d4 = *reinterpret_cast<const float4*>(DT + r * Hd + wg * 32 + 16 * m + 4 * grp);
+        dct[r][m][0] = d4.x;
+        dct[r][m][1] = d4.y;
+        dct[r][m][2] = d4.z;
+        dct[r][m][3] = d4.w;
+      }
+    float4* rw = red + ((size_t)ng * GW * 4 + wg * 4 + grp) * kCols + col;
 #pragma unroll
     for (int j = 0; j < MAXV / 2; ++j) {
-      const int q = 2 * j + ng;
-      if (q < vcL) {
+      if (2 * j + ng < vcL) {
+        float v[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          float v = 0.f;
+          v[r] = 0.f;
 #pragma unroll
           for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v += DT[r * Hd + wg * 32 + 16 * m + 4 * grp + i] * acc[2 * j + m][i];
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
-          if (grp == 0) red[((q * GW + wg) * 3 + r) * kCols + col] = v;
+            for (int i = 0; i < 4; ++i) v[r] += dct[r][m][i] * acc[2 * j + m][i];
         }
+        rw[(size_t)(2 * j) * GW * 4 * kCols] = make_float4(v[0], v[1], v[2], 0.f);
       }
     }
   }
@@ -968,8 +982,9 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     const int4 rc = orec[o];  // {block, q, first column, diagonal}
     const int cc = rc.z + d;
     float dov = 0.f;
+    const float* rq = reinterpret_cast<const float*>(red + (size_t)rc.y * GW * 4 * kCols + cc) + r;
 #pragma unroll
-    for (int w = 0; w < GW; ++w) dov += red[((rc.y * GW + w) * 3 + r) * kCols + cc];
+    for (int w = 0; w < GW * 4; ++w) dov += rq[w * kCols * 4];
     const bool diag = rc.w != 0;
     const float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
     const float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
@@ -982,8 +997,9 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     const int4 rc = orec[oc + o];  // {node, q, first force column, actuator}
     const int cc = rc.z + d;
     float dov = 0.f;
+    const float* rq = reinterpret_cast<const float*>(red + (size_t)rc.y * GW * 4 * kCols + cc) + r;
 #pragma unroll
-    for (int w = 0; w < GW; ++w) dov += red[((rc.y * GW + w) * 3 + r) * kCols + cc];
+    for (int w = 0; w < GW * 4; ++w) dov += rq[w * kCols * 4];
     const float dv = a.dt * dov;
     float* Bi = a.B + (((size_t)k * a.M + rc.x) * NBX) * a.nu;
     Bi[(3 + r) * a.nu + 3 * rc.w + d] = dv;
