@@ -175,32 +175,81 @@ __global__ void qp_prep_kernel(QpArgs<Tin> a, double* G) {
   a.Kp[t] = kv;
 }
 
-// out = W v over the first n rows, 4 lanes per row.
+// Four consecutive elements of a 16-byte aligned array.
+__device__ inline void ld4(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ inline void ld4(const double* p, double (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+
+// Triangular mat-vecs with W in the block storage.  A wave reads a whole
+// 16x16 block per instruction (lane l: row l >> 2, columns 4 (l & 3) .. +3);
+// jobs pair block rows (columns) I and nb-1-I so every wave gets ~nb + 1
+// blocks.  Input vectors are zero-padded to 16 nb entries.
+// out = W v over the first n rows.
 template <typename T>
 __device__ void tri_mv(const Work<T>& w, int n, const T* v, T* out) {
-  for (int base = 0; base < n; base += kQpThreads / 4) {
-    int i = base + threadIdx.x / 4;
-    int q = threadIdx.x & 3;
-    T s = T(0);
-    if (i < n)
-      for (int j = q; j <= i; j += 4) s += w.mat[ep(i, j)] * v[j];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (i < n && q == 0) out[i] = s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = nblocks(n), r = lane >> 2, c4 = (lane & 3) * 4;
+  for (int job = wave; job < (nb + 1) / 2; job += kWaves) {
+    for (int half = 0; half < 2; ++half) {
+      const int I = half == 0 ? job : nb - 1 - job;
+      if (half == 1 && I == job) break;
+      const T* brow = w.mat + bo(I, 0) + r * 16 + c4;
+      T s = T(0);
+#pragma unroll 4
+      for (int J = 0; J <= I; ++J) {
+        T wv[4], vv[4];
+        ld4(brow + (size_t)J * 256, wv);
+        ld4(v + 16 * J + c4, vv);
+        s += wv[0] * vv[0] + wv[1] * vv[1] + wv[2] * vv[2] + wv[3] * vv[3];
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if ((lane & 3) == 0 && 16 * I + r < n) out[16 * I + r] = s;
+    }
   }
 }
-// out = W' v over the first n rows, 4 lanes per output.
+// out = W' v over the first n rows.
 template <typename T>
 __device__ void tri_mv_t(const Work<T>& w, int n, const T* v, T* out) {
-  for (int base = 0; base < n; base += kQpThreads / 4) {
-    int p = base + threadIdx.x / 4;
-    int q = threadIdx.x & 3;
-    T s = T(0);
-    if (p < n)
-      for (int i = p + q; i < n; i += 4) s += w.mat[ep(i, p)] * v[i];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (p < n && q == 0) out[p] = s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = nblocks(n), r = lane >> 2, c4 = (lane & 3) * 4;
+  for (int job = wave; job < (nb + 1) / 2; job += kWaves) {
+    for (int half = 0; half < 2; ++half) {
+      const int J = half == 0 ? job : nb - 1 - job;
+      if (half == 1 && J == job) break;
+      T p[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+      for (int I = J; I < nb; ++I) {
+        T wv[4];
+        ld4(w.mat + bo(I, J) + r * 16 + c4, wv);
+        const T uv = v[16 * I + r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] += wv[k] * uv;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        p[k] += __shfl_xor(p[k], 4, 64);
+        p[k] += __shfl_xor(p[k], 8, 64);
+        p[k] += __shfl_xor(p[k], 16, 64);
+        p[k] += __shfl_xor(p[k], 32, 64);
+      }
+      if (lane < 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (16 * J + c4 + k < n) out[16 * J + c4 + k] = p[k];
+      }
+    }
   }
 }
 // out = K^{-1} v = W'(W v); uses w.tv as the intermediate.
@@ -406,14 +455,38 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
   return est;
 }
 
-// ||K||_1 (K symmetric: max column abs sum) from the block storage.
+// ||K||_1 (K symmetric: max column abs sum) from the lower block storage.
+// Column c sums |K_rc| over r >= c (block column c/16) and |K_cr| over r < c
+// (block row c/16); a wave takes one block column and one block row per job
+// (lanes: 16 columns x 4 row quarters), so the sum order is fixed.
 template <typename T>
 __device__ T knorm1(const Work<T>& w, int n) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = nblocks(n), cc = lane & 15, rq = lane >> 4;
   T nrm = T(0);
-  for (int c = threadIdx.x; c < n; c += kQpThreads) {
-    T cs = T(0);
-    for (int r = 0; r < n; ++r) cs += fabs(r >= c ? w.mat[ep(r, c)] : w.mat[ep(c, r)]);
-    nrm = max(nrm, cs);
+  for (int B = wave; B < nb; B += kWaves) {
+    T s = T(0);
+    // block column B: rows r >= c
+    for (int I = B; I < nb; ++I) {
+      const T* blk = w.mat + bo(I, B);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rr = 4 * rq + k;
+        if (I > B || rr >= cc) s += fabs(blk[rr * 16 + cc]);
+      }
+    }
+    // block row B: entries (c, r) with r < c, i.e. row c of blocks (B, J <= B)
+    for (int J = 0; J <= B; ++J) {
+      const T* blk = w.mat + bo(B, J);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rr = 4 * rq + k;  // column index inside the block
+        if (J < B || rr < cc) s += fabs(blk[cc * 16 + rr]);
+      }
+    }
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (16 * B + cc < n) nrm = max(nrm, s);
   }
   return block_max(nrm, w.red);
 }
@@ -517,10 +590,12 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   size_t off = 0;
   auto take = [&](size_t cnt) {
     T* p = sp + off;
-    off += (cnt + 1) & ~(size_t)1;
+    off += (cnt + 3) & ~(size_t)3;
     return p;
   };
-  w.x = take(n); w.xt = take(n); w.rhs = take(n); w.tv = take(n); w.ctv = take(n); w.gv = take(n); w.hx = take(n);
+  const int npad = kBS * nblocks(n);  // n-vectors are zero-padded for the block mat-vecs
+  w.x = take(npad); w.xt = take(npad); w.rhs = take(npad); w.tv = take(npad); w.ctv = take(npad);
+  w.gv = take(npad); w.hx = take(npad);
   w.z = take(m); w.y = take(m); w.lo = take(m); w.hi = take(m); w.rho = take(m); w.yprev = take(m);
   w.part = take(part_elems(n));
   w.red = take(64);
@@ -545,11 +620,9 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
     w.y[i] = T(0);
     w.yprev[i] = T(0);
   }
-  for (int i = threadIdx.x; i < n; i += kQpThreads) {
-    w.x[i] = T(0);
-    w.gv[i] = (T)a.g[i];
-    w.ctv[i] = T(0);
-  }
+  for (int i = threadIdx.x; i < 7 * npad; i += kQpThreads) w.x[i] = T(0);  // the 7 n-vectors are contiguous
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kQpThreads) w.gv[i] = (T)a.g[i];
   __syncthreads();
   // ---- finiteness of the data (H and Ct were checked by qp_prep_kernel; the
   // last pass of a solve clears that flag for the next call)
@@ -921,9 +994,9 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
 
 size_t lds_bytes(int n, int nc, size_t elem, bool mat) {
   const int m = n + nc;
-  auto r2 = [](size_t c) { return (c + 1) & ~(size_t)1; };
-  size_t e = 7 * r2(n) + 6 * r2(m) + r2(part_elems(n)) + 64 + 8;
-  if (mat) e += r2(bo(nblocks(n), 0));
+  auto r4 = [](size_t c) { return (c + 3) & ~(size_t)3; };
+  size_t e = 7 * r4((size_t)kBS * nblocks(n)) + 6 * r4(m) + r4(part_elems(n)) + 64 + 8;
+  if (mat) e += r4(bo(nblocks(n), 0));
   return e * elem;
 }
 
