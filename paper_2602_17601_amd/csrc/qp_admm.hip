@@ -52,10 +52,10 @@ __device__ inline double rho_rel(double l, double u) {
 constexpr int kBS = 16;
 __host__ __device__ inline int nblocks(int n) { return (n + kBS - 1) / kBS; }
 __host__ __device__ inline size_t bo(int I, int J) { return ((size_t)I * (I + 1) / 2 + J) * (kBS * kBS); }
-// per-wave partial sums of Ct' v, also the staging area of the block inverse
+// per-wave partial sums of Ct' v
 __host__ __device__ inline size_t part_elems(int n) {
-  const size_t a = (size_t)(kQpThreads / 64) * n, b = (size_t)(nblocks(n) - 1) * kBS * kBS;
-  return a > b ? a : b;
+  const size_t a = (size_t)(kQpThreads / 64) * n;
+  return a > 256 ? a : 256;  // also the 16x16 scratch of the diagonal-block factorization
 }
 __device__ inline size_t ep(int i, int j) { return bo(i >> 4, j >> 4) + (i & 15) * kBS + (j & 15); }
 
@@ -108,63 +108,88 @@ struct Work {
 
 typedef float qfloatx4 __attribute__((ext_vector_type(4)));
 
-// 16x16 block products in the MFMA C layout (lane l holds rows 4 (l >> 4) + i,
-// column l & 15): acc[i] += (A op(B))[row][col], op(B) = B^T if TRANS else B.
-// FP32 uses v_mfma_f32_16x16x4f32 (4 k-steps); FP64 uses the VALU.
+// 16x16 block products, row layout: lane l holds acc[t] = (A op(B))[l & 15][4 (l >> 4) + t],
+// op(B) = B' if TRANS else B; blocks are row-major.  FP32 runs the transposed
+// product on v_mfma_f32_16x16x4f32 with the k index permuted (step s takes
+// k = 4 (l >> 4) + s), so A rows, B' rows and the result are read and written
+// as 16-byte runs without LDS bank conflicts.  FP64 uses the VALU.
 template <bool TRANS>
 __device__ inline void bmma(float acc[4], const float* A, const float* B) {
   const int l = threadIdx.x & 63, r = l & 15, kq = l >> 4;
+  const float4 a4 = *reinterpret_cast<const float4*>(A + r * 16 + 4 * kq);
+  float b[4];
+  if (TRANS) {
+    const float4 b4 = *reinterpret_cast<const float4*>(B + r * 16 + 4 * kq);
+    b[0] = b4.x; b[1] = b4.y; b[2] = b4.z; b[3] = b4.w;
+  } else {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) b[st] = B[(4 * kq + st) * 16 + r];
+  }
+  const float av[4] = {a4.x, a4.y, a4.z, a4.w};
   qfloatx4 c = {acc[0], acc[1], acc[2], acc[3]};
 #pragma unroll
-  for (int kk = 0; kk < 16; kk += 4) {
-    const float av = A[r * 16 + kk + kq];
-    const float bv = TRANS ? B[r * 16 + kk + kq] : B[(kk + kq) * 16 + r];
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
-  }
+  for (int st = 0; st < 4; ++st) c = __builtin_amdgcn_mfma_f32_16x16x4f32(b[st], av[st], c, 0, 0, 0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = c[i];
 }
 template <bool TRANS>
 __device__ inline void bmma(double acc[4], const double* A, const double* B) {
-  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
 #pragma unroll 4
   for (int k = 0; k < 16; ++k) {
-    const double bv = TRANS ? B[c * 16 + k] : B[k * 16 + c];
+    const double av = A[r * 16 + k];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += A[(4 * g + i) * 16 + k] * bv;
+    for (int t = 0; t < 4; ++t) acc[t] += av * (TRANS ? B[(4 * g + t) * 16 + k] : B[k * 16 + 4 * g + t]);
   }
 }
 
-
-// Set-up over many workgroups, one lane per element of the block storage:
+// Set-up over many workgroups, one workgroup per 16x16 block (I, J <= I) of
+// the block storage and one lane per element:
 // G = diag(rho_rel of the box rows) + Ct' diag(rho_rel of the state rows) Ct
-// (FP64, fixed summation order, full symmetric, kept for refactorizations) and
+// (FP64, rows summed in order, full symmetric, kept for refactorizations) and
 // the first K = H + sigma I + rho G in the block storage; non-finite H or Ct
-// raise flag[1].
+// raise flag[1].  Column slices of Ct are staged through LDS 64 rows at a time.
+constexpr int kPrepRows = 64;
 template <typename Tin>
-__global__ void qp_prep_kernel(QpArgs<Tin> a, double* G) {
-  const int n = a.n, nb = nblocks(n);
-  const long total = (long)bo(nb, 0);
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int b = (int)(t >> 8), e = (int)(t & 255);
+__global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) {
+  __shared__ double ci[kPrepRows][16], cj[kPrepRows][16], rr[kPrepRows];
+  const int n = a.n;
+  const int b = blockIdx.x, e = threadIdx.x;
   int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= b) ++I;
   while (I * (I + 1) / 2 > b) --I;
   const int J = b - I * (I + 1) / 2;
   const int i = kBS * I + (e >> 4), j = kBS * J + (e & 15);
+  double sg = 0.0;
+  for (int r0 = 0; r0 < a.n_c; r0 += kPrepRows) {
+    __syncthreads();
+    for (int t = e; t < kPrepRows * 32; t += 256) {
+      const int rl = t >> 5, c = t & 31, r = r0 + rl;
+      const int col = c < 16 ? kBS * I + c : kBS * J + (c - 16);
+      const double v = (r < a.n_c && col < n) ? (double)a.Ct[(size_t)r * n + col] : 0.0;
+      if (c < 16) ci[rl][c] = v;
+      else cj[rl][c - 16] = v;
+    }
+    for (int t = e; t < kPrepRows; t += 256) {
+      const int r = r0 + t;
+      double rel = 0.0;
+      if (r < a.n_c) {
+        const double l = a.lc ? (double)a.lc[r] : -INFINITY;
+        const double u = a.uc ? (double)a.uc[r] : INFINITY;
+        rel = rho_rel(l, u);
+      }
+      rr[t] = rel;
+    }
+    __syncthreads();
+    const int nr = min(kPrepRows, a.n_c - r0);
+    for (int rl = 0; rl < nr; ++rl) sg += rr[rl] * ci[rl][e >> 4] * cj[rl][e & 15];
+  }
   double kv;
   if (j > i) {
     kv = 0.0;
   } else if (i >= n || j >= n) {
     kv = (i == j) ? 1.0 : 0.0;
   } else {
-    double sg = 0.0;
-    for (int r = 0; r < a.n_c; ++r) {
-      const double l = a.lc ? (double)a.lc[r] : -INFINITY;
-      const double u = a.uc ? (double)a.uc[r] : INFINITY;
-      sg += rho_rel(l, u) * (double)a.Ct[(size_t)r * n + i] * (double)a.Ct[(size_t)r * n + j];
-    }
     if (i == j) sg += rho_rel((double)a.lb[i], (double)a.ub[i]);
     G[(size_t)i * n + j] = sg;
     G[(size_t)j * n + i] = sg;
@@ -172,7 +197,7 @@ __global__ void qp_prep_kernel(QpArgs<Tin> a, double* G) {
     kv = h + a.rho * sg + (i == j ? a.sigma : 0.0);
     if (!isfinite(kv)) __hip_atomic_fetch_or(a.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  a.Kp[t] = kv;
+  a.Kp[(size_t)b * 256 + e] = kv;
 }
 
 // Four consecutive elements of a 16-byte aligned array.
@@ -289,129 +314,148 @@ __device__ T form_K(const QpArgs<Tin>& a, const Work<T>& w, T s) {
   return block_max(nrm, w.red);
 }
 
-// Right-looking blocked Cholesky of the block storage; false on a nonpositive pivot.
-// Per block column J: one wave factors the diagonal block in registers, one
-// lane per panel row solves against it, then the waves share the trailing
-// updates A_IK -= L_IJ L_KJ' (one 16x16 product per wave at a time).
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+
+// Cholesky factor of the 16x16 diagonal block at Dg (lower part) and its
+// inverse, by one wave; tmp is 256 elements of LDS.  Lane i < 16 holds row i;
+// each step publishes the scaled column through tmp and every lane reads it
+// back in 16-byte runs; then L goes to tmp and lane c forward-substitutes
+// column c of L^{-1}.  Writes L^{-1} (lower, zeros above) to Dg; false on a
+// nonpositive or non-finite pivot.
 template <typename T>
-__device__ bool cholesky(const Work<T>& w, int nb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ bool diag_factor_invert(T* Dg, T* tmp) {
+  const int lane = threadIdx.x & 63;
+  const bool act = lane < 16;
+  T a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = act ? Dg[lane * 16 + c] : T(0);
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (lane == j) tmp[16] = a[j];
+    __builtin_amdgcn_wave_barrier();
+    const T piv = tmp[16];
+    ok = ok && piv > T(0) && isfinite(piv);
+    const T d = sqrt(piv > T(0) ? piv : T(1));
+    const T inv = recip(d);
+    if (lane == j) a[j] = d;
+    else if (lane > j) a[j] *= inv;
+    if (act) tmp[lane] = a[j];
+    __builtin_amdgcn_wave_barrier();
+    T colv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) colv[k] = tmp[k];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k)
+      if (lane >= k) a[k] -= a[j] * colv[k];
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) tmp[lane * 16 + c] = c <= lane ? a[c] : T(0);
+  }
+  __builtin_amdgcn_wave_barrier();
+  T col[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    T sum = (r == lane) ? T(1) : T(0);
+#pragma unroll
+    for (int k = 0; k < r; ++k) sum -= tmp[r * 16 + k] * col[k];
+    col[r] = (r >= lane) ? sum * recip(tmp[r * 16 + r]) : T(0);
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Dg[r * 16 + lane] = col[r];
+  }
+  __builtin_amdgcn_wave_barrier();
+  return ok;
+}
+
+// C (block, row-major) = sgn * acc in the row layout of bmma, or C -= acc.
+template <typename T>
+__device__ inline void bstore(T* C, const T acc[4], T sgn) {
+  const int lane = threadIdx.x & 63;
+  T* p = C + (lane & 15) * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) p[t] = sgn * acc[t];
+}
+template <typename T>
+__device__ inline void bsub(T* C, const T acc[4]) {
+  const int lane = threadIdx.x & 63;
+  T* p = C + (lane & 15) * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) p[t] -= acc[t];
+}
+
+// In-place blocked Cholesky K = L L' fused with the inverse W = L^{-1}: with
+// L = L_0 L_1 ... L_{nb-1} (L_J the identity except block column J of L),
+// W = L_{nb-1}^{-1} ... L_0^{-1}, and step J applies L_J^{-1} to the rows J..
+// of the partial W while the Schur complement is updated:
+//   a. D = L_JJ^{-1} from the updated diagonal block (one wave); the other
+//      waves finish the previous column, W_{I,J-1} = -L_{I,J-1} D_{J-1}.
+//   b. panel L_IJ = K_IJ D' (I > J); W row J: W_JK <- D W_JK (K < J).
+//   c. trailing K_IK -= L_IJ L_KJ' (J < K <= I); W_IK -= L_IJ W_JK (I > J, K < J).
+// At the end block (I, K) holds W_IK.  False if K is not positive definite.
+template <typename T>
+__device__ bool factor_invert(const Work<T>& w, int nb) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int J = 0; J < nb; ++J) {
     T* D = w.mat + bo(J, J);
+    // ---- a
     if (wave == 0) {
-      T row[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) row[c] = lane < 16 ? D[lane * 16 + c] : T(0);
-      bool ok = true;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const T piv = __shfl(row[j], j, 64);
-        ok = ok && piv > T(0) && isfinite(piv);
-        const T d = sqrt(piv > T(0) ? piv : T(1));
-        if (lane == j) row[j] = d;
-        else if (lane > j) row[j] = row[j] / d;
-#pragma unroll
-        for (int c = j + 1; c < 16; ++c) {
-          const T lcj = __shfl(row[j], c, 64);
-          if (lane >= c) row[c] -= row[j] * lcj;
-        }
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) D[lane * 16 + c] = c <= lane ? row[c] : T(0);
-      }
+      const bool ok = diag_factor_invert(D, w.part);
       if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
+    } else if (J > 0) {
+      const T* Dp = w.mat + bo(J - 1, J - 1);
+      for (int I = J + wave - 1; I < nb; I += kWaves - 1) {
+        T acc[4] = {T(0), T(0), T(0), T(0)};
+        T* B = w.mat + bo(I, J - 1);
+        bmma<false>(acc, B, Dp);
+        __builtin_amdgcn_wave_barrier();
+        bstore(B, acc, T(-1));
+      }
     }
     __syncthreads();
     if (w.scal[0] < T(0)) return false;
-    const int m = nb - J - 1;
-    // panel: L_IJ = A_IJ L_JJ^{-T}, one lane per row
-    for (int t = threadIdx.x; t < m * 16; t += kQpThreads) {
-      T* rowp = w.mat + bo(J + 1 + t / 16, J) + (t % 16) * 16;
-      T x[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = rowp[c];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        T sum = x[c];
-#pragma unroll
-        for (int k = 0; k < c; ++k) sum -= x[k] * D[c * 16 + k];
-        x[c] = sum / D[c * 16 + c];
+    const int m = nb - 1 - J;
+    // ---- b: panel blocks (I, J), then W row J blocks (J, K < J)
+    for (int t = wave; t < m + J; t += kWaves) {
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      if (t < m) {
+        T* B = w.mat + bo(J + 1 + t, J);
+        bmma<true>(acc, B, D);
+        __builtin_amdgcn_wave_barrier();
+        bstore(B, acc, T(1));
+      } else {
+        T* B = w.mat + bo(J, t - m);
+        bmma<false>(acc, D, B);
+        __builtin_amdgcn_wave_barrier();
+        bstore(B, acc, T(1));
       }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) rowp[c] = x[c];
     }
     __syncthreads();
-    // trailing update over the block pairs (I, K), J < K <= I
+    // ---- c: trailing pairs, then W updates of the rows below J
     const int npairs = m * (m + 1) / 2;
-    for (int t = wave; t < npairs; t += kWaves) {
-      int ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-      while (ii * (ii + 1) / 2 > t) --ii;
-      const int kk = t - ii * (ii + 1) / 2;
-      const int I = J + 1 + ii, K = J + 1 + kk;
+    for (int t = wave; t < npairs + m * J; t += kWaves) {
       T acc[4] = {T(0), T(0), T(0), T(0)};
-      bmma<true>(acc, w.mat + bo(I, J), w.mat + bo(K, J));
-      T* C = w.mat + bo(I, K);
-      const int c = lane & 15, g = lane >> 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) C[(4 * g + i) * 16 + c] -= acc[i];
+      if (t < npairs) {
+        int ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+        while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+        while (ii * (ii + 1) / 2 > t) --ii;
+        const int kk = t - ii * (ii + 1) / 2;
+        const int I = J + 1 + ii, K = J + 1 + kk;
+        bmma<true>(acc, w.mat + bo(I, J), w.mat + bo(K, J));
+        bsub(w.mat + bo(I, K), acc);
+      } else {
+        const int u = t - npairs, I = J + 1 + u / J, K = u % J;
+        bmma<false>(acc, w.mat + bo(I, J), w.mat + bo(J, K));
+        bsub(w.mat + bo(I, K), acc);
+      }
     }
     __syncthreads();
   }
   return true;
-}
-
-// In-place W = L^{-1} on the block storage.  First every diagonal block is
-// inverted (one wave each, a column per lane); then block columns from the
-// right: W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, staged through w.part.
-template <typename T>
-__device__ void tri_invert(const Work<T>& w, int nb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int J = wave; J < nb; J += kWaves) {
-    T* D = w.mat + bo(J, J);
-    T col[16];
-    const int c = lane;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      T sum = (r == c) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < r; ++k) sum -= D[r * 16 + k] * ((k >= c) ? col[k] : T(0));
-      col[r] = (r >= c) ? sum / D[r * 16 + r] : T(0);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (c < 16) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) D[r * 16 + c] = col[r];
-    }
-  }
-  __syncthreads();
-  T* tmp = w.part;
-  for (int J = nb - 2; J >= 0; --J) {
-    const int m = nb - J - 1;
-    for (int t = wave; t < m; t += kWaves) {
-      const int I = J + 1 + t;
-      T x[4] = {T(0), T(0), T(0), T(0)};
-      for (int K = J + 1; K <= I; ++K) bmma<false>(x, w.mat + bo(I, K), w.mat + bo(K, J));
-      // stage X, then W_IJ = -X W_JJ
-      T* X = tmp + (size_t)t * 256;
-      const int cc = lane & 15, g = lane >> 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) X[(4 * g + i) * 16 + cc] = x[i];
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      T y[4] = {T(0), T(0), T(0), T(0)};
-      bmma<false>(y, X, w.mat + bo(J, J));
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-      for (int i = 0; i < 4; ++i) X[(4 * g + i) * 16 + cc] = -y[i];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < m * 256; t += kQpThreads) w.mat[bo(J + 1 + t / 256, J) + (t & 255)] = tmp[t];
-    __syncthreads();
-  }
 }
 
 // Hager's estimate of ||K^{-1}||_1 (K symmetric, so K^{-T} = K^{-1}).
@@ -494,14 +538,18 @@ __device__ T knorm1(const Work<T>& w, int n) {
 // Factor the K prepared by qp_prep_kernel and invert; false if not positive definite.
 template <typename T, typename Tin>
 __device__ bool factor_prepared(const QpArgs<Tin>& a, const Work<T>& w, T* knorm) {
-  const long total = (long)bo(nblocks(a.n), 0);
-  for (long t = threadIdx.x; t < total; t += kQpThreads) w.mat[t] = (T)a.Kp[t];
+  const long total2 = (long)bo(nblocks(a.n), 0) / 2;
+  const double2* src = reinterpret_cast<const double2*>(a.Kp);
+#pragma unroll 8
+  for (long t = threadIdx.x; t < total2; t += kQpThreads) {
+    const double2 v = src[t];
+    w.mat[2 * t] = (T)v.x;
+    w.mat[2 * t + 1] = (T)v.y;
+  }
   __syncthreads();
   *knorm = knorm1(w, a.n);
   __syncthreads();
-  if (!cholesky(w, nblocks(a.n))) return false;
-  tri_invert(w, nblocks(a.n));
-  return true;
+  return factor_invert(w, nblocks(a.n));
 }
 
 // Factor K(s) and invert; false if K is not positive definite.
@@ -509,9 +557,7 @@ template <typename T, typename Tin>
 __device__ bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
   *knorm = form_K(a, w, s);
   __syncthreads();
-  if (!cholesky(w, nblocks(a.n))) return false;
-  tri_invert(w, nblocks(a.n));
-  return true;
+  return factor_invert(w, nblocks(a.n));
 }
 
 
@@ -1035,7 +1081,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   unsigned char* ws = (unsigned char*)p->d_qp;
   const size_t nbo = bo(nblocks(n), 0);
   a.G = (const double*)ws;
-  a.gmat = (double*)(ws + sizeof(double) * (size_t)n * n);
+  a.gmat = (double*)(ws + (sizeof(double) * (size_t)n * n + 255) / 256 * 256);  // 256-byte aligned
   a.Kp = a.gmat + nbo;
   a.flag = p->d_qp_flag;
   a.rho = st->rho;
@@ -1047,7 +1093,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.max_iter = st->max_iter;
   a.check_every = st->check_every;
   phase_begin(p, GNMPC_PH_QP, s);
-  qp_prep_kernel<Tin><<<ceil_div((long)nbo, 256), 256, 0, s>>>(a, (double*)ws);
+  qp_prep_kernel<Tin><<<(int)(nbo / 256), 256, 0, s>>>(a, (double*)ws);
   gnmpc_status rc;
   if (sizeof(Tin) == 8) {
     rc = launch_pass<double, Tin>(p, a, 2, s);
@@ -1065,7 +1111,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
 
 size_t qp_workspace_bytes(int n, int n_c) {
   (void)n_c;
-  return sizeof(double) * ((size_t)n * n + 2 * bo(nblocks(n), 0) + 64);
+  return (sizeof(double) * (size_t)n * n + 255) / 256 * 256 + sizeof(double) * (2 * bo(nblocks(n), 0) + 64);
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
