@@ -139,16 +139,21 @@ def main():
                           settings=settings)
 
     def timed(plan, b):
+        """Throughput over exactly args.steps steps with no event records in
+        the stream; then the same number of steps again with the per-phase
+        HIP-event timers on (the events add gaps, so they stay out of `value`)."""
         for _ in range(args.warmup):
             step(plan, b)
-        torch.cuda.synchronize()
-        plan.timers_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(plan, b)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        plan.timers_enable(True)
+        for _ in range(args.steps):
+            step(plan, b)
+        torch.cuda.synchronize()
         phases = plan.timers_read()
         plan.timers_enable(False)
         return el, phases

@@ -229,6 +229,7 @@ void gnmpc_plan_destroy(gnmpc_plan* p) {
   dfree(p->d_pcol);
   dfree(p->d_erow);
   dfree(p->d_diag);
+  prop_blocks_free(p);
   dfree(p->d_act_of_node);
   dfree(p->d_row_node);
   dfree(p->d_row_stage);
@@ -278,6 +279,7 @@ gnmpc_status gnmpc_graph_set(gnmpc_plan* p, const int32_t* row_ptr, const int32_
   if ((s = upload(p, p->d_pcol, pcol.data(), pcol.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_erow, erow.data(), erow.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_diag, diag.data(), diag.size())) != GNMPC_OK) return s;
+  if ((s = prop_blocks_build(p)) != GNMPC_OK) return s;
   p->graph_ready = true;
   p->model = 0;  // a model must be (re)bound to the new graph
   return GNMPC_OK;

@@ -15,6 +15,7 @@
 // Constraint rows (stacked-constraint formula of Sec. V-B):
 // Ct[t] = C_t S^{i_t}_{k_t}, dt[t] = d_t - C_t Gx^{i_t}_{k_t}.
 #include <algorithm>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -88,6 +89,125 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
   }
 }
 
+// Block propagation: a workgroup takes pb_nodes consecutive nodes and a
+// slice of kPropCW columns; the S_k rows of the union of their pattern
+// columns are staged in LDS once (the rows a chain neighbourhood shares are
+// read from L2 once instead of once per node), with the nodes' A blocks.
+// Thread: one node and one column.  Slice 0 also does Gx.
+constexpr int kPropCW = 64;
+constexpr int kStageBatch = 8;
+__device__ inline void ld4v(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ inline void ld4v(const double* p, double (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+template <typename T>
+__global__ void __launch_bounds__(256)
+sprop_block_kernel(int k, int M, int nu, int nbn, const int32_t* __restrict__ prow, const int32_t* __restrict__ pcol,
+                   const int32_t* __restrict__ ubeg, const int32_t* __restrict__ ulist,
+                   const int32_t* __restrict__ epos, const T* __restrict__ A_k, const T* __restrict__ B_k,
+                   const T* __restrict__ c_k, const T* __restrict__ S_in, T* __restrict__ S_out,
+                   const T* __restrict__ Gx_in, T* __restrict__ Gx_out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pb[];
+  const int b = blockIdx.x, c0 = blockIdx.y * kPropCW;
+  const int node0 = b * nbn, nn = min(nbn, M - node0);
+  const int cin = k * nu, cout = cin + nu;
+  const int ub = ubeg[b], uc = ubeg[b + 1] - ub;
+  const int e0 = prow[node0], ne = prow[node0 + nn] - e0;
+  const int cw = max(0, min(kPropCW, cin - c0));  // staged columns of S_k
+  T* Ss = reinterpret_cast<T*>(smem_pb);          // [uc][6][kPropCW]
+  T* As = Ss + (size_t)uc * NBX * kPropCW;        // [ne][36]
+  T* Gs = As + (size_t)ne * 36;                   // [uc][6] (chunk 0)
+  int32_t* Es = reinterpret_cast<int32_t*>(Gs + (size_t)uc * NBX);  // [ne] union position of each entry
+  int32_t* Rs = Es + ne;                                             // [nn + 1] row starts (relative)
+  int32_t* Us = Rs + nn + 1;                                         // [uc] union nodes
+  for (int t = threadIdx.x; t < uc; t += 256) Us[t] = ulist[ub + t];
+  for (int t = threadIdx.x; t <= nn; t += 256) Rs[t] = prow[node0 + t] - e0;
+  // every staging loop keeps kStageBatch loads in flight per lane
+  for (int t0 = threadIdx.x; t0 < ne * 36; t0 += 256 * kStageBatch) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + 256 * u;
+      v[u] = t < ne * 36 ? A_k[(size_t)e0 * 36 + t] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (t0 + 256 * u < ne * 36) As[t0 + 256 * u] = v[u];
+  }
+  for (int t = threadIdx.x; t < ne; t += 256) Es[t] = epos[e0 + t];
+  __syncthreads();
+  if (cw > 0) {
+    // 4 rows of kPropCW columns per pass of 256 lanes
+    const int c = threadIdx.x % kPropCW, rq = threadIdx.x / kPropCW;
+    for (int row0 = rq; row0 < uc * NBX; row0 += 4 * kStageBatch) {
+      T v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int row = row0 + 4 * u;
+        const bool ok = row < uc * NBX && c < cw;
+        const int uu = ok ? row / NBX : 0, sr = ok ? row - uu * NBX : 0;
+        v[u] = ok ? S_in[((size_t)Us[uu] * NBX + sr) * cin + c0 + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (row0 + 4 * u < uc * NBX) Ss[(size_t)(row0 + 4 * u) * kPropCW + c] = v[u];
+    }
+  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < uc * NBX; t += 256) Gs[t] = Gx_in[(size_t)Us[t / NBX] * NBX + t % NBX];
+  __syncthreads();
+  // one thread per (node, column) of the slice
+  for (int it = threadIdx.x; it < nn * kPropCW; it += 256) {
+    const int ln = it / kPropCW, cl = it - ln * kPropCW, col = c0 + cl, i = node0 + ln;
+    if (col >= cout) continue;
+    if (col < cin) {
+      T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      const int rs = Rs[ln], w = Rs[ln + 1] - rs;
+      for (int e = 0; e < w; ++e) {
+        const T* Ae = As + (size_t)(rs + e) * 36;
+        const T* Su = Ss + (size_t)Es[rs + e] * NBX * kPropCW + cl;
+        T sv[6], av[36];
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) sv[sr] = Su[sr * kPropCW];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ld4v(Ae + 4 * q, *reinterpret_cast<T(*)[4]>(av + 4 * q));
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int sr = 0; sr < 6; ++sr) o[r] += av[r * 6 + sr] * sv[sr];
+      }
+#pragma unroll
+      for (int r = 0; r < 6; ++r) S_out[((size_t)i * NBX + r) * cout + col] = o[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+        S_out[((size_t)i * NBX + r) * cout + col] = B_k[((size_t)i * NBX + r) * nu + (col - cin)];
+    }
+  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < nn * NBX; t += 256) {
+      const int ln = t / NBX, r = t - ln * NBX, i = node0 + ln;
+      T v = T(0);
+      for (int e = Rs[ln]; e < Rs[ln + 1]; ++e) {
+        const T* Ae = As + (size_t)e * 36 + r * 6;
+        const T* xj = Gs + (size_t)Es[e] * NBX;
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) v += Ae[sr] * xj[sr];
+      }
+      Gx_out[(size_t)i * NBX + r] = v + c_k[(size_t)i * NBX + r];
+    }
+}
+
 // ---------------------------------------------------------------- Gram + gradient
 // H: 32x32 output tiles of the lower triangle, one workgroup per (tile, stage,
 // row chunk); each of the 4 waves owns a 16x16 quarter and runs
@@ -151,14 +271,40 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
     for (int y = 0; y < 2; ++y) acc[x][y] = cfloatx4{0.f, 0.f, 0.f, 0.f};
   // this wave's quarter may lie entirely past the live columns
   const bool live = kT * ta + qa < cols && kT * tb + qb < cols;
+  // staging: thread t owns column cc = t % kT of rows t / kT + 4 u (u < kRB / 4); with a
+  // diagonal Q the next row block is loaded into registers while this one is multiplied
+  constexpr int kPer = kRB * kT / 256;
+  const int cc = threadIdx.x % kT, rr0 = threadIdx.x / kT;
+  const int ca = kT * ta + cc, cb = kT * tb + cc;
+  float pa[kPer], pb[kPer], pq[kPer];
+  auto fetch = [&](int rb) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int r = rb + rr0 + 4 * u;
+      const bool vr = r < r1;
+      pa[u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
+      pb[u] = (vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
+      pq[u] = vr ? Qk[r] : 0.f;
+    }
+  };
+  if (!Q_full) fetch(r0);
   for (int rb = r0; rb < r1; rb += kRB) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kRB * kT; t += 256) {
-      const int rr = t / kT, cc = t % kT, r = rb + rr;
-      const int ca = kT * ta + cc, cb = kT * tb + cc;
-      const bool vr = r < r1;
-      As[rr][cc] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
-      Bs[rr][cc] = (vr && cb < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb) : 0.f;
+    if (!Q_full) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        As[rr0 + 4 * u][cc] = pa[u];
+        Bs[rr0 + 4 * u][cc] = pq[u] * pb[u];
+      }
+      if (rb + kRB < r1) fetch(rb + kRB);
+    } else {
+      for (int t = threadIdx.x; t < kRB * kT; t += 256) {
+        const int rr = t / kT, c2 = t % kT, r = rb + rr;
+        const int ca2 = kT * ta + c2, cb2 = kT * tb + c2;
+        const bool vr = r < r1;
+        As[rr][c2] = (vr && ca2 < cols) ? Sk[(size_t)r * cols + ca2] : 0.f;
+        Bs[rr][c2] = (vr && cb2 < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb2) : 0.f;
+      }
     }
     __syncthreads();
     if (live) {
@@ -348,13 +494,28 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   phase_begin(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
   copy_kernel<T><<<ceil_div((long)M * NBX, 256), 256, 0, s>>>((const T*)x0, G, (long)M * NBX);
   const int wmax = p->wmax;
+  const size_t pb_lds = sizeof(T) * ((size_t)p->pb_umax * NBX * (kPropCW + 1) + (size_t)p->pb_emax * 36) +
+                        sizeof(int32_t) * ((size_t)p->pb_emax + p->pb_nodes + 1 + p->pb_umax);
+  const bool use_blocks = p->pb_nodes > 0 && pb_lds <= 64 * 1024;
+  if (use_blocks)
+    GNMPC_HIP_TRY(p, set_max_lds((const void*)sprop_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)pb_lds));
   for (int k = 0; k < N; ++k) {
+    const T* S_in = k ? S + S_offset(k, M, nu) : nullptr;
+    if (use_blocks) {
+      dim3 grid(p->pb_count, ceil_div((k + 1) * nu, kPropCW));
+      sprop_block_kernel<T><<<grid, 256, pb_lds, s>>>(
+          k, M, nu, p->pb_nodes, p->d_prow, p->d_pcol, p->d_pb_ubeg, p->d_pb_ulist, p->d_pb_epos,
+          (const T*)A + (size_t)k * p->nnz * 36, (const T*)B + (size_t)k * M * NBX * nu,
+          (const T*)c + (size_t)k * M * NBX, S_in, S + S_offset(k + 1, M, nu), G + (size_t)k * M * NBX,
+          G + (size_t)(k + 1) * M * NBX);
+      continue;
+    }
     int ncol = (k + 1) * nu + 1;
     int npw = std::max(1, kPropThreads / ncol);
     int lds_cap = (int)(48 * 1024 / (sizeof(T) * 36 * wmax));
     npw = std::max(1, std::min(npw, lds_cap));
     size_t lds = sizeof(T) * 36 * (size_t)wmax * npw + sizeof(int32_t) * ((size_t)wmax * npw + npw + 1);
-    const T* S_in = k ? S + S_offset(k, M, nu) : nullptr;
     sprop_kernel<T><<<ceil_div(M, npw), kPropThreads, lds, s>>>(
         k, M, nu, npw, p->d_prow, p->d_pcol, (const T*)A + (size_t)k * p->nnz * 36,
         (const T*)B + (size_t)k * M * NBX * nu, (const T*)c + (size_t)k * M * NBX, S_in,
@@ -392,6 +553,60 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
 }
 
 }  // namespace
+
+void prop_blocks_free(gnmpc_plan* p) {
+  for (int32_t** q : {&p->d_pb_ubeg, &p->d_pb_ulist, &p->d_pb_epos})
+    if (*q) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
+  p->pb_nodes = p->pb_count = p->pb_umax = p->pb_emax = 0;
+}
+
+// Node blocks for the block propagation kernel: the largest block size (4, 2,
+// 1 nodes: one thread per node and column of a 64-column slice) whose staged
+// union and A blocks fit 64 KB of LDS in the plan's precision; pb_nodes = 0 if
+// even single nodes do not fit.
+gnmpc_status prop_blocks_build(gnmpc_plan* p) {
+  prop_blocks_free(p);
+  const int M = p->M;
+  const size_t elem = (size_t)p->elem;
+  for (int nb = 4; nb >= 1; nb /= 2) {
+    std::vector<int32_t> ubeg(1, 0), ulist, epos(p->h_pcol.size());
+    int umax = 0, emax = 0;
+    for (int node0 = 0; node0 < M; node0 += nb) {
+      const int node1 = std::min(M, node0 + nb);
+      const int e0 = p->h_prow[node0], e1 = p->h_prow[node1];
+      std::vector<int32_t> u(p->h_pcol.begin() + e0, p->h_pcol.begin() + e1);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      for (int e = e0; e < e1; ++e)
+        epos[e] = (int32_t)(std::lower_bound(u.begin(), u.end(), p->h_pcol[e]) - u.begin());
+      ulist.insert(ulist.end(), u.begin(), u.end());
+      ubeg.push_back((int32_t)ulist.size());
+      umax = std::max(umax, (int)u.size());
+      emax = std::max(emax, e1 - e0);
+    }
+    if (elem * ((size_t)umax * NBX * (kPropCW + 1) + (size_t)emax * 36) + 4 * ((size_t)emax + nb + 1 + umax) >
+        64 * 1024)
+      continue;
+    auto up = [&](int32_t*& dst, const std::vector<int32_t>& v) -> gnmpc_status {
+      GNMPC_HIP_TRY(p, hipMalloc((void**)&dst, sizeof(int32_t) * std::max<size_t>(v.size(), 1)));
+      if (!v.empty()) GNMPC_HIP_TRY(p, hipMemcpy(dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
+      return GNMPC_OK;
+    };
+    gnmpc_status st;
+    if ((st = up(p->d_pb_ubeg, ubeg)) != GNMPC_OK) return st;
+    if ((st = up(p->d_pb_ulist, ulist)) != GNMPC_OK) return st;
+    if ((st = up(p->d_pb_epos, epos)) != GNMPC_OK) return st;
+    p->pb_nodes = nb;
+    p->pb_count = (int)ubeg.size() - 1;
+    p->pb_umax = umax;
+    p->pb_emax = emax;
+    return GNMPC_OK;
+  }
+  return GNMPC_OK;
+}
 
 size_t condense_partial_elems(int M, int nu, int N) {
   GramShape sh = gram_shape(M, nu, N);

@@ -22,6 +22,11 @@ struct gnmpc_plan {
   std::vector<int32_t> h_row_ptr, h_col, h_prow, h_pcol;
   int32_t *d_row_ptr = nullptr, *d_col = nullptr;
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_erow = nullptr, *d_diag = nullptr;
+  // propagation blocks: pb_nodes consecutive nodes per block, the union of
+  // their pattern columns (ulist, block b at ubeg[b]) and, per pattern entry,
+  // the position of its column in its block's union (epos)
+  int pb_nodes = 0, pb_count = 0, pb_umax = 0, pb_emax = 0;
+  int32_t *d_pb_ubeg = nullptr, *d_pb_ulist = nullptr, *d_pb_epos = nullptr;
 
   // model
   int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN
@@ -106,6 +111,8 @@ gnmpc_status launch_condense(gnmpc_plan* p, const void* A, const void* B, const 
                              void* Gx, hipStream_t s);
 // qp_admm.hip
 size_t qp_workspace_bytes(int n, int n_c);
+gnmpc_status prop_blocks_build(gnmpc_plan* p);
+void prop_blocks_free(gnmpc_plan* p);
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
                        int n_c, const void* Ct, const void* lc, const void* uc,
                        const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
