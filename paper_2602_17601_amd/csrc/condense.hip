@@ -251,9 +251,12 @@ __device__ inline T qs_value(const T* Sk, const T* Qk, int Q_full, int cols, int
 constexpr int kRB = 32;
 __global__ void __launch_bounds__(256)
 gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __restrict__ Q, int Q_full,
-                float* __restrict__ part) {
+                const float* __restrict__ Gx_all, const float* __restrict__ q, float* __restrict__ part,
+                float* __restrict__ gpart) {
   __shared__ float As[kRB][kT + 4];
   __shared__ float Bs[kRB][kT + 4];
+  __shared__ float Ws[kRB];        // w = Q_k Gx_k + q_k of the staged rows (diagonal tiles)
+  __shared__ float Gp[4][kT];      // gradient partials of the 4 row quarters
   const int k = blockIdx.y + 1, chunk = blockIdx.z;
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
@@ -261,6 +264,10 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   const int cols = k * sh.nu, rows = NBX * sh.M;
   const float* Sk = S_all + S_offset(k, sh.M, sh.nu);
   const float* Qk = Q + (size_t)k * sh.M * NBX * (Q_full ? NBX : 1);
+  const float* Gxk = Gx_all + (size_t)k * sh.M * NBX;
+  const float* qk = q + (size_t)k * sh.M * NBX;
+  const bool diag = ta == tb;
+  float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT, rows 8 (threadIdx.x / kT) .. +7 of each block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int qa = 32 * (wave >> 1), qb = 32 * (wave & 1);
   const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
@@ -276,7 +283,8 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   constexpr int kPer = kRB * kT / 256;
   const int cc = threadIdx.x % kT, rr0 = threadIdx.x / kT;
   const int ca = kT * ta + cc, cb = kT * tb + cc;
-  float pa[kPer], pb[kPer], pq[kPer];
+  float pa[kPer], pb[kPer], pq[kPer], pw = 0.f;
+  // lanes with threadIdx.x < kRB also fetch w for row rb + threadIdx.x (diagonal tiles)
   auto fetch = [&](int rb) {
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -285,6 +293,10 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
       pa[u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
       pb[u] = (vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
       pq[u] = vr ? Qk[r] : 0.f;
+    }
+    if (diag && threadIdx.x < kRB) {
+      const int r = rb + threadIdx.x;
+      pw = r < r1 ? Qk[r] * Gxk[r] + qk[r] : 0.f;
     }
   };
   if (!Q_full) fetch(r0);
@@ -296,6 +308,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
         As[rr0 + 4 * u][cc] = pa[u];
         Bs[rr0 + 4 * u][cc] = pq[u] * pb[u];
       }
+      if (diag && threadIdx.x < kRB) Ws[threadIdx.x] = pw;
       if (rb + kRB < r1) fetch(rb + kRB);
     } else {
       for (int t = threadIdx.x; t < kRB * kT; t += 256) {
@@ -305,8 +318,24 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
         As[rr][c2] = (vr && ca2 < cols) ? Sk[(size_t)r * cols + ca2] : 0.f;
         Bs[rr][c2] = (vr && cb2 < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb2) : 0.f;
       }
+      if (diag && threadIdx.x < kRB) {
+        const int r = rb + threadIdx.x;
+        float wv = 0.f;
+        if (r < r1) {
+          const int node = r / NBX, rr = r - node * NBX;
+          const float* Qn = Qk + ((size_t)node * NBX + rr) * NBX;
+#pragma unroll
+          for (int s2 = 0; s2 < NBX; ++s2) wv += Qn[s2] * Gxk[(size_t)node * NBX + s2];
+          wv += qk[r];
+        }
+        Ws[threadIdx.x] = wv;
+      }
     }
     __syncthreads();
+    if (diag) {
+#pragma unroll
+      for (int u = 0; u < kRB / 4; ++u) gacc += As[8 * rr0 + u][cc] * Ws[8 * rr0 + u];
+    }
     if (live) {
 #pragma unroll
       for (int kk = 0; kk < kRB; kk += 4) {
@@ -321,6 +350,13 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
           for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
       }
     }
+  }
+  if (diag) {
+    Gp[rr0][cc] = gacc;
+    __syncthreads();
+    if (threadIdx.x < kT)
+      gpart[(((size_t)ta * sh.N + (k - 1)) * sh.nchunks + chunk) * kT + threadIdx.x] =
+          ((Gp[0][threadIdx.x] + Gp[1][threadIdx.x]) + Gp[2][threadIdx.x]) + Gp[3][threadIdx.x];
   }
   // C layout: lane holds rows 4 (lane >> 4) + i of each 16x16 tile, column lane & 15
   float* out = part + (((size_t)blockIdx.x * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
@@ -405,14 +441,28 @@ __global__ void gvec_fold_kernel(GramShape sh, const T* __restrict__ gpart, T* _
 }
 
 // One lane per element of the lower triangle (and g): fixed-order sum of the
-// partials over stages and chunks, plus R (or r), mirrored to the upper triangle.
+// partials over stages and chunks (chunk loads batched 8 at a time), plus R
+// (or r), mirrored to the upper triangle.  g comes from per-stage sums
+// (gstage, [N][n]) or, when gtile is set, from the per-(tile, stage, chunk)
+// partials of the diagonal Gram tiles ([nt][N][nchunks][kT]).
 template <typename T>
 __global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, const T* __restrict__ gstage,
-                                   const T* __restrict__ R, const T* __restrict__ r, T* __restrict__ H,
-                                   T* __restrict__ g) {
+                                   const T* __restrict__ gtile, const T* __restrict__ R, const T* __restrict__ r,
+                                   T* __restrict__ H, T* __restrict__ g) {
   const int n = sh.n;
   const long nlow = (long)n * (n + 1) / 2;
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  auto chunk_sum = [&](const T* base, size_t stride) {
+    T s = T(0);
+    for (int c0 = 0; c0 < sh.nchunks; c0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c0 + u < sh.nchunks ? base[(size_t)(c0 + u) * stride] : T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    return s;
+  };
   if (t < nlow) {
     int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((long)(a + 1) * (a + 2) / 2 <= t) ++a;
@@ -423,8 +473,7 @@ __global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, con
     int e = (a % kT) * kT + (b % kT);
     T s = T(0);
     for (int k = a / sh.nu + 1; k <= sh.N; ++k)
-      for (int ch = 0; ch < sh.nchunks; ++ch)
-        s += part[((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks + ch) * (kT * kT) + e];
+      s += chunk_sum(part + ((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks) * (kT * kT) + e, (size_t)kT * kT);
     int ka = a / sh.nu, kb = b / sh.nu;
     if (ka == kb) s += R[((size_t)ka * sh.nu + (a % sh.nu)) * sh.nu + (b % sh.nu)];
     H[(size_t)a * n + b] = s;
@@ -432,7 +481,13 @@ __global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, con
   } else if (t < nlow + n) {
     int a = (int)(t - nlow);
     T s = T(0);
-    for (int k = a / sh.nu + 1; k <= sh.N; ++k) s += gstage[(size_t)(k - 1) * n + a];
+    if (gtile) {
+      const int ta = a / kT;
+      for (int k = a / sh.nu + 1; k <= sh.N; ++k)
+        s += chunk_sum(gtile + (((size_t)ta * sh.N + (k - 1)) * sh.nchunks) * kT + a % kT, (size_t)kT);
+    } else {
+      for (int k = a / sh.nu + 1; k <= sh.N; ++k) s += gstage[(size_t)(k - 1) * n + a];
+    }
     g[a] = s + r[a];
   }
 }
@@ -527,16 +582,21 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   T* part = (T*)p->d_part;
   T* gpart = part + (size_t)sh.ntiles * N * sh.nchunks * kT * kT;
   dim3 grid(sh.ntiles, N, sh.nchunks);
-  if (sizeof(T) == 4)
-    gram_kernel_f32<<<grid, 256, 0, s>>>(sh, (const float*)S, (const float*)Q, Q_full, (float*)part);
-  else
-    gram_kernel_f64<<<grid, 256, 0, s>>>(sh, (const double*)S, (const double*)Q, Q_full, (double*)part);
-  gvec_kernel<T><<<dim3(N, sh.ngchunks), 256, 0, s>>>(sh, S, G, (const T*)Q, Q_full, (const T*)q, gpart);
   T* gstage = gpart + (size_t)N * sh.ngchunks * sh.n;
-  gvec_fold_kernel<T><<<ceil_div((long)N * sh.n, 256), 256, 0, s>>>(sh, gpart, gstage);
+  const T* gtile = nullptr;
+  if (sizeof(T) == 4) {
+    // the gradient partials come from the diagonal Gram tiles
+    gram_kernel_f32<<<grid, 256, 0, s>>>(sh, (const float*)S, (const float*)Q, Q_full, (const float*)G,
+                                         (const float*)q, (float*)part, (float*)gpart);
+    gtile = gpart;
+  } else {
+    gram_kernel_f64<<<grid, 256, 0, s>>>(sh, (const double*)S, (const double*)Q, Q_full, (double*)part);
+    gvec_kernel<T><<<dim3(N, sh.ngchunks), 256, 0, s>>>(sh, S, G, (const T*)Q, Q_full, (const T*)q, gpart);
+    gvec_fold_kernel<T><<<ceil_div((long)N * sh.n, 256), 256, 0, s>>>(sh, gpart, gstage);
+  }
   long nred = (long)sh.n * (sh.n + 1) / 2 + sh.n;
-  gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, part, gstage, (const T*)R, (const T*)r, (T*)H,
-                                                            (T*)g);
+  gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, part, gstage, gtile, (const T*)R, (const T*)r,
+                                                            (T*)H, (T*)g);
   phase_end(p, GNMPC_PH_CONDENSE_GRAM, s);
   if (p->n_c > 0) {
     phase_begin(p, GNMPC_PH_CONDENSE_ROWS, s);
@@ -610,7 +670,11 @@ gnmpc_status prop_blocks_build(gnmpc_plan* p) {
 
 size_t condense_partial_elems(int M, int nu, int N) {
   GramShape sh = gram_shape(M, nu, N);
-  return (size_t)sh.ntiles * N * sh.nchunks * kT * kT + (size_t)N * sh.ngchunks * sh.n + (size_t)N * sh.n;
+  // H partials, then either the gradient partials of the diagonal tiles (FP32) or the
+  // per-chunk gradient partials and their per-stage sums (FP64)
+  const size_t gt = (size_t)sh.nt * N * sh.nchunks * kT;
+  const size_t gv = (size_t)N * sh.ngchunks * sh.n + (size_t)N * sh.n;
+  return (size_t)sh.ntiles * N * sh.nchunks * kT * kT + std::max(gt, gv);
 }
 
 gnmpc_status launch_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
