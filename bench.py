@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB 5 times (the reference kernel "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
@@ -100,6 +103,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_mib:
+        nb = args.copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}), flush=True)
+        return
     from paper_2602_17601_amd import gnmpc as gn
     from paper_2602_17601_amd import workloads as wl
 

@@ -418,6 +418,13 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
 // LDS columns are XOR-swizzled in 16-byte chunks by (column & 7), so the 16
 // lanes that read one k-slice of 16 different columns hit different banks.
 __device__ inline int swz(int byte_in_col, int c) { return (((byte_in_col >> 4) ^ (c & 7)) << 4) | (byte_in_col & 15); }
+// The same over all 16 chunks of a 256-byte column (16 lanes reading 16 columns
+// hit 16 different chunk positions), for columns of 128 bf16 features.
+template <int CB>
+__device__ inline int swzc(int byte_in_col, int c) {
+  constexpr int mask = CB >= 256 ? 15 : 7;
+  return (((byte_in_col >> 4) ^ (c & mask)) << 4) | (byte_in_col & 15);
+}
 
 template <int MT>
 __global__ void __launch_bounds__(256) jvp_mfma_kernel(MfmaArgs a) {
@@ -793,7 +800,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         const uint32_t b1 = (valid && ((bits >> (2 * h + 1)) & 1u)) ? (__float_as_uint(ev[2 * h + 1]) & 0xFFFF0000u) : 0u;
         pk[h] = b0 | b1;
       }
-      *reinterpret_cast<uint4*>(R1 + ((size_t)q * kCols + c) * CB + swz(16 * fc, c)) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+      *reinterpret_cast<uint4*>(R1 + ((size_t)q * kCols + c) * CB + swzc<CB>(16 * fc, c)) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
   }
   for (int t = threadIdx.x; t < a.stage_words / 4; t += NT)
@@ -826,7 +833,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB;
       bf16x8_t bfr[KB];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swz(64 * kb + 16 * grp, col));
+      for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swzc<CB>(64 * kb + 16 * grp, col));
       const uint4 hd = rec4[0];
       const uint4 t0 = rec4[1 + 4 * mw], t1 = rec4[2 + 4 * mw], t2 = rec4[3 + 4 * mw], t3 = rec4[4 + 4 * mw];
       const uint32_t cw = reinterpret_cast<const uint32_t*>(rec4)[4 + 16 * HW + (f0 >> 2)];
@@ -857,7 +864,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       }
     }
     {
-      unsigned char* AGw = AG + (size_t)col * CB + swz(2 * f0, col);
+      unsigned char* AGw = AG + (size_t)col * CB + swzc<CB>(2 * f0, col);
 #pragma unroll
       for (int q = 0; q < MAXV; ++q) {
         if (q < vc1) {
@@ -895,8 +902,8 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         if (self >= 0) {
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb) {
-            const bf16x8_t bs = *reinterpret_cast<const bf16x8_t*>(Ts + swz(64 * kb + 16 * grp, col));
-            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col));
+            const bf16x8_t bs = *reinterpret_cast<const bf16x8_t*>(Ts + swzc<CB>(64 * kb + 16 * grp, col));
+            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swzc<CB>(64 * kb + 16 * grp, col));
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
               c1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m][kb], bs, c1[m], 0, 0, 0);
@@ -906,7 +913,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         } else {
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb) {
-            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swz(64 * kb + 16 * grp, col));
+            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swzc<CB>(64 * kb + 16 * grp, col));
 #pragma unroll
             for (int m = 0; m < 2; ++m) c2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c2[m], 0, 0, 0);
           }
@@ -923,7 +930,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     __syncthreads();
     if (l < a.L) {
       unsigned char* R1g = R1 + ((size_t)ng * kCols + col) * CB;
-      const int sw0 = swz(2 * (wg * 32 + 4 * grp), col), sw1 = swz(2 * (wg * 32 + 16 + 4 * grp), col);
+      const int sw0 = swzc<CB>(2 * (wg * 32 + 4 * grp), col), sw1 = swzc<CB>(2 * (wg * 32 + 16 + 4 * grp), col);
 #pragma unroll
       for (int j = 0; j < MAXV / 2; ++j) {
         const int q = 2 * j + ng;
