@@ -63,9 +63,10 @@ struct GnnState {
   uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
   uint8_t* cnt = nullptr;         // [L][N][M][Hd] active in-edges of each node per feature
   int n_ftiles = 0, fedge_cap = 0;
-  int32_t *fcols = nullptr;       // [n_ftiles][16] node of each column (-1 = empty)
+  int32_t *fcols = nullptr;       // [n_ftiles][NC] node of each column (-1 = empty)
   int32_t *fmeta = nullptr;       // [n_ftiles][4]: targets, edge begin, edge count, -
-  int32_t *fecnt = nullptr;       // [n_ftiles][16] in-edges of each target column
+  int32_t *fecnt = nullptr;       // [n_ftiles][NC] in-edges of each target column
+  int32_t *fepre = nullptr;       // [n_ftiles][NC] edges of the columns before it (exclusive prefix)
   int32_t *fesrc = nullptr, *feid = nullptr;  // per edge: source column, CSR edge id
   std::vector<void*> allocs;
 };
@@ -1069,24 +1070,31 @@ struct FwdMfmaArgs {
   const float *be, *bn;                 // this round's biases
   uint32_t *mask_edge, *mask_node;      // this round, all stages
   uint8_t* cnt;                         // this round, all stages: active in-edges per (node, feature)
-  const int32_t *fcols, *fmeta, *fecnt, *fesrc, *feid;
+  const int32_t *fcols, *fmeta, *fecnt, *fepre, *fesrc, *feid;
 };
+
+// Column tiles of the forward pass hold kFwdCT * 16 node columns (Hd <= 128;
+// Hd = 256 uses one 16-column group): the weight fragments a wave loads feed
+// kFwdCT MFMA column groups.
+constexpr int kFwdCT = 4;
+__host__ __device__ constexpr int fwd_groups(int Hd) { return Hd <= 128 ? kFwdCT : 1; }
 
 template <int MT>
 __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   constexpr int Hd = MT * 64, KB = Hd / 32, RW = Hd / 4, CB = Hd * 2, HW = Hd / 32, NQ = Hd / 4;
-  __shared__ __attribute__((aligned(16))) unsigned char Hs[16 * CB];   // layer input, bf16 columns
-  __shared__ __attribute__((aligned(16))) unsigned char Ag[16 * CB];   // aggregates, bf16 columns
-  __shared__ __attribute__((aligned(16))) float Ybs[16 * Hd];          // W_b h per column, fp32
-  extern __shared__ unsigned char qmask[];                            // [edges + 16][NQ] 4-bit groups
+  constexpr int CT = fwd_groups(Hd), NC = 16 * CT;
+  __shared__ __attribute__((aligned(16))) unsigned char Hs[NC * CB];   // layer input, bf16 columns
+  __shared__ __attribute__((aligned(16))) unsigned char Ag[NC * CB];   // aggregates, bf16 columns
+  __shared__ __attribute__((aligned(16))) float Ybs[NC * Hd];          // W_b h per column, fp32
+  extern __shared__ unsigned char qmask[];                            // [edges + NC][NQ] 4-bit groups
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* fm = a.fmeta + (size_t)tile * 4;
   const int nt = fm[0], eb = fm[1], ec = fm[2];
-  const int32_t* cols = a.fcols + (size_t)tile * 16;
-  // ---- gather the 16 input columns
-  for (int t = threadIdx.x; t < 16 * CB / 16; t += 256) {
+  const int32_t* cols = a.fcols + (size_t)tile * NC;
+  // ---- gather the input columns
+  for (int t = threadIdx.x; t < NC * CB / 16; t += 256) {
     const int c = t / (CB / 16), ch = t % (CB / 16);
     const int node = cols[c];
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -1095,39 +1103,52 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   }
   __syncthreads();
   // ---- edge GEMMs: Yb = W_b h, P = W_a h + Yb
-  floatx4_t ap[MT], ay[MT];
+  floatx4_t ap[CT][MT], ay[CT][MT];
   {
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      ap[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-      ay[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        ap[ct][m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        ay[ct][m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      }
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(Hs + col * CB + swz(64 * kb + 16 * grp, col));
+      bf16x8_t wa[MT], wb[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int row = wave * RW + 16 * m + col;
-        const bf16x8_t wa = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)row * Hd + kb * 32 + grp * 8);
-        const bf16x8_t wb = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)row * Hd + kb * 32 + grp * 8);
-        ay[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, bfr, ay[m], 0, 0, 0);
-        ap[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, bfr, ap[m], 0, 0, 0);
+        wa[m] = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)row * Hd + kb * 32 + grp * 8);
+        wb[m] = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)row * Hd + kb * 32 + grp * 8);
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = 16 * ct + col;
+        const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(Hs + c * CB + swz(64 * kb + 16 * grp, c));
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          ay[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[m], bfr, ay[ct][m], 0, 0, 0);
+          ap[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[m], bfr, ap[ct][m], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int f0 = wave * RW + 16 * m + 4 * grp;
-      *reinterpret_cast<floatx4_t*>(Ybs + col * Hd + f0) = ay[m];
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ap[m][i] += ay[m][i] + a.be[f0 + i];
-    }
+      for (int m = 0; m < MT; ++m) {
+        const int f0 = wave * RW + 16 * m + 4 * grp;
+        *reinterpret_cast<floatx4_t*>(Ybs + (16 * ct + col) * Hd + f0) = ay[ct][m];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ap[ct][m][i] += ay[ct][m][i] + a.be[f0 + i];
+      }
   }
   __syncthreads();
   // ---- edge terms of the target columns: agg = sum_j relu(P_i - Yb_j)
-  {
-    int e0 = 0;
-    for (int c = 0; c < col; ++c) e0 += a.fecnt[(size_t)tile * 16 + c];
-    const int ne = col < nt ? a.fecnt[(size_t)tile * 16 + col] : 0;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = 16 * ct + col;
+    const int e0 = a.fepre[(size_t)tile * NC + c];
+    const int ne = c < nt ? a.fecnt[(size_t)tile * NC + c] : 0;
     float agg[MT][4];
     uint32_t ncnt[MT];  // 4 byte counters: in-edges whose ReLU is on, per feature
 #pragma unroll
@@ -1145,7 +1166,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
         uint32_t nib = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float z = ap[m][i] - yb[i];
+          const float z = ap[ct][m][i] - yb[i];
           const bool on = z > 0.f;
           agg[m][i] += on ? z : 0.f;
           nib |= (on ? 1u : 0u) << i;
@@ -1154,8 +1175,8 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
         qmask[(size_t)(e0 + t) * NQ + f0 / 4] = (unsigned char)nib;
       }
     }
-    if (col < nt) {
-      const int node = cols[col];
+    if (c < nt) {
+      const int node = cols[c];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int f0 = wave * RW + 16 * m + 4 * grp;
@@ -1168,47 +1189,61 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       uint2 v;
       v.x = pack_bf16x2(agg[m][0], agg[m][1]);
       v.y = pack_bf16x2(agg[m][2], agg[m][3]);
-      *reinterpret_cast<uint2*>(Ag + col * CB + swz(2 * f0, col)) = v;
+      *reinterpret_cast<uint2*>(Ag + c * CB + swz(2 * f0, c)) = v;
     }
   }
   __syncthreads();
   // ---- node update: h' = relu(W_n1 h + W_n2 agg + b_n)
   {
-    floatx4_t acc[MT];
+    floatx4_t acc[CT][MT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[ct][m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(Hs + col * CB + swz(64 * kb + 16 * grp, col));
-      const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Ag + col * CB + swz(64 * kb + 16 * grp, col));
+      bf16x8_t w1[MT], w2[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int row = wave * RW + 16 * m + col;
-        const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + (size_t)row * Hd + kb * 32 + grp * 8);
-        const bf16x8_t w2 = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + (size_t)row * Hd + kb * 32 + grp * 8);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, bh, acc[m], 0, 0, 0);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2, bg, acc[m], 0, 0, 0);
+        w1[m] = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + (size_t)row * Hd + kb * 32 + grp * 8);
+        w2[m] = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + (size_t)row * Hd + kb * 32 + grp * 8);
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = 16 * ct + col;
+        const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(Hs + c * CB + swz(64 * kb + 16 * grp, c));
+        const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Ag + c * CB + swz(64 * kb + 16 * grp, c));
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], bh, acc[ct][m], 0, 0, 0);
+          acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m], bg, acc[ct][m], 0, 0, 0);
+        }
       }
     }
-    if (col < nt) {
-      const int node = cols[col];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int f0 = wave * RW + 16 * m + 4 * grp;
-        float hv[4];
-        uint32_t nib = 0;
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c = 16 * ct + col;
+      if (c < nt) {
+        const int node = cols[c];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float z = acc[m][i] + a.bn[f0 + i];
-          const bool on = z > 0.f;
-          hv[i] = on ? z : 0.f;
-          nib |= (on ? 1u : 0u) << i;
+        for (int m = 0; m < MT; ++m) {
+          const int f0 = wave * RW + 16 * m + 4 * grp;
+          float hv[4];
+          uint32_t nib = 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float z = acc[ct][m][i] + a.bn[f0 + i];
+            const bool on = z > 0.f;
+            hv[i] = on ? z : 0.f;
+            nib |= (on ? 1u : 0u) << i;
+          }
+          uint2 v;
+          v.x = pack_bf16x2(hv[0], hv[1]);
+          v.y = pack_bf16x2(hv[2], hv[3]);
+          *reinterpret_cast<uint2*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = v;
+          qmask[(size_t)(a.fedge_cap + c) * NQ + f0 / 4] = (unsigned char)nib;
         }
-        uint2 v;
-        v.x = pack_bf16x2(hv[0], hv[1]);
-        v.y = pack_bf16x2(hv[2], hv[3]);
-        *reinterpret_cast<uint2*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = v;
-        qmask[(size_t)(a.fedge_cap + col) * NQ + f0 / 4] = (unsigned char)nib;
       }
     }
   }
@@ -1229,33 +1264,43 @@ __global__ void fill_zero_kernel(float* p, long n) {
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = 0.f;
 }
 
-// c = f - sum_j A^{ij} xhat^j - B^i uhat (and f copied out); one lane per (stage, node).
+// c = f - sum_j A^{ij} xhat^j - B^i uhat (and f copied out); one lane per
+// (stage, node, row), pattern blocks taken 4 at a time so their loads overlap.
 __global__ void gnn_offset_kernel(int N, int M, int nu, long nnz, const int32_t* prow, const int32_t* pcol,
                                   const float* xhat, const float* uhat, const float* A, const float* B,
                                   const float* fwd, float* c, float* fnext) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N * M) return;
-  const int k = s / M, i = s - k * M;
-  float lin[6] = {0, 0, 0, 0, 0, 0};
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)N * M * NBX) return;
+  const int r = (int)(t % NBX);
+  const long s = t / NBX;
+  const int k = (int)(s / M), i = (int)(s - (long)k * M);
   const float* xk = xhat + (size_t)k * M * NBX;
-  for (int e = prow[i]; e < prow[i + 1]; ++e) {
-    const float* blk = A + ((size_t)k * nnz + e) * 36;
-    const float* xj = xk + (size_t)pcol[e] * NBX;
+  float lin = 0.f;
+  const int e0 = prow[i], e1 = prow[i + 1];
+  for (int e = e0; e < e1; e += 4) {
+    float av[4][6], xv[4][6];
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+    for (int u = 0; u < 4; ++u) {
+      const int eu = e + u < e1 ? e + u : e;
+      const float* blk = A + ((size_t)k * nnz + eu) * 36 + r * 6;
+      const float* xj = xk + (size_t)pcol[eu] * NBX;
 #pragma unroll
-      for (int d = 0; d < 6; ++d) lin[r] += blk[r * 6 + d] * xj[d];
+      for (int d = 0; d < 6; ++d) {
+        av[u][d] = e + u < e1 ? blk[d] : 0.f;
+        xv[u][d] = xj[d];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < 6; ++d) lin += av[u][d] * xv[u][d];
   }
-  const float* Bi = B + (size_t)s * NBX * nu;
+  const float* Bi = B + ((size_t)s * NBX + r) * nu;
   const float* u = uhat + (size_t)k * nu;
-  for (int r = 0; r < 6; ++r)
-    for (int d = 0; d < nu; ++d) lin[r] += Bi[r * nu + d] * u[d];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    float fv = fwd[(size_t)s * NBX + r];
-    c[(size_t)s * NBX + r] = fv - lin[r];
-    if (fnext) fnext[(size_t)s * NBX + r] = fv;
-  }
+  for (int d = 0; d < nu; ++d) lin += Bi[d] * u[d];
+  const float fv = fwd[(size_t)s * NBX + r];
+  c[(size_t)s * NBX + r] = fv - lin;
+  if (fnext) fnext[(size_t)s * NBX + r] = fv;
 }
 
 template <typename T>
@@ -1621,8 +1666,9 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     UP(Wa16, wa16) UP(Wb16, wb16) UP(Wn1_16, w1_16) UP(Wn2_16, w2_16)
     UP(prog, tp.prog) UP(elist, tp.elist) UP(glist, tp.glist)
     // forward column tiles: greedily add target nodes while targets plus their
-    // senders fit in 16 columns; targets occupy the first columns
-    std::vector<int32_t> fcols, fmeta, fecnt, fesrc, feid;
+    // senders fit in NC columns; targets occupy the first columns
+    const size_t NC = 16 * (size_t)fwd_groups(Hd);
+    std::vector<int32_t> fcols, fmeta, fecnt, fepre, fesrc, feid;
     int i = 0;
     g.fedge_cap = 0;
     while (i < g.M) {
@@ -1637,21 +1683,22 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
                   all.end());
         std::sort(all.begin(), all.end());
         all.erase(std::unique(all.begin(), all.end()), all.end());
-        if (cand_t.size() + all.size() > 16) break;
+        if (cand_t.size() + all.size() > NC) break;
         tg = cand_t;
         hal = all;
         ++i;
       }
       if (tg.empty()) {
-        p->last_error = "model_set_gnn: a node has more than 15 in-neighbours (forward tiles hold 16 columns)";
+        p->last_error = "model_set_gnn: a node has too many in-neighbours for a forward column tile";
         gnn_free(p);
         return GNMPC_UNSUPPORTED;
       }
       std::vector<int32_t> colv = tg;
       colv.insert(colv.end(), hal.begin(), hal.end());
       const int eb = (int)fesrc.size();
-      for (size_t c = 0; c < 16; ++c) {
+      for (size_t c = 0; c < NC; ++c) {
         fcols.push_back(c < colv.size() ? colv[c] : -1);
+        fepre.push_back((int32_t)fesrc.size() - eb);
         if (c < tg.size()) {
           const int node = tg[c];
           fecnt.push_back(p->h_row_ptr[node + 1] - p->h_row_ptr[node]);
@@ -1671,7 +1718,7 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
       fmeta.push_back(0);
       ++g.n_ftiles;
     }
-    UP(fcols, fcols) UP(fmeta, fmeta) UP(fecnt, fecnt) UP(fesrc, fesrc) UP(feid, feid)
+    UP(fcols, fcols) UP(fmeta, fmeta) UP(fecnt, fecnt) UP(fepre, fepre) UP(fesrc, fesrc) UP(feid, feid)
     if ((s = dalloc(p, g.h16, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
     if ((s = dalloc(p, g.cnt, (size_t)L * NM * Hd)) != GNMPC_OK) return s;
   }
@@ -1741,10 +1788,16 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       f.fcols = g.fcols;
       f.fmeta = g.fmeta;
       f.fecnt = g.fecnt;
+      f.fepre = g.fepre;
       f.fesrc = g.fesrc;
       f.feid = g.feid;
-      const size_t qbytes = (size_t)(g.fedge_cap + 16) * (Hd / 4);
+      const size_t qbytes = (size_t)(g.fedge_cap + 16 * fwd_groups(Hd)) * (Hd / 4);
       dim3 fg(g.n_ftiles, N);
+      {
+        const void* ffn = Hd == 64 ? (const void*)fwd_mfma_layer_kernel<1>
+                        : Hd == 128 ? (const void*)fwd_mfma_layer_kernel<2> : (const void*)fwd_mfma_layer_kernel<4>;
+        GNMPC_HIP_TRY(p, set_max_lds(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)qbytes));
+      }
       if (Hd == 64) fwd_mfma_layer_kernel<1><<<fg, 256, qbytes, s>>>(f);
       else if (Hd == 128) fwd_mfma_layer_kernel<2><<<fg, 256, qbytes, s>>>(f);
       else fwd_mfma_layer_kernel<4><<<fg, 256, qbytes, s>>>(f);
@@ -1884,7 +1937,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   }
   phase_end(p, GNMPC_PH_GNN_JACOBIAN, s);
   phase_begin(p, GNMPC_PH_GNN_ASSEMBLY, s);
-  gnn_offset_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(N, M, p->dims.nu, p->nnz, p->d_prow, p->d_pcol,
+  gnn_offset_kernel<<<ceil_div((long)N * M * NBX, 256), 256, 0, s>>>(N, M, p->dims.nu, p->nnz, p->d_prow, p->d_pcol,
                                                                (const float*)xhat, (const float*)uhat,
                                                                (const float*)A, (const float*)B, g.fnext,
                                                                (float*)c, (float*)fnext);
