@@ -1042,21 +1042,39 @@ __global__ void fwd_enc_bf16_kernel(FwdArgs a, uint16_t* h0) {
   store_mask(a.mask_enc + (size_t)s * (a.Hd / 32), f, on);
 }
 
+// Decoder velocity rows on the last hidden state: 16 lanes per (stage, node),
+// each taking 8 consecutive features, reduced across the 16 lanes.
 __global__ void fwd_dec_bf16_kernel(FwdArgs a, const uint16_t* hL) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.N * a.M) return;
-  const uint16_t* h = hL + (size_t)s * a.Hd;
-  float o[3] = {a.bdec[3], a.bdec[4], a.bdec[5]};
-  for (int q = 0; q < a.Hd; ++q) {
-    const float hv = __uint_as_float((uint32_t)h[q] << 16);
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long s = t >> 4;
+  const int sub = (int)(t & 15);
+  const bool live = s < (long)a.N * a.M;
+  float o[3] = {0.f, 0.f, 0.f};
+  if (live) {
+    for (int f0 = 8 * sub; f0 < a.Hd; f0 += 128) {
+      const uint4 hv = *reinterpret_cast<const uint4*>(hL + (size_t)s * a.Hd + f0);
+      const uint32_t w[4] = {hv.x, hv.y, hv.z, hv.w};
 #pragma unroll
-    for (int r = 0; r < 3; ++r) o[r] += a.decT[q * 6 + 3 + r] * hv;
+      for (int q = 0; q < 8; ++q) {
+        const float h = __uint_as_float(q & 1 ? (w[q >> 1] & 0xFFFF0000u) : (w[q >> 1] << 16));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) o[r] += a.decT[(f0 + q) * 6 + 3 + r] * h;
+      }
+    }
   }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    o[r] += __shfl_xor(o[r], 8, 16);
+    o[r] += __shfl_xor(o[r], 4, 16);
+    o[r] += __shfl_xor(o[r], 2, 16);
+    o[r] += __shfl_xor(o[r], 1, 16);
+  }
+  if (!live || sub != 0) return;
   const float* x = a.xhat + (size_t)s * NBX;
   float* fo = a.fnext + (size_t)s * NBX;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const float vn = x[3 + r] + a.dt * o[r];
+    const float vn = x[3 + r] + a.dt * (o[r] + a.bdec[3 + r]);
     fo[3 + r] = vn;
     fo[r] = x[r] + a.dt * vn;
   }
@@ -1802,7 +1820,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       else if (Hd == 128) fwd_mfma_layer_kernel<2><<<fg, 256, qbytes, s>>>(f);
       else fwd_mfma_layer_kernel<4><<<fg, 256, qbytes, s>>>(f);
     }
-    fwd_dec_bf16_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa, g.h16 + (size_t)g.L * NM * Hd);
+    fwd_dec_bf16_kernel<<<ceil_div((long)N * M * 16, 256), 256, 0, s>>>(fa, g.h16 + (size_t)g.L * NM * Hd);
   } else {
     fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
     const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;
