@@ -96,6 +96,48 @@ __device__ T block_sum(T v, T* red) {
   return r;
 }
 
+// Largest |v[i]| over i < n and its first index (ties: smallest index), for the
+// whole block; red needs 2 kWaves entries.
+template <typename T>
+__device__ void block_argmax_abs(const T* v, int n, T* red, T& vmax, int& imax) {
+  T bv = T(-1);
+  int bi = 0x7FFFFFFF;
+  for (int i = threadIdx.x; i < n; i += kQpThreads) {
+    const T a = fabs(v[i]);
+    if (a > bv) {  // i increases, so the first maximum of this lane is kept
+      bv = a;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    red[w] = bv;
+    red[kWaves + w] = (T)bi;
+  }
+  __syncthreads();
+  vmax = red[0];
+  imax = (int)red[kWaves];
+  for (int q = 1; q < kWaves; ++q) {
+    const T ov = red[q];
+    const int oi = (int)red[kWaves + q];
+    if (ov > vmax || (ov == vmax && oi < imax)) {
+      vmax = ov;
+      imax = oi;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 struct Work {
   T* mat;   // packed lower triangle: K, then L, then W = L^{-1}
@@ -392,23 +434,34 @@ __device__ inline void bsub(T* C, const T acc[4]) {
 // L = L_0 L_1 ... L_{nb-1} (L_J the identity except block column J of L),
 // W = L_{nb-1}^{-1} ... L_0^{-1}, and step J applies L_J^{-1} to the rows J..
 // of the partial W while the Schur complement is updated:
-//   a. D = L_JJ^{-1} from the updated diagonal block (one wave); the other
-//      waves finish the previous column, W_{I,J-1} = -L_{I,J-1} D_{J-1}.
-//   b. panel L_IJ = K_IJ D' (I > J); W row J: W_JK <- D W_JK (K < J).
-//   c. trailing K_IK -= L_IJ L_KJ' (J < K <= I); W_IK -= L_IJ W_JK (I > J, K < J).
+//   a. the waves finish the previous column, W_{I,J-1} = -L_{I,J-1} D_{J-1}
+//      (D_J = L_JJ^{-1} is already in block (J, J));
+//   b. panel L_IJ = K_IJ D' (I > J); W row J: W_JK <- D W_JK (K < J);
+//   c. trailing K_IK -= L_IJ L_KJ' (J < K <= I) and W_IK -= L_IJ W_JK (I > J,
+//      K < J).  Wave 0 takes the update of block (J+1, J+1) first and then
+//      factors and inverts it (lookahead) while the other waves do the rest,
+//      two block products at a time.
 // At the end block (I, K) holds W_IK.  False if K is not positive definite.
+template <typename T>
+__device__ inline void bmma_rt(T acc[4], const T* A, const T* B, bool trans) {
+  if (trans) bmma<true>(acc, A, B);
+  else bmma<false>(acc, A, B);
+}
+
 template <typename T>
 __device__ bool factor_invert(const Work<T>& w, int nb) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave == 0) {
+    const bool ok = diag_factor_invert(w.mat, w.part);
+    if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
+  }
+  __syncthreads();
   for (int J = 0; J < nb; ++J) {
     T* D = w.mat + bo(J, J);
     // ---- a
-    if (wave == 0) {
-      const bool ok = diag_factor_invert(D, w.part);
-      if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
-    } else if (J > 0) {
+    if (J > 0) {
       const T* Dp = w.mat + bo(J - 1, J - 1);
-      for (int I = J + wave - 1; I < nb; I += kWaves - 1) {
+      for (int I = J + wave; I < nb; I += kWaves) {
         T acc[4] = {T(0), T(0), T(0), T(0)};
         T* B = w.mat + bo(I, J - 1);
         bmma<false>(acc, B, Dp);
@@ -435,22 +488,52 @@ __device__ bool factor_invert(const Work<T>& w, int nb) {
       }
     }
     __syncthreads();
-    // ---- c: trailing pairs, then W updates of the rows below J
-    const int npairs = m * (m + 1) / 2;
-    for (int t = wave; t < npairs + m * J; t += kWaves) {
-      T acc[4] = {T(0), T(0), T(0), T(0)};
+    if (m == 0) break;
+    // ---- c: task 0 is the pair (J+1, J+1); tasks 1.. are the other trailing pairs, then the W updates
+    const int npairs = m * (m + 1) / 2, ntask = npairs + m * J;
+    auto decode = [&](int t, const T*& A, const T*& B, T*& C, bool& trans) {
       if (t < npairs) {
         int ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
         while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
         while (ii * (ii + 1) / 2 > t) --ii;
         const int kk = t - ii * (ii + 1) / 2;
-        const int I = J + 1 + ii, K = J + 1 + kk;
-        bmma<true>(acc, w.mat + bo(I, J), w.mat + bo(K, J));
-        bsub(w.mat + bo(I, K), acc);
+        A = w.mat + bo(J + 1 + ii, J);
+        B = w.mat + bo(J + 1 + kk, J);
+        C = w.mat + bo(J + 1 + ii, J + 1 + kk);
+        trans = true;
       } else {
         const int u = t - npairs, I = J + 1 + u / J, K = u % J;
-        bmma<false>(acc, w.mat + bo(I, J), w.mat + bo(J, K));
-        bsub(w.mat + bo(I, K), acc);
+        A = w.mat + bo(I, J);
+        B = w.mat + bo(J, K);
+        C = w.mat + bo(I, K);
+        trans = false;
+      }
+    };
+    if (wave == 0) {
+      const T *A, *B;
+      T* C;
+      bool tr;
+      decode(0, A, B, C, tr);
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      bmma_rt(acc, A, B, tr);
+      bsub(C, acc);
+      __builtin_amdgcn_wave_barrier();
+      const bool ok = diag_factor_invert(w.mat + bo(J + 1, J + 1), w.part);
+      if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
+    } else {
+      constexpr int S = kWaves - 1;
+      for (int t = wave; t < ntask; t += 2 * S) {
+        const bool two = t + S < ntask;
+        const T *A0, *B0, *A1 = nullptr, *B1 = nullptr;
+        T *C0, *C1 = nullptr;
+        bool tr0, tr1 = false;
+        decode(t, A0, B0, C0, tr0);
+        if (two) decode(t + S, A1, B1, C1, tr1);
+        T acc0[4] = {T(0), T(0), T(0), T(0)}, acc1[4] = {T(0), T(0), T(0), T(0)};
+        bmma_rt(acc0, A0, B0, tr0);
+        if (two) bmma_rt(acc1, A1, B1, tr1);
+        bsub(C0, acc0);
+        if (two) bsub(C1, acc1);
       }
     }
     __syncthreads();
@@ -479,18 +562,7 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
     int jmax = 0;
     for (int i = threadIdx.x; i < n; i += kQpThreads) ztx += y[i] * v[i];
     ztx = block_sum(ztx, w.red);
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < n; ++i)
-        if (fabs(y[i]) > zmax) {
-          zmax = fabs(y[i]);
-          jmax = i;
-        }
-      w.scal[1] = zmax;
-      w.scal[2] = (T)jmax;
-    }
-    __syncthreads();
-    zmax = w.scal[1];
-    jmax = (int)w.scal[2];
+    block_argmax_abs(y, n, w.red, zmax, jmax);
     if (zmax <= ztx) break;
     for (int i = threadIdx.x; i < n; i += kQpThreads) v[i] = (i == jmax) ? T(1) : T(0);
     __syncthreads();
