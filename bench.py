@@ -54,37 +54,68 @@ def jacobian_flops(P):
     return total * P.N
 
 
+def measured_traffic():
+    """HBM bytes per launch of the Jacobian kernel from the counter summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
+    copy of known size), or None when the kernel source has changed since the
+    counters were taken (the summary records the SHA-256 of the source file)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "jvp_mfma2_kernel_chain1000_counters.md")
+    src = os.path.join(ROOT, "paper_2602_17601_amd", "csrc", "gnn.hip")
+    try:
+        fields = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and line.strip().startswith("- "):
+                    k, v = line.strip()[2:].split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("source_sha256") != sha:
+            return None
+        return int(fields["fetch_bytes_per_launch"]) + int(fields["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(P, Pm):
-    """The FP64 oracle on the host: a bounded sample of the GNN linearization
-    (node-stages), one full condensing with the GNN Jacobian pattern and one QP
-    solve; the step time is extrapolated from the per-node-stage cost."""
+    """The FP64 oracle on the host, one thread, on a bounded sample of the
+    step: the GNN linearization on 1000 node-stages (extrapolated to all
+    N*M), then one full condensing on the GNN Jacobian pattern and one QP
+    solve.  The condensing takes the analytic mass-spring-damper Jacobians of
+    the same chain (oracle) placed into the wider GNN pattern, so the blocks
+    have the dynamics' magnitudes and the QP is the plain model's real one."""
     from threadpoolctl import threadpool_limits
     from oracle.condense import condense_local
     from oracle.gnn import gnn_linearize
     from oracle.graph import jacobian_pattern
+    from oracle.msd import msd_linearize
     from oracle.qp import qp_ipm
     Wr = P.gnn.rounded_bf16()
-    stages, nodes = [7], list(range(300, 500))
+    stages, nodes = [3, 7, 11, 15, 19], list(range(300, 500))
     with threadpool_limits(1):
         t0 = time.perf_counter()
         gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes, rounding="bf16")
         t_lin = (time.perf_counter() - t0) / (len(stages) * len(nodes)) * P.N * P.M
         prow, pcol = jacobian_pattern(P.row_ptr, P.col, P.M, P.gnn.L)
-        rng = np.random.default_rng(0)
-        A = rng.normal(0, 0.02, size=(P.N, len(pcol), 6, 6))
-        B = rng.normal(0, 1e-4, size=(P.N, P.M, 6, P.nu))
-        c = rng.normal(0, 1e-4, size=(P.N, P.M, 6))
+        mrow, mcol, Am, Bm, cm = msd_linearize(Pm.xhat, Pm.uhat, Pm.row_ptr, Pm.col, Pm.act, Pm.msd)
+        A = np.zeros((P.N, len(pcol), 6, 6))
+        for i in range(P.M):
+            cols = pcol[prow[i]:prow[i + 1]]
+            for e in range(mrow[i], mrow[i + 1]):
+                A[:, prow[i] + int(np.searchsorted(cols, mcol[e]))] = Am[:, e]
         t0 = time.perf_counter()
-        l = condense_local(A, B, c, prow, pcol, P.x0, P.costs.Q, P.costs.q, P.costs.R, P.costs.r, P.rows)
+        l = condense_local(A, Bm, cm, prow, pcol, Pm.x0, Pm.costs.Q, Pm.costs.q, Pm.costs.R, Pm.costs.r, Pm.rows)
         t_cond = time.perf_counter() - t0
         t0 = time.perf_counter()
-        qp_ipm(l["H"], l["g"], P.lb, P.ub, l["Ct"], np.full(P.rows.n, -np.inf), l["dt"] + 1.0)
+        qp_ipm(l["H"], l["g"], Pm.lb, Pm.ub, l["Ct"], np.full(Pm.rows.n, -np.inf), l["dt"])
         t_qp = time.perf_counter() - t0
     step = t_lin + t_cond + t_qp
     return {"value": 1.0 / step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle, 1 thread: GNN linearization timed on {len(nodes)} node-stages "
-                       f"({t_lin / (P.N * P.M) * 1e3:.1f} ms each, extrapolated to {P.N * P.M}), "
-                       f"one full condensing ({t_cond:.2f} s) and one QP ({t_qp:.2f} s)")}
+            "sample": (f"FP64 oracle, 1 thread: GNN linearization timed on {len(stages) * len(nodes)} node-stages "
+                       f"({t_lin / (P.N * P.M) * 1e3:.1f} ms each, extrapolated to {P.N * P.M}), one full "
+                       f"condensing on the {len(pcol)}-block GNN pattern ({t_cond:.2f} s) and one QP "
+                       f"({t_qp:.2f} s, mass-spring-damper Jacobians)")}
 
 
 def main():
@@ -184,7 +215,8 @@ def main():
     achieved = flops / jac_avg_s / 1e12 if jac_avg_s > 0 else 0.0
     roofline = {"kernel": "gnn_jacobian", "bound": "mfma", "achieved": achieved,
                 "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / BF16_DENSE_PEAK_TFLOPS,
-                "traffic": None, "algorithmic_flops_per_launch": flops, "avg_launch_ms": jac_avg_s * 1e3}
+                "traffic": measured_traffic(), "algorithmic_flops_per_launch": flops,
+                "avg_launch_ms": jac_avg_s * 1e3}
 
     def phase_avg(ph):
         return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items() if v[1]}
