@@ -359,12 +359,46 @@ __device__ T form_K(const QpArgs<Tin>& a, const Work<T>& w, T s) {
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
 
+// Value of lane J of this lane's 16-lane row (DPP row_newbcast, one VALU op).
+template <int J>
+__device__ inline float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xF, 0xF, false));
+}
+template <int J>
+__device__ inline double row_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), 0x150 + J, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + J, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Pivot step J of the row-per-lane Cholesky (lane i < 16 holds row i in a).
+template <int J, typename T>
+__device__ inline void chol_step(T (&a)[16], int lane, bool& ok) {
+  const T piv = row_bcast<J>(a[J]);
+  ok = ok && piv > T(0) && isfinite(piv);
+  const T d = sqrt(piv > T(0) ? piv : T(1));
+  const T inv = recip(d);
+  a[J] = lane == J ? d : (lane > J ? a[J] * inv : a[J]);
+  if constexpr (J + 1 < 16) {
+    // column J of L is now a[J] across the lanes; lane i updates a[k] for J < k <= i
+    T colv[16];
+#define GNMPC_BC(K) \
+    if constexpr (K > J) colv[K] = row_bcast<K>(a[J]);
+    GNMPC_BC(1) GNMPC_BC(2) GNMPC_BC(3) GNMPC_BC(4) GNMPC_BC(5) GNMPC_BC(6) GNMPC_BC(7) GNMPC_BC(8)
+    GNMPC_BC(9) GNMPC_BC(10) GNMPC_BC(11) GNMPC_BC(12) GNMPC_BC(13) GNMPC_BC(14) GNMPC_BC(15)
+#undef GNMPC_BC
+#pragma unroll
+    for (int k = J + 1; k < 16; ++k)
+      if (lane >= k) a[k] -= a[J] * colv[k];
+  }
+}
+
 // Cholesky factor of the 16x16 diagonal block at Dg (lower part) and its
 // inverse, by one wave; tmp is 256 elements of LDS.  Lane i < 16 holds row i;
-// each step publishes the scaled column through tmp and every lane reads it
-// back in 16-byte runs; then L goes to tmp and lane c forward-substitutes
-// column c of L^{-1}.  Writes L^{-1} (lower, zeros above) to Dg; false on a
-// nonpositive or non-finite pivot.
+// pivots and columns move between lanes by row broadcasts (no memory); then L
+// goes to tmp and lane c forward-substitutes column c of L^{-1}.  Writes
+// L^{-1} (lower, zeros above) to Dg; false on a nonpositive or non-finite pivot.
 template <typename T>
 __device__ bool diag_factor_invert(T* Dg, T* tmp) {
   const int lane = threadIdx.x & 63;
@@ -373,26 +407,24 @@ __device__ bool diag_factor_invert(T* Dg, T* tmp) {
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = act ? Dg[lane * 16 + c] : T(0);
   bool ok = true;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (lane == j) tmp[16] = a[j];
-    __builtin_amdgcn_wave_barrier();
-    const T piv = tmp[16];
-    ok = ok && piv > T(0) && isfinite(piv);
-    const T d = sqrt(piv > T(0) ? piv : T(1));
-    const T inv = recip(d);
-    if (lane == j) a[j] = d;
-    else if (lane > j) a[j] *= inv;
-    if (act) tmp[lane] = a[j];
-    __builtin_amdgcn_wave_barrier();
-    T colv[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) colv[k] = tmp[k];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = j + 1; k < 16; ++k)
-      if (lane >= k) a[k] -= a[j] * colv[k];
-  }
+  chol_step<0>(a, lane, ok);
+  chol_step<1>(a, lane, ok);
+  chol_step<2>(a, lane, ok);
+  chol_step<3>(a, lane, ok);
+  chol_step<4>(a, lane, ok);
+  chol_step<5>(a, lane, ok);
+  chol_step<6>(a, lane, ok);
+  chol_step<7>(a, lane, ok);
+  chol_step<8>(a, lane, ok);
+  chol_step<9>(a, lane, ok);
+  chol_step<10>(a, lane, ok);
+  chol_step<11>(a, lane, ok);
+  chol_step<12>(a, lane, ok);
+  chol_step<13>(a, lane, ok);
+  chol_step<14>(a, lane, ok);
+  chol_step<15>(a, lane, ok);
+  // the pivots are read by every lane of row 0; lanes >= 16 carry zeros, so only row 0 decides
+  ok = __builtin_amdgcn_readfirstlane((int)ok) != 0;
   if (act) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) tmp[lane * 16 + c] = c <= lane ? a[c] : T(0);
