@@ -54,11 +54,11 @@ struct GnnState {
   uint16_t *Wa16 = nullptr, *Wb16 = nullptr, *Wn1_16 = nullptr, *Wn2_16 = nullptr;  // [L][Hd][Hd]
   int32_t *prog = nullptr, *elist = nullptr;
   int stage_cap = 0;
-  // register-aggregate Jacobian kernel (Hd 64 or 128)
+  // register-aggregate Jacobian kernel (Hd 64 or 128), on its own (packed) seed tiles
   bool mfma2 = false;
   size_t mfma2_lds = 0;
-  int stage2_words = 0;
-  int32_t* glist = nullptr;
+  int stage2_words = 0, t2_tiles = 0, t2_cap1 = 0, t2_cap2 = 0;
+  int32_t *glist = nullptr, *t2_meta = nullptr, *t2_V = nullptr, *t2_Vself = nullptr, *t2_colmap = nullptr;
   // matrix-core forward pass (BF16): hidden states as bf16, node column tiles
   uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
   uint8_t* cnt = nullptr;         // [L][N][M][Hd] active in-edges of each node per feature
@@ -695,7 +695,7 @@ struct Mfma2Args {
   const float *encT, *decT;
   const uint16_t *Wa, *Wb, *Wn1, *Wn2;
   const uint32_t *mask_enc, *mask_node, *mask_edge, *cnt;
-  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *glist, *out3, *bout2;
+  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *glist, *out3, *bout2, *colmap;
   float *A, *B;
   long nnz;
 };
@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   const int ng = wave / GW, wg = wave % GW;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
-  const int sb = mt[0], oc = mt[3], bc = mt[5];
+  const int oc = mt[3], bc = mt[5];
 
   // lane offsets of the weight fragments (rows of the A operands): phase A, then phase B's two row tiles
   const uint32_t woA = (uint32_t)((wave * 16 + col) * Hd + grp * 8);
@@ -787,9 +787,9 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     for (int t = threadIdx.x; t < vc * kCols * (Hd / 8); t += NT) {
       const int q = t / (kCols * (Hd / 8)), c = (t / (Hd / 8)) % kCols, fc = t % (Hd / 8);
       const int node = a.V[vb + q];
-      const int p = a.Vself[vb + q];
-      const int d = c - a.seedcol[sb + p];
-      const bool valid = d >= 0 && (d < 6 || (a.seedact[sb + p] >= 0 && d < 9));
+      const int cm = a.colmap[(size_t)tile * kCols + c];  // (seed << 4) | dimension of column c
+      const bool valid = cm >= 0 && (cm >> 4) == q;
+      const int d = cm & 15;
       const uint32_t bits = (a.mask_enc[((size_t)k * a.M + node) * HW + (fc >> 2)] >> (8 * (fc & 3))) & 0xFFu;
       const float4* e4 = reinterpret_cast<const float4*>(a.encT + (size_t)(valid ? d : 0) * Hd + 8 * fc);
       const float4 lo = e4[0], hi = e4[1];
@@ -986,14 +986,15 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   __syncthreads();
   const int4* orec = reinterpret_cast<const int4*>(ST) + (so >> 2);
   for (int t = threadIdx.x; t < oc * 18; t += NT) {
-    const int o = t / 18, rem = t % 18, r = rem / 6, d = rem % 6;
-    const int4 rc = orec[o];  // {block, q, first column, diagonal}
-    const int cc = rc.z + d;
+    const int o = t / 18, rem = t % 18, r = rem / 6, dd = rem % 6;
+    const int4 rc = orec[o];  // {block, q, first column, first dim | count << 8 | diagonal << 16}
+    if (dd >= ((rc.w >> 8) & 0xFF)) continue;
+    const int d = (rc.w & 0xFF) + dd, cc = rc.z + dd;
     float dov = 0.f;
     const float* rq = reinterpret_cast<const float*>(red + (size_t)rc.y * GW * 4 * kCols + cc) + r;
 #pragma unroll
     for (int w = 0; w < GW * 4; ++w) dov += rq[w * kCols * 4];
-    const bool diag = rc.w != 0;
+    const bool diag = (rc.w >> 16) != 0;
     const float dv = (diag && d == 3 + r ? 1.f : 0.f) + a.dt * dov;
     const float dp = (diag && d == r ? 1.f : 0.f) + a.dt * dv;
     float* blk = a.A + ((size_t)k * a.nnz + rc.x) * 36;
@@ -1001,17 +1002,18 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     blk[(3 + r) * 6 + d] = dv;
   }
   for (int t = threadIdx.x; t < bc * 9; t += NT) {
-    const int o = t / 9, rem = t % 9, r = rem / 3, d = rem % 3;
-    const int4 rc = orec[oc + o];  // {node, q, first force column, actuator}
-    const int cc = rc.z + d;
+    const int o = t / 9, rem = t % 9, r = rem / 3, dd = rem % 3;
+    const int4 rc = orec[oc + o];  // {node, q, first column, 3 actuator + first force dim | count << 8}
+    if (dd >= (rc.w >> 8)) continue;
+    const int cc = rc.z + dd, bcol = (rc.w & 0xFF) + dd;
     float dov = 0.f;
     const float* rq = reinterpret_cast<const float*>(red + (size_t)rc.y * GW * 4 * kCols + cc) + r;
 #pragma unroll
     for (int w = 0; w < GW * 4; ++w) dov += rq[w * kCols * 4];
     const float dv = a.dt * dov;
     float* Bi = a.B + (((size_t)k * a.M + rc.x) * NBX) * a.nu;
-    Bi[(3 + r) * a.nu + 3 * rc.w + d] = dv;
-    Bi[r * a.nu + 3 * rc.w + d] = a.dt * dv;
+    Bi[(3 + r) * a.nu + bcol] = dv;
+    Bi[r * a.nu + bcol] = a.dt * dv;
   }
 }
 
@@ -1347,11 +1349,22 @@ struct TilePlan {
   // per (tile, round l >= 1): gather list that fills the LDS stage of the
   // register-aggregate kernel, pairs (destination word | kind << 28, source)
   std::vector<int32_t> glist;
-  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0, stage2_cap = 0, gmax = 0;
+  // per tile and tangent column: (seed index in the tile << 4) | state or force dimension, or -1
+  std::vector<int32_t> colmap;
+  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0, stage2_cap = 0, gmax = 0, vmax = 0;
 };
 
 
-void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
+// Seed tiles.  Classic tiles hold whole seeds (one or two, at most 16
+// columns).  Packed tiles take the seeds' columns as one stream in node order
+// (6 state dimensions, then 3 force dimensions for an actuated node) and cut
+// it every 16 columns, so a seed may continue in the next tile; a packed tile
+// is shortened to whole seeds only when a round would reach more than 16 nodes.
+struct SeedCols {
+  int32_t node, c0, d0, cnt;  // first column in the tile, first dimension, number of columns
+};
+
+void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool packed = false) {
   const int M = p->M;
   std::vector<std::vector<int32_t>> outn(M);  // receivers of each sender
   for (int i = 0; i < M; ++i)
@@ -1362,17 +1375,67 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
   const int Hd = p->gnn ? p->gnn->Hd : 128;
   const int HW = Hd / 32;
   std::vector<int32_t> where(M, -1);
-  int i = 0;
+  auto ncols_of = [&](int node) { return 6 + (act_of[node] >= 0 ? 3 : 0); };
+  auto rounds_of = [&](const std::vector<int32_t>& v0) {
+    std::vector<std::vector<int32_t>> Vl(L + 1);
+    Vl[0] = v0;
+    for (int l = 1; l <= L; ++l) {
+      std::vector<int32_t> nxt = Vl[l - 1];
+      for (int32_t j : Vl[l - 1])
+        for (int32_t r : outn[j]) nxt.push_back(r);
+      std::sort(nxt.begin(), nxt.end());
+      nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
+      Vl[l] = nxt;
+    }
+    return Vl;
+  };
+  int i = 0, dpos = 0;  // column stream position: node i, its dimension dpos
   while (i < M) {
+    std::vector<SeedCols> sc;
+    if (!packed) {
+      int used = 0;
+      while (i < M && (int)sc.size() < max_seeds) {
+        const int need = ncols_of(i);
+        if (used + need > kCols) break;
+        sc.push_back({i, used, 0, need});
+        used += need;
+        ++i;
+      }
+    } else {
+      const int i0 = i, d0 = dpos;
+      int used = 0;
+      while (i < M && used < kCols) {
+        const int take = std::min(kCols - used, ncols_of(i) - dpos);
+        sc.push_back({i, used, dpos, take});
+        used += take;
+        dpos += take;
+        if (dpos == ncols_of(i)) {
+          ++i;
+          dpos = 0;
+        }
+      }
+      // shorten to whole seeds while a round would hold more than 16 nodes
+      auto too_wide = [&]() {
+        std::vector<int32_t> v0;
+        for (const SeedCols& c : sc) v0.push_back(c.node);
+        auto Vl = rounds_of(v0);
+        for (auto& v : Vl)
+          if (v.size() > 16) return true;
+        return false;
+      };
+      while (sc.size() > 1 && too_wide()) {
+        const SeedCols last = sc.back();
+        sc.pop_back();
+        i = last.node;
+        dpos = last.d0;
+      }
+      (void)i0;
+      (void)d0;
+    }
     std::vector<int32_t> seeds, cols;
-    int used = 0;
-    while (i < M && (int)seeds.size() < max_seeds) {
-      int need = 6 + (act_of[i] >= 0 ? 3 : 0);
-      if (used + need > kCols) break;
-      seeds.push_back(i);
-      cols.push_back(used);
-      used += need;
-      ++i;
+    for (const SeedCols& c : sc) {
+      seeds.push_back(c.node);
+      cols.push_back(c.c0 - c.d0);  // column of dimension 0 (classic tiles: the seed's first column)
     }
     std::vector<int32_t> m(stride, 0);
     m[0] = (int32_t)tp.seed.size();
@@ -1382,17 +1445,12 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
       tp.seedcol.push_back(cols[t]);
       tp.seedact.push_back(act_of[seeds[t]]);
     }
-    std::vector<std::vector<int32_t>> Vl(L + 1);
-    Vl[0] = seeds;
-    for (int l = 1; l <= L; ++l) {
-      std::vector<int32_t> nxt = Vl[l - 1];
-      for (int32_t j : Vl[l - 1])
-        for (int32_t r : outn[j]) nxt.push_back(r);
-      std::sort(nxt.begin(), nxt.end());
-      nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
-      Vl[l] = nxt;
-    }
+    std::vector<std::vector<int32_t>> Vl = rounds_of(seeds);
+    for (int c = 0; c < kCols; ++c) tp.colmap.push_back(-1);
+    for (size_t t = 0; t < sc.size(); ++t)
+      for (int d = 0; d < sc[t].cnt; ++d) tp.colmap[tp.colmap.size() - kCols + sc[t].c0 + d] = (int32_t)(t << 4) | (sc[t].d0 + d);
     for (int l = 0; l <= L; ++l) {
+      tp.vmax = std::max(tp.vmax, (int)Vl[l].size());
       m[6 + 2 * l] = (int32_t)tp.V.size();
       m[7 + 2 * l] = (int32_t)Vl[l].size();
       if (l < L) tp.cap1 = std::max(tp.cap1, (int)Vl[l].size());
@@ -1460,6 +1518,7 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
       tp.stage_cap = std::max(tp.stage_cap, words);
     }
     // gather lists of the register-aggregate kernel
+    int ocount = 0, bcount = 0;
     {
       const int SREC = stage_record_words(Hd);
       int so = 0;
@@ -1498,33 +1557,41 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
         }
         so = sfb + ((int)nx.size() + 3) / 4 * 4;
         if (l == L) {
-          // output records: A blocks {CSR block id, node index q, first column, diagonal?},
-          // then B blocks {node, q, first force column, actuator}
+          // output records (the tile's columns of each block):
+          //   A blocks {CSR block id, node index q, first column, first dim | count << 8 | diagonal << 16},
+          //   then B blocks {node, q, first column, 3 actuator + first force dim | count << 8}
+          ocount = 0;
+          bcount = 0;
           for (size_t q = 0; q < nx.size(); ++q) {
             const int32_t node = nx[q];
             const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
             const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
-            for (size_t sd = 0; sd < seeds.size(); ++sd) {
-              const int32_t* it = std::lower_bound(rb, re, seeds[sd]);
-              if (it == re || *it != seeds[sd]) continue;
+            for (const SeedCols& c : sc) {
+              const int s0 = c.d0, s1 = std::min(c.d0 + c.cnt, 6);
+              if (s1 <= s0) continue;
+              const int32_t* it = std::lower_bound(rb, re, c.node);
+              if (it == re || *it != c.node) continue;
               item(so++, kGConst, (int32_t)(it - p->h_pcol.data()));
               item(so++, kGConst, (int32_t)q);
-              item(so++, kGConst, cols[sd]);
-              item(so++, kGConst, node == seeds[sd] ? 1 : 0);
+              item(so++, kGConst, c.c0);
+              item(so++, kGConst, s0 | ((s1 - s0) << 8) | ((node == c.node ? 1 : 0) << 16));
+              ++ocount;
             }
           }
           for (size_t q = 0; q < nx.size(); ++q)
-            for (size_t sd = 0; sd < seeds.size(); ++sd) {
-              if (act_of[seeds[sd]] < 0) continue;
+            for (const SeedCols& c : sc) {
+              const int f0 = std::max(c.d0, 6), f1 = c.d0 + c.cnt;
+              if (act_of[c.node] < 0 || f1 <= f0) continue;
               const int32_t node = nx[q];
               const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
               const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
-              const int32_t* it = std::lower_bound(rb, re, seeds[sd]);
-              if (it == re || *it != seeds[sd]) continue;
+              const int32_t* it = std::lower_bound(rb, re, c.node);
+              if (it == re || *it != c.node) continue;
               item(so++, kGConst, node);
               item(so++, kGConst, (int32_t)q);
-              item(so++, kGConst, cols[sd] + 6);
-              item(so++, kGConst, act_of[seeds[sd]]);
+              item(so++, kGConst, c.c0 + (f0 - c.d0));
+              item(so++, kGConst, (3 * act_of[c.node] + (f0 - 6)) | ((f1 - f0) << 8));
+              ++bcount;
             }
         }
         const int gc = (int)tp.glist.size() / 2 - gb;
@@ -1538,7 +1605,7 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
     m[2] = (int32_t)(tp.out3.size() / 3);
     m[4] = (int32_t)(tp.bout2.size() / 2);
     int oc = 0, bc = 0;
-    for (size_t q = 0; q < Vl[L].size(); ++q) {
+    for (size_t q = 0; q < (packed ? 0 : Vl[L].size()); ++q) {
       int32_t node = Vl[L][q];
       const int32_t* rb = p->h_pcol.data() + p->h_prow[node];
       const int32_t* re = p->h_pcol.data() + p->h_prow[node + 1];
@@ -1556,8 +1623,8 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp) {
         }
       }
     }
-    m[3] = oc;
-    m[5] = bc;
+    m[3] = packed ? ocount : oc;
+    m[5] = packed ? bcount : bc;
     tp.meta.insert(tp.meta.end(), m.begin(), m.end());
     ++tp.n_tiles;
   }
@@ -1661,10 +1728,22 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   g.stage_cap = tp.stage_cap;
   g.mfma_lds = (size_t)tp.cap1 * kCols * Hd * 2 + (size_t)tp.cap2 * kCols * Hd * 4 + (size_t)tp.stage_cap * 4;
   g.mfma = bf && (Hd == 64 || Hd == 128 || Hd == 256) && tp.cap2 <= 16 && g.mfma_lds <= 160 * 1024;
-  g.stage2_words = (tp.stage2_cap + 3) / 4 * 4;
-  g.mfma2_lds = (size_t)(tp.cap1 + tp.cap2) * kCols * Hd * 2 + (size_t)g.stage2_words * 4 + (size_t)3 * Hd * 4;
-  g.mfma2 = g.mfma && (Hd == 64 || Hd == 128) && tp.cap2 <= 16 && g.mfma2_lds <= 160 * 1024 &&
-            tp.gmax <= Hd * 4 * kGatherPerThread;  // gmax: stage words gathered per tile, all rounds
+  // register-aggregate kernel: packed tiles (16 columns from a column stream) when every
+  // round stays within 16 nodes, else the classic tiles
+  TilePlan tp2;
+  auto fits2 = [&](const TilePlan& t, size_t& lds, int& words) {
+    words = (t.stage2_cap + 3) / 4 * 4;
+    lds = (size_t)(t.cap1 + t.cap2) * kCols * Hd * 2 + (size_t)words * 4 + (size_t)3 * Hd * 4;
+    return t.vmax <= 16 && lds <= 160 * 1024 && t.gmax <= Hd * 4 * kGatherPerThread;
+  };
+  g.mfma2 = false;
+  const TilePlan* t2 = nullptr;
+  if (g.mfma && (Hd == 64 || Hd == 128)) {
+    build_tiles(p, L, 0, tp2, true);
+    if (fits2(tp2, g.mfma2_lds, g.stage2_words)) t2 = &tp2;
+    else if (fits2(tp, g.mfma2_lds, g.stage2_words)) t2 = &tp;
+    g.mfma2 = t2 != nullptr;
+  }
   if (g.mfma) {
     std::vector<uint16_t> wa16((size_t)L * Hd * Hd), wb16(wa16.size()), w1_16(wa16.size()), w2_16(wa16.size());
     auto b16 = [](float v) {
@@ -1682,7 +1761,13 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
           w2_16[dst] = b16(Wn2T[src]);
         }
     UP(Wa16, wa16) UP(Wb16, wb16) UP(Wn1_16, w1_16) UP(Wn2_16, w2_16)
-    UP(prog, tp.prog) UP(elist, tp.elist) UP(glist, tp.glist)
+    UP(prog, tp.prog) UP(elist, tp.elist)
+    if (t2) {
+      UP(glist, t2->glist) UP(t2_meta, t2->meta) UP(t2_V, t2->V) UP(t2_Vself, t2->Vself) UP(t2_colmap, t2->colmap)
+      g.t2_tiles = t2->n_tiles;
+      g.t2_cap1 = t2->cap1;
+      g.t2_cap2 = t2->cap2;
+    }
     // forward column tiles: greedily add target nodes while targets plus their
     // senders fit in NC columns; targets occupy the first columns
     const size_t NC = 16 * (size_t)fwd_groups(Hd);
@@ -1875,8 +1960,8 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.L = g.L;
     ma.nu = p->dims.nu;
     ma.meta_stride = g.meta_stride;
-    ma.cap1 = g.cap1;
-    ma.cap2 = g.cap2;
+    ma.cap1 = g.t2_cap1;
+    ma.cap2 = g.t2_cap2;
     ma.stage_words = g.stage2_words;
     ma.dt = g.dt;
     ma.encT = g.encT;
@@ -1889,13 +1974,14 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.mask_node = g.mask_node;
     ma.mask_edge = g.mask_edge;
     ma.cnt = reinterpret_cast<const uint32_t*>(g.cnt);
-    ma.meta = g.meta;
+    ma.meta = g.t2_meta;
     ma.seed = g.seed;
     ma.seedcol = g.seedcol;
     ma.seedact = g.seedact;
-    ma.V = g.V;
-    ma.Vself = g.Vself;
+    ma.V = g.t2_V;
+    ma.Vself = g.t2_Vself;
     ma.glist = g.glist;
+    ma.colmap = g.t2_colmap;
     ma.out3 = g.out3;
     ma.bout2 = g.bout2;
     ma.A = (float*)A;
@@ -1903,8 +1989,9 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.nnz = p->nnz;
     const void* kfn = Hd == 64 ? (const void*)jvp_mfma2_kernel<64> : (const void*)jvp_mfma2_kernel<128>;
     GNMPC_HIP_TRY(p, set_max_lds(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma2_lds));
-    if (Hd == 64) jvp_mfma2_kernel<64><<<grid, 256, g.mfma2_lds, s>>>(ma);
-    else jvp_mfma2_kernel<128><<<grid, 512, g.mfma2_lds, s>>>(ma);
+    dim3 grid2(g.t2_tiles, N);
+    if (Hd == 64) jvp_mfma2_kernel<64><<<grid2, 256, g.mfma2_lds, s>>>(ma);
+    else jvp_mfma2_kernel<128><<<grid2, 512, g.mfma2_lds, s>>>(ma);
   } else if (g.mfma) {
     MfmaArgs ma;
     ma.N = N;
