@@ -78,22 +78,26 @@ constexpr int kCols = 16;  // tangent columns per seed tile
 
 // Stage layout of the register-aggregate Jacobian kernel, per round l >= 1
 // (32-bit words): one record per node p of round l-1 -- [0] index of p in
-// round l, [1] bit set of p's receivers in round l, [2..3] unused,
+// round l (equal to p: each round starts with the previous round's nodes),
+// [1] bit set of p's receivers in round l, [2..3] unused,
 // [4 + 16 w + q] word w of the ReLU mask of edge (receiver q <- p) or 0,
 // [4 + 16 HW + g] four byte counters of p's active in-edges for features
 // 4g..4g+3 -- then the node-update masks of the nodes of round l ([q][HW]),
-// then the index of each node of round l in round l-1 (or -1), each padded
-// to 4 words; after the last round, one 4-word record per output block.  The
-// host builds, per round, a list of (word, source) pairs that fills it from
-// the forward pass.
+// padded to 4 words; after the last round, one 4-word record per output
+// block.  The host builds, per round, a list of (word, source) pairs that
+// fills it from the forward pass.
 enum GatherKind { kGEdgeMask = 0, kGNodeMask = 1, kGCount = 2, kGConst = 3 };
 __host__ __device__ constexpr int stage_record_words(int Hd) { return 4 + 16 * (Hd / 32) + Hd / 4; }
 
-__device__ inline float bf16r(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return __uint_as_float(u & 0xFFFF0000u);
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+
+// Round to bf16, nearest-even (one v_cvt_pk_bf16_f32 on gfx950).
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  const float2v_t f = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
+__device__ inline float bf16r(float x) { return __uint_as_float(pack_bf16x2(0.f, x) & 0xFFFF0000u); }
 
 float host_bf16r(float x) {
   uint32_t u;
@@ -412,9 +416,6 @@ struct MfmaArgs {
   long nnz;
 };
 
-__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
-  return (__float_as_uint(bf16r(lo)) >> 16) | (__float_as_uint(bf16r(hi)) & 0xFFFF0000u);
-}
 
 // LDS columns are XOR-swizzled in 16-byte chunks by (column & 7), so the 16
 // lanes that read one k-slice of 16 different columns hit different banks.
@@ -746,6 +747,16 @@ __device__ inline bf16x8_t ldw(const uint16_t* base, uint32_t off) {
   return *reinterpret_cast<const bf16x8_t*>(base + off);
 }
 
+// Weight fragments through buffer resources: one 32-bit lane offset with the
+// k-block in the immediate field and the round in the scalar offset.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ inline __amdgpu_buffer_rsrc_t weight_rsrc(const uint16_t* w, int elems) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(w), (short)0, 2 * elems, 0x00020000);
+}
+__device__ inline bf16x8_t ldwr(__amdgpu_buffer_rsrc_t r, uint32_t voff_bytes, uint32_t soff_bytes) {
+  return __builtin_bit_cast(bf16x8_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff_bytes, soff_bytes, 0));
+}
+
 template <int Hd>
 __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   constexpr int NW = Hd / 16;   // waves
@@ -763,9 +774,14 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   float* DT = reinterpret_cast<float*>(ST + a.stage_words);                    // decoder rows 3..5, [3][Hd]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  // phase A: wave w owns output features [16 w, 16 w + 16) of every node
-  const int f0 = wave * 16 + 4 * grp;
-  const int mw = wave >> 1, msh = 16 * (wave & 1) + 4 * grp;
+  // phase A: wave w owns output features [16 w, 16 w + 16) of every node.  The
+  // tangents are the A operand, so lane (n, g) holds feature fA = 16 w + n of
+  // tangent columns 4 g .. 4 g + 3 and each edge mask is one bit per lane.
+  const int fA = wave * 16 + col;
+  const int mw = fA >> 5, mpos = fA & 31;
+  // byte offset of feature fA in aggregate column 4 g + i: agb + i CB + ((agc ^ i) << 4)
+  const int agb = 4 * grp * CB + (2 * fA & 15);
+  const int agc = (2 * fA) >> 4 ^ ((4 * grp) & (CB >= 256 ? 15 : 7));
   // phase B: node group ng takes nodes q = 2 j + ng; its wave wg owns features [32 wg, 32 wg + 32)
   const int ng = wave / GW, wg = wave % GW;
   const int tile = blockIdx.x, k = blockIdx.y;
@@ -775,11 +791,14 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   // lane offsets of the weight fragments (rows of the A operands): phase A, then phase B's two row tiles
   const uint32_t woA = (uint32_t)((wave * 16 + col) * Hd + grp * 8);
   const uint32_t woB = (uint32_t)((wg * 32 + col) * Hd + grp * 8);
+  const int wel = a.L * Hd * Hd;
+  const __amdgpu_buffer_rsrc_t rWa = weight_rsrc(a.Wa, wel), rWb = weight_rsrc(a.Wb, wel);
+  const __amdgpu_buffer_rsrc_t rW1 = weight_rsrc(a.Wn1, wel), rW2 = weight_rsrc(a.Wn2, wel);
   bf16x8_t wa[KB], wb[KB], w1[2][KB], w2[2][KB];
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
-    wa[kb] = ldw(a.Wa, woA + kb * 32);
-    wb[kb] = ldw(a.Wb, woA + kb * 32);
+    wa[kb] = ldwr(rWa, 2 * woA + 64 * kb, 0);
+    wb[kb] = ldwr(rWb, 2 * woA + 64 * kb, 0);
   }
   // round 0: encoder tangents of the seeds (mask x weight, exact in bf16), 8 features per item
   {
@@ -817,62 +836,64 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     const int vc0 = mt[7 + 2 * (l - 1)];
     const int vb1 = mt[6 + 2 * l], vc1 = mt[7 + 2 * l];
     const int nbase = so + vc0 * SREC;
-    const int sfbase = nbase + (vc1 * HW + 3) / 4 * 4;
     const size_t woff = (size_t)(l - 1) * Hd * Hd;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        w1[m][kb] = ldw(a.Wn1 + woff, woB + 16 * m * Hd + kb * 32);
-        w2[m][kb] = ldw(a.Wn2 + woff, woB + 16 * m * Hd + kb * 32);
+        w1[m][kb] = ldwr(rW1, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
+        w2[m][kb] = ldwr(rW2, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
       }
-    // ---- phase A: edge GEMMs per sender, aggregates of every receiver in registers
+    // ---- phase A: edge GEMMs per sender, aggregates of every receiver in registers.
+    // Round l-1's nodes lead round l in the same order, so sender p is node p of round l.
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    for (int p = 0; p < vc0; ++p) {
-      const uint4* rec4 = reinterpret_cast<const uint4*>(ST) + (so >> 2) + p * (SREC / 4);
-      const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB;
-      bf16x8_t bfr[KB];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swzc<CB>(64 * kb + 16 * grp, col));
-      const uint4 hd = rec4[0];
-      const uint4 t0 = rec4[1 + 4 * mw], t1 = rec4[2 + 4 * mw], t2 = rec4[3 + 4 * mw], t3 = rec4[4 + 4 * mw];
-      const uint32_t cw = reinterpret_cast<const uint32_t*>(rec4)[4 + 16 * HW + (f0 >> 2)];
-      const int qp = __builtin_amdgcn_readfirstlane((int)hd.x);
-      const uint32_t rcv = (uint32_t)__builtin_amdgcn_readfirstlane((int)hd.y);
-      floatx4_t ay = floatx4_t{0.f, 0.f, 0.f, 0.f}, aa = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < MAXV; ++p) {
+      if (p < vc0) {
+        const uint32_t* rec = ST + so + p * SREC;
+        const uint4* rec4 = reinterpret_cast<const uint4*>(rec);
+        const unsigned char* Tp = R1 + ((size_t)p * kCols + col) * CB;
+        bf16x8_t bfr[KB];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        ay = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[kb], bfr[kb], ay, 0, 0, 0);
-        aa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kb], bfr[kb], aa, 0, 0, 0);
-      }
-      const uint32_t tbl[16] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w,
-                                t2.x, t2.y, t2.z, t2.w, t3.x, t3.y, t3.z, t3.w};
-      const uint32_t touch = rcv | (1u << qp);
+        for (int kb = 0; kb < KB; ++kb) bfr[kb] = *reinterpret_cast<const bf16x8_t*>(Tp + swzc<CB>(64 * kb + 16 * grp, col));
+        const uint4 t0 = rec4[1 + 4 * mw], t1 = rec4[2 + 4 * mw], t2 = rec4[3 + 4 * mw], t3 = rec4[4 + 4 * mw];
+        const float cf = (float)reinterpret_cast<const unsigned char*>(rec + 4 + 16 * HW)[fA];
+        const uint32_t rcv = (uint32_t)__builtin_amdgcn_readfirstlane((int)rec[1]);
+        // Yb = W_b dh_p, then P = W_a dh_p + Yb accumulated on top of it
+        floatx4_t ay = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < MAXV; ++q) {
-        if ((touch >> q) & 1u) {
+        for (int kb = 0; kb < KB; ++kb) ay = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb], wb[kb], ay, 0, 0, 0);
+        floatx4_t aa = ay;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) aa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb], wa[kb], aa, 0, 0, 0);
+        const uint32_t tbl[16] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w,
+                                  t2.x, t2.y, t2.z, t2.w, t3.x, t3.y, t3.z, t3.w};
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) {
           if ((rcv >> q) & 1u) {
+            // 1.0f where the edge's ReLU is on for this lane's feature, else 0
+            const float mf = __uint_as_float((uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], mpos, 1) & 0x3F800000u);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              acc[q][i] -= __uint_as_float(__float_as_uint(ay[i]) & (uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], msh + i, 1));
-          }
-          if (q == qp) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[q][i] += (float)((cw >> (8 * i)) & 0xFFu) * (aa[i] + ay[i]);
+            for (int i = 0; i < 4; ++i) acc[q][i] = __builtin_fmaf(-mf, ay[i], acc[q][i]);
           }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[p][i] = __builtin_fmaf(cf, aa[i], acc[p][i]);
       }
     }
     {
-      unsigned char* AGw = AG + (size_t)col * CB + swzc<CB>(2 * f0, col);
+      // bf16 aggregates: this lane's feature in four columns
 #pragma unroll
       for (int q = 0; q < MAXV; ++q) {
         if (q < vc1) {
-          uint2 v;
-          v.x = pack_bf16x2(acc[q][0], acc[q][1]);
-          v.y = pack_bf16x2(acc[q][2], acc[q][3]);
-          *reinterpret_cast<uint2*>(AGw + (size_t)q * kCols * CB) = v;
+          unsigned char* Gq = AG + (size_t)q * kCols * CB;
+          const uint32_t lo = pack_bf16x2(acc[q][0], acc[q][1]), hi = pack_bf16x2(acc[q][2], acc[q][3]);
+          unsigned char* Gl = Gq + agb + (agc << 4);
+          *reinterpret_cast<uint16_t*>(Gl) = (uint16_t)lo;
+          *reinterpret_cast<uint16_t*>(Gl + CB + (((agc ^ 1) - agc) << 4)) = (uint16_t)(lo >> 16);
+          *reinterpret_cast<uint16_t*>(Gl + 2 * CB + (((agc ^ 2) - agc) << 4)) = (uint16_t)hi;
+          *reinterpret_cast<uint16_t*>(Gl + 3 * CB + (((agc ^ 3) - agc) << 4)) = (uint16_t)(hi >> 16);
         }
       }
     }
@@ -881,8 +902,8 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       const size_t wn = (size_t)l * Hd * Hd;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        wa[kb] = ldw(a.Wa + wn, woA + kb * 32);
-        wb[kb] = ldw(a.Wb + wn, woA + kb * 32);
+        wa[kb] = ldwr(rWa, 2 * woA + 64 * kb, (uint32_t)(2 * wn));
+        wb[kb] = ldwr(rWb, 2 * woA + 64 * kb, (uint32_t)(2 * wn));
       }
     }
     // ---- phase B: node GEMMs, two node groups; results stay in registers until every wave is done reading
@@ -891,40 +912,31 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     for (int j = 0; j < MAXV / 2; ++j) {
       const int q = 2 * j + ng;
       if (q < vc1) {
-        floatx4_t c1[2], c2[2];
+        floatx4_t c[2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          c1[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-          c2[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        }
-        const int self = __builtin_amdgcn_readfirstlane((int)ST[sfbase + q]);
-        const unsigned char* Ts = R1 + ((size_t)(self >= 0 ? self : 0) * kCols + col) * CB;
+        for (int m = 0; m < 2; ++m) c[m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         const unsigned char* Gq = AGg + (size_t)(2 * j) * kCols * CB;
-        if (self >= 0) {
+        if (q < vc0) {  // node q of round l-1 is node q of round l
+          const unsigned char* Ts = R1 + ((size_t)q * kCols + col) * CB;
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb) {
             const bf16x8_t bs = *reinterpret_cast<const bf16x8_t*>(Ts + swzc<CB>(64 * kb + 16 * grp, col));
-            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swzc<CB>(64 * kb + 16 * grp, col));
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-              c1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m][kb], bs, c1[m], 0, 0, 0);
-              c2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c2[m], 0, 0, 0);
-            }
+            for (int m = 0; m < 2; ++m) c[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m][kb], bs, c[m], 0, 0, 0);
           }
-        } else {
+        }
 #pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swzc<CB>(64 * kb + 16 * grp, col));
+        for (int kb = 0; kb < KB; ++kb) {
+          const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Gq + swzc<CB>(64 * kb + 16 * grp, col));
 #pragma unroll
-            for (int m = 0; m < 2; ++m) c2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c2[m], 0, 0, 0);
-          }
+          for (int m = 0; m < 2; ++m) c[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m][kb], bg, c[m], 0, 0, 0);
         }
         const int bits = (int)ST[nbase + q * HW + wg];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            acc[2 * j + m][i] = __uint_as_float(__float_as_uint(c1[m][i] + c2[m][i]) &
+            acc[2 * j + m][i] = __uint_as_float(__float_as_uint(c[m][i]) &
                                                 (uint32_t)__builtin_amdgcn_sbfe(bits, 16 * m + 4 * grp + i, 1));
       }
     }
@@ -947,7 +959,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       }
       __syncthreads();
     }
-    so = sfbase + (vc1 + 3) / 4 * 4;
+    so = nbase + (vc1 * HW + 3) / 4 * 4;
   }
 
   // ---- decoder: velocity rows 3..5 of W_dec on the last round's FP32 tangents
@@ -1376,18 +1388,25 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
   const int HW = Hd / 32;
   std::vector<int32_t> where(M, -1);
   auto ncols_of = [&](int node) { return 6 + (act_of[node] >= 0 ? 3 : 0); };
+  // Round l holds round l-1's nodes first, in their order, then their other
+  // receivers sorted by node, so a node keeps its index from round to round.
   auto rounds_of = [&](const std::vector<int32_t>& v0) {
     std::vector<std::vector<int32_t>> Vl(L + 1);
     Vl[0] = v0;
     for (int l = 1; l <= L; ++l) {
-      std::vector<int32_t> nxt = Vl[l - 1];
+      std::vector<int32_t> fresh;
       for (int32_t j : Vl[l - 1])
-        for (int32_t r : outn[j]) nxt.push_back(r);
-      std::sort(nxt.begin(), nxt.end());
-      nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
-      Vl[l] = nxt;
+        for (int32_t r : outn[j])
+          if (std::find(Vl[l - 1].begin(), Vl[l - 1].end(), r) == Vl[l - 1].end()) fresh.push_back(r);
+      std::sort(fresh.begin(), fresh.end());
+      fresh.erase(std::unique(fresh.begin(), fresh.end()), fresh.end());
+      Vl[l] = Vl[l - 1];
+      Vl[l].insert(Vl[l].end(), fresh.begin(), fresh.end());
     }
     return Vl;
+  };
+  auto idx_in = [](const std::vector<int32_t>& v, int32_t node) {
+    return (int32_t)(std::find(v.begin(), v.end(), node) - v.begin());
   };
   int i = 0, dpos = 0;  // column stream position: node i, its dimension dpos
   while (i < M) {
@@ -1497,13 +1516,13 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
       const std::vector<int32_t>& nx = Vl[l];
       const int pb = (int32_t)tp.prog.size(), eb = (int32_t)tp.elist.size();
       for (int32_t node : prv) {
-        tp.prog.push_back((int32_t)(std::lower_bound(nx.begin(), nx.end(), node) - nx.begin()));
+        tp.prog.push_back(idx_in(nx, node));
         const int nin = p->h_row_ptr[node + 1] - p->h_row_ptr[node];
         tp.prog.push_back(nin);
         tp.prog.push_back((int32_t)outn[node].size());
         for (int e = p->h_row_ptr[node]; e < p->h_row_ptr[node + 1]; ++e) tp.elist.push_back(e);
         for (int32_t r : outn[node]) {
-          tp.prog.push_back((int32_t)(std::lower_bound(nx.begin(), nx.end(), r) - nx.begin()));
+          tp.prog.push_back(idx_in(nx, r));
           const int32_t* rb = p->h_col.data() + p->h_row_ptr[r];
           const int32_t* re = p->h_col.data() + p->h_row_ptr[r + 1];
           tp.elist.push_back((int32_t)(std::lower_bound(rb, re, node) - p->h_col.data()));
@@ -1535,7 +1554,7 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
           const int rec = so + (int)pp * SREC;
           uint32_t rcv = 0;
           for (int32_t r : outn[node]) {
-            const int q = (int)(std::lower_bound(nx.begin(), nx.end(), r) - nx.begin());
+            const int q = idx_in(nx, r);
             if (q >= 16) continue;  // more than 16 nodes in a round: this kernel is not used
             rcv |= 1u << q;
             const int32_t* rb = p->h_col.data() + p->h_row_ptr[r];
@@ -1543,19 +1562,14 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
             const int32_t e = (int32_t)(std::lower_bound(rb, re, node) - p->h_col.data());
             for (int w = 0; w < HW; ++w) item(rec + 4 + 16 * w + q, kGEdgeMask, e * HW + w);
           }
-          item(rec, kGConst, (int32_t)(std::lower_bound(nx.begin(), nx.end(), node) - nx.begin()));
+          item(rec, kGConst, idx_in(nx, node));
           item(rec + 1, kGConst, (int32_t)rcv);
           for (int g4 = 0; g4 < Hd / 4; ++g4) item(rec + 4 + 16 * HW + g4, kGCount, node * (Hd / 4) + g4);
         }
         const int nb = so + (int)prv.size() * SREC;
         for (size_t q = 0; q < nx.size(); ++q)
           for (int w = 0; w < HW; ++w) item(nb + (int)q * HW + w, kGNodeMask, nx[q] * HW + w);
-        const int sfb = nb + ((int)nx.size() * HW + 3) / 4 * 4;
-        for (size_t q = 0; q < nx.size(); ++q) {
-          auto it = std::lower_bound(prv.begin(), prv.end(), nx[q]);
-          item(sfb + (int)q, kGConst, (it != prv.end() && *it == nx[q]) ? (int32_t)(it - prv.begin()) : -1);
-        }
-        so = sfb + ((int)nx.size() + 3) / 4 * 4;
+        so = nb + ((int)nx.size() * HW + 3) / 4 * 4;
         if (l == L) {
           // output records (the tile's columns of each block):
           //   A blocks {CSR block id, node index q, first column, first dim | count << 8 | diagonal << 16},
