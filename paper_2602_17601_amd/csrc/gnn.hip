@@ -58,7 +58,9 @@ struct GnnState {
   bool mfma2 = false;
   size_t mfma2_lds = 0;
   int stage2_words = 0, t2_tiles = 0, t2_cap1 = 0, t2_cap2 = 0;
-  int32_t *glist = nullptr, *t2_meta = nullptr, *t2_V = nullptr, *t2_Vself = nullptr, *t2_colmap = nullptr;
+  int32_t *img_src = nullptr, *t2_meta = nullptr, *t2_V = nullptr, *t2_Vself = nullptr, *t2_colmap = nullptr;
+  uint32_t* img = nullptr;  // stage images [N][img_words]
+  long img_words = 0;
   // matrix-core forward pass (BF16): hidden states as bf16, node column tiles
   uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
   uint8_t* cnt = nullptr;         // [L][N][M][Hd] active in-edges of each node per feature
@@ -84,9 +86,13 @@ constexpr int kCols = 16;  // tangent columns per seed tile
 // [4 + 16 HW + g] four byte counters of p's active in-edges for features
 // 4g..4g+3 -- then the node-update masks of the nodes of round l ([q][HW]),
 // padded to 4 words; after the last round, one 4-word record per output
-// block.  The host builds, per round, a list of (word, source) pairs that
-// fills it from the forward pass.
-enum GatherKind { kGEdgeMask = 0, kGNodeMask = 1, kGCount = 2, kGConst = 3 };
+// block, then the encoder block: the tile's 16 column-map words and the
+// encoder ReLU masks of round 0's nodes ([q][HW]).  The host describes every
+// word of a tile's stage by its source, (kind | round << 4, index), and a
+// gather kernel writes the stage image of every (tile, stage) to global
+// memory after the forward pass, so the Jacobian kernel reads its stage in
+// one contiguous copy.
+enum GatherKind { kGEdgeMask = 0, kGNodeMask = 1, kGCount = 2, kGConst = 3, kGEncMask = 4 };
 __host__ __device__ constexpr int stage_record_words(int Hd) { return 4 + 16 * (Hd / 32) + Hd / 4; }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -696,51 +702,45 @@ struct Mfma2Args {
   const float *encT, *decT;
   const uint16_t *Wa, *Wb, *Wn1, *Wn2;
   const uint32_t *mask_enc, *mask_node, *mask_edge, *cnt;
-  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *glist, *out3, *bout2, *colmap;
+  const int32_t *meta, *seed, *seedcol, *seedact, *V, *Vself, *out3, *bout2, *colmap;
+  const uint32_t* img;  // stage images, [N][img_words]
+  long img_words;
   float *A, *B;
   long nnz;
 };
 
-constexpr int kGatherPerThread = 8;
-
-// Gather of every round's stage words at the start of the workgroup: all list
-// entries are fetched first, then all values (no branches on the loads:
-// out-of-range slots read entry 0 and are dropped), then stored to LDS.
-template <int Hd, int NT>
-__device__ inline void gather_all(const Mfma2Args& a, int k, const int32_t* mt, uint32_t* ST) {
+// Stage images: word w of (tile, stage k) = its source, read from the forward
+// pass's masks and counters of stage k (or a constant).  One thread per word
+// and all stages, so each source entry is read once; the source list holds
+// (kind | round << 4, index) pairs for every tile.
+template <int Hd>
+__global__ void stage_image_kernel(int N, int M, int E, long img_words, const int32_t* __restrict__ src,
+                                   const uint32_t* __restrict__ mask_enc, const uint32_t* __restrict__ mask_node,
+                                   const uint32_t* __restrict__ mask_edge, const uint32_t* __restrict__ cnt,
+                                   uint32_t* __restrict__ img) {
   constexpr int HW = Hd / 32;
-  const int* gm = mt + 6 + 2 * (a.L + 1) + 4 * a.L;
-  const int gb = gm[0];
-  int gc = 0;
-  for (int l = 1; l <= a.L; ++l) gc += gm[2 * (l - 1) + 1];
-  const int2* gl = reinterpret_cast<const int2*>(a.glist);
-  int2 it[kGatherPerThread];
+  const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= img_words) return;
+  const int2 it = reinterpret_cast<const int2*>(src)[w];
+  const int kind = it.x & 15, l = it.x >> 4;
+  // stage k's word sits at base + k * step (step 0 for a constant)
+  const uint32_t* base = &mask_enc[0];
+  size_t step = 0;
+  const size_t lo = (size_t)(l > 0 ? l - 1 : 0) * N;
+  if (kind == kGEdgeMask) { base = mask_edge + lo * E * HW + it.y; step = (size_t)E * HW; }
+  else if (kind == kGNodeMask) { base = mask_node + lo * M * HW + it.y; step = (size_t)M * HW; }
+  else if (kind == kGCount) { base = cnt + lo * M * (Hd / 4) + it.y; step = (size_t)M * (Hd / 4); }
+  else if (kind == kGEncMask) { base = mask_enc + it.y; step = (size_t)M * HW; }
+  const bool cst = kind == kGConst;
+  int k = 0;
+  for (; k + 4 <= N; k += 4) {
+    uint32_t v[4];
 #pragma unroll
-  for (int j = 0; j < kGatherPerThread; ++j) {
-    const int t = threadIdx.x + j * NT;
-    it[j] = gl[t < gc ? gb + t : 0];
+    for (int u = 0; u < 4; ++u) v[u] = cst ? (uint32_t)it.y : base[(size_t)(k + u) * step];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) img[(size_t)(k + u) * img_words + w] = v[u];
   }
-  // round of each entry: the lists of consecutive rounds are contiguous
-  uint32_t v[kGatherPerThread];
-#pragma unroll
-  for (int j = 0; j < kGatherPerThread; ++j) {
-    const int t = threadIdx.x + j * NT;
-    int l = 1, end = gm[1];
-    while (l < a.L && t >= end) {
-      end += gm[2 * l + 1];
-      ++l;
-    }
-    const int kind = (int)((uint32_t)it[j].x >> 28);
-    const size_t slab = (size_t)(l - 1) * a.N + k;
-    const uint32_t* base = kind == kGEdgeMask ? a.mask_edge + slab * a.E * HW
-                         : kind == kGNodeMask ? a.mask_node + slab * a.M * HW : a.cnt + slab * a.M * (Hd / 4);
-    const bool load = t < gc && kind != kGConst;
-    const uint32_t x = base[load ? it[j].y : 0];
-    v[j] = kind == kGConst ? (uint32_t)it[j].y : x;
-  }
-#pragma unroll
-  for (int j = 0; j < kGatherPerThread; ++j)
-    if ((int)threadIdx.x + j * NT < gc) ST[it[j].x & 0x0FFFFFFF] = v[j];
+  for (; k < N; ++k) img[(size_t)k * img_words + w] = cst ? (uint32_t)it.y : base[(size_t)k * step];
 }
 
 __device__ inline bf16x8_t ldw(const uint16_t* base, uint32_t off) {
@@ -772,6 +772,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   unsigned char* AG = R1 + (size_t)a.cap1 * kCols * CB;             // [cap2][16] bf16 aggregate columns
   uint32_t* ST = reinterpret_cast<uint32_t*>(AG + (size_t)a.cap2 * kCols * CB);  // stage words
   float* DT = reinterpret_cast<float*>(ST + a.stage_words);                    // decoder rows 3..5, [3][Hd]
+  float* ET = DT + 3 * Hd;                                                     // encoder weights [9][Hd]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   // phase A: wave w owns output features [16 w, 16 w + 16) of every node.  The
@@ -800,17 +801,27 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     wa[kb] = ldwr(rWa, 2 * woA + 64 * kb, 0);
     wb[kb] = ldwr(rWb, 2 * woA + 64 * kb, 0);
   }
+  // start-up: the stage image (one contiguous read), decoder rows and encoder weights to LDS
+  {
+    const int ib = mt[6 + 2 * (a.L + 1) + 4 * a.L], nw = mt[6 + 2 * (a.L + 1) + 4 * a.L + 1];
+    const uint4* im = reinterpret_cast<const uint4*>(a.img + (size_t)k * a.img_words + ib);
+    for (int t = threadIdx.x; t < nw / 4; t += NT) reinterpret_cast<uint4*>(ST)[t] = im[t];
+  }
+  for (int t = threadIdx.x; t < 3 * Hd; t += NT) DT[t] = a.decT[(t % Hd) * 6 + 3 + t / Hd];
+  for (int t = threadIdx.x; t < 9 * Hd / 4; t += NT) reinterpret_cast<float4*>(ET)[t] = reinterpret_cast<const float4*>(a.encT)[t];
+  __syncthreads();
   // round 0: encoder tangents of the seeds (mask x weight, exact in bf16), 8 features per item
   {
-    const int vb = mt[6], vc = mt[7];
+    const int vc = mt[7];
+    const uint32_t* CM = ST + mt[a.meta_stride - 1];  // (seed << 4) | dimension of each column, or -1
+    const uint32_t* EM = CM + kCols;                  // encoder masks of round 0's nodes
     for (int t = threadIdx.x; t < vc * kCols * (Hd / 8); t += NT) {
       const int q = t / (kCols * (Hd / 8)), c = (t / (Hd / 8)) % kCols, fc = t % (Hd / 8);
-      const int node = a.V[vb + q];
-      const int cm = a.colmap[(size_t)tile * kCols + c];  // (seed << 4) | dimension of column c
+      const int cm = (int)CM[c];
       const bool valid = cm >= 0 && (cm >> 4) == q;
       const int d = cm & 15;
-      const uint32_t bits = (a.mask_enc[((size_t)k * a.M + node) * HW + (fc >> 2)] >> (8 * (fc & 3))) & 0xFFu;
-      const float4* e4 = reinterpret_cast<const float4*>(a.encT + (size_t)(valid ? d : 0) * Hd + 8 * fc);
+      const uint32_t bits = (EM[q * HW + (fc >> 2)] >> (8 * (fc & 3))) & 0xFFu;
+      const float4* e4 = reinterpret_cast<const float4*>(ET + (valid ? d : 0) * Hd + 8 * fc);
       const float4 lo = e4[0], hi = e4[1];
       const float ev[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
       uint32_t pk[4];
@@ -823,11 +834,6 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       *reinterpret_cast<uint4*>(R1 + ((size_t)q * kCols + c) * CB + swzc<CB>(16 * fc, c)) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
   }
-  for (int t = threadIdx.x; t < a.stage_words / 4; t += NT)
-    reinterpret_cast<uint4*>(ST)[t] = make_uint4(0u, 0u, 0u, 0u);
-  for (int t = threadIdx.x; t < 3 * Hd; t += NT) DT[t] = a.decT[(t % Hd) * 6 + 3 + t / Hd];
-  __syncthreads();
-  gather_all<Hd, NT>(a, k, mt, ST);
   __syncthreads();
 
   floatx4_t acc[MAXV];
@@ -1358,12 +1364,12 @@ struct TilePlan {
   // per (tile, round l >= 1): the sender program {qp, n_in, n_out, qr...} of every node of
   // round l-1 and the CSR ids of the edges whose masks it reads (in-edges, then out-edges)
   std::vector<int32_t> prog, elist;
-  // per (tile, round l >= 1): gather list that fills the LDS stage of the
-  // register-aggregate kernel, pairs (destination word | kind << 28, source)
-  std::vector<int32_t> glist;
   // per tile and tangent column: (seed index in the tile << 4) | state or force dimension, or -1
   std::vector<int32_t> colmap;
-  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0, stage2_cap = 0, gmax = 0, vmax = 0;
+  // stage image sources of the register-aggregate kernel: every word of every
+  // tile's stage as a (kind | round << 4, index) pair, tiles at multiples of 4 words
+  std::vector<int32_t> img;
+  int bufX = 0, bufY = 0, n_tiles = 0, cap1 = 0, cap2 = 0, stage_cap = 0, stage2_cap = 0, vmax = 0;
 };
 
 
@@ -1383,7 +1389,7 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
     for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) outn[p->h_col[e]].push_back(i);
   std::vector<int32_t> act_of(M, -1);
   for (int a = 0; a < (int)p->h_act.size(); ++a) act_of[p->h_act[a]] = a;
-  const int stride = 6 + 2 * (L + 1) + 4 * L + 2 * L;
+  const int stride = 6 + 2 * (L + 1) + 4 * L + 2 * L + 1;
   const int Hd = p->gnn ? p->gnn->Hd : 128;
   const int HW = Hd / 32;
   std::vector<int32_t> where(M, -1);
@@ -1536,18 +1542,19 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
       const int words = (m[base + 1] + 3) / 4 * 4 + m[base + 3] * HW + (int)nx.size() * HW;
       tp.stage_cap = std::max(tp.stage_cap, words);
     }
-    // gather lists of the register-aggregate kernel
+    // stage image sources of the register-aggregate kernel
     int ocount = 0, bcount = 0;
     {
       const int SREC = stage_record_words(Hd);
       int so = 0;
+      std::vector<int32_t> sp;  // (word, kind | round << 4, source) of every sourced word
       for (int l = 1; l <= L; ++l) {
         const std::vector<int32_t>& prv = Vl[l - 1];
         const std::vector<int32_t>& nx = Vl[l];
-        const int gb = (int)tp.glist.size() / 2;
         auto item = [&](int dst, int kind, int32_t src) {
-          tp.glist.push_back(dst | (kind << 28));
-          tp.glist.push_back(src);
+          sp.push_back(dst);
+          sp.push_back(kind | (l << 4));
+          sp.push_back(src);
         };
         for (size_t pp = 0; pp < prv.size(); ++pp) {
           const int32_t node = prv[pp];
@@ -1607,13 +1614,26 @@ void build_tiles(const gnmpc_plan* p, int L, int max_seeds, TilePlan& tp, bool p
               item(so++, kGConst, (3 * act_of[c.node] + (f0 - 6)) | ((f1 - f0) << 8));
               ++bcount;
             }
+          // encoder block: the tile's column map, then the encoder masks of round 0's nodes
+          m[stride - 1] = so;
+          const size_t cmb = tp.colmap.size() - kCols;
+          for (int c = 0; c < kCols; ++c) item(so++, kGConst, tp.colmap[cmb + c]);
+          for (size_t q = 0; q < Vl[0].size(); ++q)
+            for (int w = 0; w < HW; ++w) item(so++, kGEncMask, Vl[0][q] * HW + w);
         }
-        const int gc = (int)tp.glist.size() / 2 - gb;
-        m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1)] = gb;
-        m[6 + 2 * (L + 1) + 4 * L + 2 * (l - 1) + 1] = gc;
       }
-      tp.gmax = std::max(tp.gmax, (int)tp.glist.size() / 2 - m[6 + 2 * (L + 1) + 4 * L]);
-      tp.stage2_cap = std::max(tp.stage2_cap, so);
+      // dense image sources: words without a source are constant zeros
+      const int words = (so + 3) / 4 * 4;
+      const size_t ib = tp.img.size() / 2;
+      tp.img.resize(tp.img.size() + 2 * (size_t)words, 0);
+      for (int w = 0; w < words; ++w) tp.img[2 * (ib + w)] = kGConst;
+      for (size_t t = 0; t < sp.size(); t += 3) {
+        tp.img[2 * (ib + sp[t])] = sp[t + 1];
+        tp.img[2 * (ib + sp[t]) + 1] = sp[t + 2];
+      }
+      m[6 + 2 * (L + 1) + 4 * L] = (int32_t)ib;
+      m[6 + 2 * (L + 1) + 4 * L + 1] = words;
+      tp.stage2_cap = std::max(tp.stage2_cap, words);
     }
     // output blocks: (node of the last round, seed) pairs inside the pattern
     m[2] = (int32_t)(tp.out3.size() / 3);
@@ -1733,7 +1753,7 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     return GNMPC_UNSUPPORTED;
   }
   g.n_tiles = tp.n_tiles;
-  g.meta_stride = 6 + 2 * (L + 1) + 4 * L + 2 * L;
+  g.meta_stride = 6 + 2 * (L + 1) + 4 * L + 2 * L + 1;
   g.bufX = tp.bufX;
   g.bufY = tp.bufY;
   // The matrix-core path needs BF16, a supported width and the round buffers in LDS.
@@ -1747,8 +1767,8 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   TilePlan tp2;
   auto fits2 = [&](const TilePlan& t, size_t& lds, int& words) {
     words = (t.stage2_cap + 3) / 4 * 4;
-    lds = (size_t)(t.cap1 + t.cap2) * kCols * Hd * 2 + (size_t)words * 4 + (size_t)3 * Hd * 4;
-    return t.vmax <= 16 && lds <= 160 * 1024 && t.gmax <= Hd * 4 * kGatherPerThread;
+    lds = (size_t)(t.cap1 + t.cap2) * kCols * Hd * 2 + (size_t)words * 4 + (size_t)(3 + 9) * Hd * 4;
+    return t.vmax <= 16 && lds <= 160 * 1024;
   };
   g.mfma2 = false;
   const TilePlan* t2 = nullptr;
@@ -1777,10 +1797,12 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
     UP(Wa16, wa16) UP(Wb16, wb16) UP(Wn1_16, w1_16) UP(Wn2_16, w2_16)
     UP(prog, tp.prog) UP(elist, tp.elist)
     if (t2) {
-      UP(glist, t2->glist) UP(t2_meta, t2->meta) UP(t2_V, t2->V) UP(t2_Vself, t2->Vself) UP(t2_colmap, t2->colmap)
+      UP(img_src, t2->img) UP(t2_meta, t2->meta) UP(t2_V, t2->V) UP(t2_Vself, t2->Vself) UP(t2_colmap, t2->colmap)
       g.t2_tiles = t2->n_tiles;
       g.t2_cap1 = t2->cap1;
       g.t2_cap2 = t2->cap2;
+      g.img_words = (long)(t2->img.size() / 2);
+      if ((s = dalloc(p, g.img, (size_t)g.N * g.img_words)) != GNMPC_OK) return s;
     }
     // forward column tiles: greedily add target nodes while targets plus their
     // senders fit in NC columns; targets occupy the first columns
@@ -1994,7 +2016,8 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.seedact = g.seedact;
     ma.V = g.t2_V;
     ma.Vself = g.t2_Vself;
-    ma.glist = g.glist;
+    ma.img = g.img;
+    ma.img_words = g.img_words;
     ma.colmap = g.t2_colmap;
     ma.out3 = g.out3;
     ma.bout2 = g.bout2;
@@ -2003,6 +2026,14 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.nnz = p->nnz;
     const void* kfn = Hd == 64 ? (const void*)jvp_mfma2_kernel<64> : (const void*)jvp_mfma2_kernel<128>;
     GNMPC_HIP_TRY(p, set_max_lds(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma2_lds));
+    // stage images of every (tile, stage) from this forward pass
+    const dim3 gimg((unsigned)((g.img_words + 255) / 256));
+    if (Hd == 64)
+      stage_image_kernel<64><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
+                                                  g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
+    else
+      stage_image_kernel<128><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
+                                                   g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
     dim3 grid2(g.t2_tiles, N);
     if (Hd == 64) jvp_mfma2_kernel<64><<<grid2, 256, g.mfma2_lds, s>>>(ma);
     else jvp_mfma2_kernel<128><<<grid2, 512, g.mfma2_lds, s>>>(ma);
