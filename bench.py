@@ -5,9 +5,11 @@ One step is one pass of the whole hot path of Algorithm 1 on resident inputs:
 linearize the GNN (forward pass + forward-mode Jacobians, BF16 MLPs with FP32
 accumulation), condense (S_k / Gx_k recursion, H, g, 200 node-position rows,
 FP32) and solve the condensed box QP (ADMM, FP32).  The plain form (analytic
-mass-spring-damper Jacobians on the same graph) is timed beside it.
+mass-spring-damper Jacobians on the same graph) is timed beside it.  The
+step is captured once as a HIP graph and replayed (``--eager`` times eager
+launches instead).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--eager]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -124,6 +126,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eagerly launched steps instead of replays of the step captured as a HIP graph")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB 5 times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -182,9 +186,12 @@ def main():
                           settings=settings)
 
     def timed(plan, b):
-        """Throughput over exactly args.steps steps with no event records in
-        the stream; then the same number of steps again with the per-phase
-        HIP-event timers on (the events add gaps, so they stay out of `value`)."""
+        """Throughput over exactly args.steps steps: replays of the whole step
+        captured once as a HIP graph (or eager launches with --eager), with no
+        event records in the timed stream.  Then the eager throughput, the
+        per-step median and p95 of the replays (an event pair around each),
+        and the per-phase HIP-event timers on eager steps (the events add
+        gaps, so they stay out of `value`)."""
         for _ in range(args.warmup):
             step(plan, b)
         torch.cuda.synchronize()
@@ -192,19 +199,42 @@ def main():
         for _ in range(args.steps):
             step(plan, b)
         torch.cuda.synchronize()
+        el_eager = time.perf_counter() - t0
+        graph = None
+        if not args.eager:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                step(plan, b)
+            for _ in range(args.warmup):
+                graph.replay()
+            torch.cuda.synchronize()
+        run = graph.replay if graph is not None else (lambda: step(plan, b))
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e0, e1 in ev:
+            e0.record()
+            run()
+            e1.record()
+        torch.cuda.synchronize()
+        per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        stats = {"median_ms": per[len(per) // 2], "p95_ms": per[min(len(per) - 1, int(0.95 * len(per)))],
+                 "eager_steps_per_s": args.steps / el_eager}
         plan.timers_enable(True)
         for _ in range(args.steps):
             step(plan, b)
         torch.cuda.synchronize()
         phases = plan.timers_read()
         plan.timers_enable(False)
-        return el, phases
+        return el, phases, stats
 
     plan_g, bg = make(P, True)
     plan_m, bm = make(Pm, False)
-    el_g, ph_g = timed(plan_g, bg)
-    el_m, ph_m = timed(plan_m, bm)
+    el_g, ph_g, st_g = timed(plan_g, bg)
+    el_m, ph_m, st_m = timed(plan_m, bm)
     qpi = gn.qp_info(bg["info"])
     steps_g = args.steps / el_g
     steps_m = args.steps / el_m
@@ -237,8 +267,14 @@ def main():
         "config": {"workload": ("1000-node 1-2-hop chain, GNN Hd=128 L=3 (BF16 MLPs, FP32 accumulate), "
                                 "n_u=12 at 4 nodes, N=20, 200 node-position rows, FP32 condensing, ADMM box QP"),
                    "M": P.M, "N": P.N, "nu": P.nu, "nnz_blocks": int(plan_g.nnz), "state_rows": P.rows.n},
+        "timing": "eager launches" if args.eager else "HIP graph replay of the whole step",
+        "median_ms_per_step": st_g["median_ms"],
+        "p95_ms_per_step": st_g["p95_ms"],
+        "eager_steps_per_s": st_g["eager_steps_per_s"],
         "plain_steps_per_s": steps_m,
         "plain_ms_per_step": el_m / args.steps * 1e3,
+        "plain_median_ms_per_step": st_m["median_ms"],
+        "plain_eager_steps_per_s": st_m["eager_steps_per_s"],
         "phase_ms_gnn": phase_avg(ph_g),
         "phase_ms_plain": phase_avg(ph_m),
         "qp_iters_gnn": qpi.iters,
