@@ -239,7 +239,8 @@ typedef enum {
   GNMPC_PH_CONDENSE_GRAM = 5,     /* H and g                                           */
   GNMPC_PH_CONDENSE_ROWS = 6,     /* condensed state rows                              */
   GNMPC_PH_QP = 7,                /* the QP solve                                      */
-  GNMPC_PH_COUNT = 8
+  GNMPC_PH_GNN_STAGE_IMAGES = 8,  /* the Jacobian kernel's stage images from the forward pass */
+  GNMPC_PH_COUNT = 9
 } gnmpc_phase;
 
 /* Enable (1) or disable (0) the timers; enabling clears earlier records and

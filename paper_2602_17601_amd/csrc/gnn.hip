@@ -1987,6 +1987,18 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   ja.B = (float*)B;
   ja.nnz = p->nnz;
   dim3 grid(g.n_tiles, N);
+  if (g.mfma2) {
+    // stage images of every (tile, stage) from this forward pass
+    phase_begin(p, GNMPC_PH_GNN_STAGE_IMAGES, s);
+    const dim3 gimg((unsigned)((g.img_words + 255) / 256));
+    if (Hd == 64)
+      stage_image_kernel<64><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
+                                                  g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
+    else
+      stage_image_kernel<128><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
+                                                   g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
+    phase_end(p, GNMPC_PH_GNN_STAGE_IMAGES, s);
+  }
   phase_begin(p, GNMPC_PH_GNN_JACOBIAN, s);
   if (g.mfma2) {
     Mfma2Args ma;
@@ -2026,14 +2038,6 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     ma.nnz = p->nnz;
     const void* kfn = Hd == 64 ? (const void*)jvp_mfma2_kernel<64> : (const void*)jvp_mfma2_kernel<128>;
     GNMPC_HIP_TRY(p, set_max_lds(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.mfma2_lds));
-    // stage images of every (tile, stage) from this forward pass
-    const dim3 gimg((unsigned)((g.img_words + 255) / 256));
-    if (Hd == 64)
-      stage_image_kernel<64><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
-                                                  g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
-    else
-      stage_image_kernel<128><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
-                                                   g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
     dim3 grid2(g.t2_tiles, N);
     if (Hd == 64) jvp_mfma2_kernel<64><<<grid2, 256, g.mfma2_lds, s>>>(ma);
     else jvp_mfma2_kernel<128><<<grid2, 512, g.mfma2_lds, s>>>(ma);

@@ -19,7 +19,7 @@ OK, INVALID_ARG, BAD_GRAPH, SHAPE, UNSUPPORTED, HIP_ERROR, BAD_CONSTRAINT, NOT_R
 F64, F32, BF16 = 0, 1, 2
 QP_SOLVED, QP_MAXITER, QP_PRIMAL_INFEASIBLE, QP_NONFINITE, QP_NOT_PD = range(5)
 PHASES = ("gnn_forward", "gnn_jacobian", "gnn_assembly", "msd_linearize", "condense_propagate",
-          "condense_gram", "condense_rows", "qp")
+          "condense_gram", "condense_rows", "qp", "gnn_stage_images")
 
 
 class GnmpcError(RuntimeError):
