@@ -93,7 +93,10 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
 // slice of kPropCW columns; the S_k rows of the union of their pattern
 // columns are staged in LDS once (the rows a chain neighbourhood shares are
 // read from L2 once instead of once per node), with the nodes' A blocks.
-// Thread: one node and one column.  Slice 0 also does Gx.
+// Thread: one node and one column.  Slice 0 also does Gx.  The block's static
+// data is one fixed-stride record (first pattern entry, entry count, union
+// size, node count, row starts, union nodes, union position of every entry),
+// so a stage is two dependent reads: the record, then A_k and the S_k rows.
 constexpr int kPropCW = 64;
 constexpr int kStageBatch = 8;
 __device__ inline void ld4v(const float* p, float (&o)[4]) {
@@ -112,26 +115,25 @@ __device__ inline void ld4v(const double* p, double (&o)[4]) {
 }
 template <typename T>
 __global__ void __launch_bounds__(256)
-sprop_block_kernel(int k, int M, int nu, int nbn, const int32_t* __restrict__ prow, const int32_t* __restrict__ pcol,
-                   const int32_t* __restrict__ ubeg, const int32_t* __restrict__ ulist,
-                   const int32_t* __restrict__ epos, const T* __restrict__ A_k, const T* __restrict__ B_k,
+sprop_block_kernel(int k, int M, int nu, int nbn, int rstride, int umax, int emax, const int32_t* __restrict__ rec,
+                   const T* __restrict__ A_k, const T* __restrict__ B_k,
                    const T* __restrict__ c_k, const T* __restrict__ S_in, T* __restrict__ S_out,
                    const T* __restrict__ Gx_in, T* __restrict__ Gx_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pb[];
   const int b = blockIdx.x, c0 = blockIdx.y * kPropCW;
-  const int node0 = b * nbn, nn = min(nbn, M - node0);
+  const int node0 = b * nbn;
   const int cin = k * nu, cout = cin + nu;
-  const int ub = ubeg[b], uc = ubeg[b + 1] - ub;
-  const int e0 = prow[node0], ne = prow[node0 + nn] - e0;
   const int cw = max(0, min(kPropCW, cin - c0));  // staged columns of S_k
-  T* Ss = reinterpret_cast<T*>(smem_pb);          // [uc][6][kPropCW]
-  T* As = Ss + (size_t)uc * NBX * kPropCW;        // [ne][36]
-  T* Gs = As + (size_t)ne * 36;                   // [uc][6] (chunk 0)
-  int32_t* Es = reinterpret_cast<int32_t*>(Gs + (size_t)uc * NBX);  // [ne] union position of each entry
-  int32_t* Rs = Es + ne;                                             // [nn + 1] row starts (relative)
-  int32_t* Us = Rs + nn + 1;                                         // [uc] union nodes
-  for (int t = threadIdx.x; t < uc; t += 256) Us[t] = ulist[ub + t];
-  for (int t = threadIdx.x; t <= nn; t += 256) Rs[t] = prow[node0 + t] - e0;
+  T* Ss = reinterpret_cast<T*>(smem_pb);          // [umax][6][kPropCW]
+  T* As = Ss + (size_t)umax * NBX * kPropCW;      // [emax][36]
+  T* Gs = As + (size_t)emax * 36;                 // [umax][6] (chunk 0)
+  int32_t* Rr = reinterpret_cast<int32_t*>(Gs + (size_t)umax * NBX);  // the block's record
+  for (int t = threadIdx.x; t < rstride; t += 256) Rr[t] = rec[(size_t)b * rstride + t];
+  __syncthreads();
+  const int e0 = Rr[0], ne = Rr[1], uc = Rr[2], nn = Rr[3];
+  const int32_t* Rs = Rr + 4;                // [nn + 1] row starts (relative)
+  const int32_t* Us = Rs + nbn + 1;          // [uc] union nodes
+  const int32_t* Es = Us + umax;             // [ne] union position of each entry
   // every staging loop keeps kStageBatch loads in flight per lane
   for (int t0 = threadIdx.x; t0 < ne * 36; t0 += 256 * kStageBatch) {
     T v[kStageBatch];
@@ -144,7 +146,6 @@ sprop_block_kernel(int k, int M, int nu, int nbn, const int32_t* __restrict__ pr
     for (int u = 0; u < kStageBatch; ++u)
       if (t0 + 256 * u < ne * 36) As[t0 + 256 * u] = v[u];
   }
-  for (int t = threadIdx.x; t < ne; t += 256) Es[t] = epos[e0 + t];
   __syncthreads();
   if (cw > 0) {
     // 4 rows of kPropCW columns per pass of 256 lanes
@@ -550,7 +551,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   copy_kernel<T><<<ceil_div((long)M * NBX, 256), 256, 0, s>>>((const T*)x0, G, (long)M * NBX);
   const int wmax = p->wmax;
   const size_t pb_lds = sizeof(T) * ((size_t)p->pb_umax * NBX * (kPropCW + 1) + (size_t)p->pb_emax * 36) +
-                        sizeof(int32_t) * ((size_t)p->pb_emax + p->pb_nodes + 1 + p->pb_umax);
+                        sizeof(int32_t) * (size_t)p->pb_rec_stride;
   const bool use_blocks = p->pb_nodes > 0 && pb_lds <= 64 * 1024;
   if (use_blocks)
     GNMPC_HIP_TRY(p, set_max_lds((const void*)sprop_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -560,7 +561,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
     if (use_blocks) {
       dim3 grid(p->pb_count, ceil_div((k + 1) * nu, kPropCW));
       sprop_block_kernel<T><<<grid, 256, pb_lds, s>>>(
-          k, M, nu, p->pb_nodes, p->d_prow, p->d_pcol, p->d_pb_ubeg, p->d_pb_ulist, p->d_pb_epos,
+          k, M, nu, p->pb_nodes, p->pb_rec_stride, p->pb_umax, p->pb_emax, p->d_pb_rec,
           (const T*)A + (size_t)k * p->nnz * 36, (const T*)B + (size_t)k * M * NBX * nu,
           (const T*)c + (size_t)k * M * NBX, S_in, S + S_offset(k + 1, M, nu), G + (size_t)k * M * NBX,
           G + (size_t)(k + 1) * M * NBX);
@@ -615,12 +616,11 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
 }  // namespace
 
 void prop_blocks_free(gnmpc_plan* p) {
-  for (int32_t** q : {&p->d_pb_ubeg, &p->d_pb_ulist, &p->d_pb_epos})
-    if (*q) {
-      (void)hipFree(*q);
-      *q = nullptr;
-    }
-  p->pb_nodes = p->pb_count = p->pb_umax = p->pb_emax = 0;
+  if (p->d_pb_rec) {
+    (void)hipFree(p->d_pb_rec);
+    p->d_pb_rec = nullptr;
+  }
+  p->pb_nodes = p->pb_count = p->pb_umax = p->pb_emax = p->pb_rec_stride = 0;
 }
 
 // Node blocks for the block propagation kernel: the largest block size (4, 2,
@@ -647,22 +647,31 @@ gnmpc_status prop_blocks_build(gnmpc_plan* p) {
       umax = std::max(umax, (int)u.size());
       emax = std::max(emax, e1 - e0);
     }
-    if (elem * ((size_t)umax * NBX * (kPropCW + 1) + (size_t)emax * 36) + 4 * ((size_t)emax + nb + 1 + umax) >
-        64 * 1024)
-      continue;
-    auto up = [&](int32_t*& dst, const std::vector<int32_t>& v) -> gnmpc_status {
-      GNMPC_HIP_TRY(p, hipMalloc((void**)&dst, sizeof(int32_t) * std::max<size_t>(v.size(), 1)));
-      if (!v.empty()) GNMPC_HIP_TRY(p, hipMemcpy(dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
-      return GNMPC_OK;
-    };
-    gnmpc_status st;
-    if ((st = up(p->d_pb_ubeg, ubeg)) != GNMPC_OK) return st;
-    if ((st = up(p->d_pb_ulist, ulist)) != GNMPC_OK) return st;
-    if ((st = up(p->d_pb_epos, epos)) != GNMPC_OK) return st;
+    // record: e0, ne, uc, nn, row starts [nb + 1], union nodes [umax], entry positions [emax]
+    const int stride = (4 + (nb + 1) + umax + emax + 3) / 4 * 4;
+    if (elem * ((size_t)umax * NBX * (kPropCW + 1) + (size_t)emax * 36) + 4 * (size_t)stride > 64 * 1024) continue;
+    const int nblk = (int)ubeg.size() - 1;
+    std::vector<int32_t> rec((size_t)nblk * stride, 0);
+    for (int b = 0; b < nblk; ++b) {
+      int32_t* r = rec.data() + (size_t)b * stride;
+      const int node0 = b * nb, node1 = std::min(M, node0 + nb);
+      const int e0 = p->h_prow[node0], e1 = p->h_prow[node1];
+      r[0] = e0;
+      r[1] = e1 - e0;
+      r[2] = ubeg[b + 1] - ubeg[b];
+      r[3] = node1 - node0;
+      for (int t = 0; t <= node1 - node0; ++t) r[4 + t] = p->h_prow[node0 + t] - e0;
+      for (int t = 0; t < r[2]; ++t) r[4 + nb + 1 + t] = ulist[ubeg[b] + t];
+      for (int e = e0; e < e1; ++e) r[4 + nb + 1 + umax + (e - e0)] = epos[e];
+    }
+    GNMPC_HIP_TRY(p, hipMalloc((void**)&p->d_pb_rec, sizeof(int32_t) * std::max<size_t>(rec.size(), 1)));
+    if (!rec.empty())
+      GNMPC_HIP_TRY(p, hipMemcpy(p->d_pb_rec, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice));
     p->pb_nodes = nb;
-    p->pb_count = (int)ubeg.size() - 1;
+    p->pb_count = nblk;
     p->pb_umax = umax;
     p->pb_emax = emax;
+    p->pb_rec_stride = stride;
     return GNMPC_OK;
   }
   return GNMPC_OK;

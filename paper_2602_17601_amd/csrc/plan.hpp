@@ -22,11 +22,12 @@ struct gnmpc_plan {
   std::vector<int32_t> h_row_ptr, h_col, h_prow, h_pcol;
   int32_t *d_row_ptr = nullptr, *d_col = nullptr;
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_erow = nullptr, *d_diag = nullptr;
-  // propagation blocks: pb_nodes consecutive nodes per block, the union of
-  // their pattern columns (ulist, block b at ubeg[b]) and, per pattern entry,
-  // the position of its column in its block's union (epos)
-  int pb_nodes = 0, pb_count = 0, pb_umax = 0, pb_emax = 0;
-  int32_t *d_pb_ubeg = nullptr, *d_pb_ulist = nullptr, *d_pb_epos = nullptr;
+  // propagation blocks: pb_nodes consecutive nodes per block; one record of
+  // pb_rec_stride words per block (first pattern entry, entry count, union
+  // size, node count, row starts, the union of the nodes' pattern columns and,
+  // per pattern entry, the position of its column in that union)
+  int pb_nodes = 0, pb_count = 0, pb_umax = 0, pb_emax = 0, pb_rec_stride = 0;
+  int32_t* d_pb_rec = nullptr;
 
   // model
   int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN
