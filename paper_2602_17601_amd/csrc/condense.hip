@@ -99,6 +99,7 @@ sprop_kernel(int k, int M, int nu, int npw, const int32_t* __restrict__ prow, co
 // so a stage is two dependent reads: the record, then A_k and the S_k rows.
 constexpr int kPropCW = 64;
 constexpr int kStageBatch = 8;
+constexpr int kRowBatch = 32;  // S_k rows in flight per lane: a 4-node block's union (about 16 nodes) in one batch
 __device__ inline void ld4v(const float* p, float (&o)[4]) {
   const float4 v = *reinterpret_cast<const float4*>(p);
   o[0] = v.x;
@@ -150,17 +151,17 @@ sprop_block_kernel(int k, int M, int nu, int nbn, int rstride, int umax, int ema
   if (cw > 0) {
     // 4 rows of kPropCW columns per pass of 256 lanes
     const int c = threadIdx.x % kPropCW, rq = threadIdx.x / kPropCW;
-    for (int row0 = rq; row0 < uc * NBX; row0 += 4 * kStageBatch) {
-      T v[kStageBatch];
+    for (int row0 = rq; row0 < uc * NBX; row0 += 4 * kRowBatch) {
+      T v[kRowBatch];
 #pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
+      for (int u = 0; u < kRowBatch; ++u) {
         const int row = row0 + 4 * u;
         const bool ok = row < uc * NBX && c < cw;
         const int uu = ok ? row / NBX : 0, sr = ok ? row - uu * NBX : 0;
         v[u] = ok ? S_in[((size_t)Us[uu] * NBX + sr) * cin + c0 + c] : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < kStageBatch; ++u)
+      for (int u = 0; u < kRowBatch; ++u)
         if (row0 + 4 * u < uc * NBX) Ss[(size_t)(row0 + 4 * u) * kPropCW + c] = v[u];
     }
   }
