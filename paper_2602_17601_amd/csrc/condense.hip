@@ -269,7 +269,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   const float* Gxk = Gx_all + (size_t)k * sh.M * NBX;
   const float* qk = q + (size_t)k * sh.M * NBX;
   const bool diag = ta == tb;
-  float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT, rows 8 (threadIdx.x / kT) .. +7 of each block
+  float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT, rows (kRB / 4) (threadIdx.x / kT) .. + kRB / 4 - 1 of each block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int qa = 32 * (wave >> 1), qb = 32 * (wave & 1);
   const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
@@ -336,7 +336,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
     __syncthreads();
     if (diag) {
 #pragma unroll
-      for (int u = 0; u < kRB / 4; ++u) gacc += As[8 * rr0 + u][cc] * Ws[8 * rr0 + u];
+      for (int u = 0; u < kRB / 4; ++u) gacc += As[(kRB / 4) * rr0 + u][cc] * Ws[(kRB / 4) * rr0 + u];
     }
     if (live) {
 #pragma unroll
