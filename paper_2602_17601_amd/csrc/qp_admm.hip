@@ -358,6 +358,10 @@ __device__ T form_K(const QpArgs<Tin>& a, const Work<T>& w, T s) {
 
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
+// 1 / sqrt(x) for x > 0: the hardware reciprocal square root in FP32 (about
+// 1 ulp, like the reciprocal above); the correctly rounded quotient in FP64.
+__device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
 
 // Value of lane J of this lane's 16-lane row (DPP row_newbcast, one VALU op).
 template <int J>
@@ -373,15 +377,17 @@ __device__ inline double row_bcast(double v) {
 }
 
 // Pivot step J of the row-per-lane Cholesky (lane i < 16 holds row i in a).
+// Only the lower triangle is meaningful: entries a[k] with k > lane are updated
+// too (no per-lane masks) but never read into the lower part, and are zeroed
+// when L is written out.
 template <int J, typename T>
 __device__ inline void chol_step(T (&a)[16], int lane, bool& ok) {
   const T piv = row_bcast<J>(a[J]);
   ok = ok && piv > T(0) && isfinite(piv);
-  const T d = sqrt(piv > T(0) ? piv : T(1));
-  const T inv = recip(d);
-  a[J] = lane == J ? d : (lane > J ? a[J] * inv : a[J]);
+  const T inv = rsqrt_pos(piv > T(0) ? piv : T(1));  // 1 / sqrt(pivot)
+  a[J] = lane == J ? piv * inv : a[J] * inv;
   if constexpr (J + 1 < 16) {
-    // column J of L is now a[J] across the lanes; lane i updates a[k] for J < k <= i
+    // column J of L is now a[J] across the lanes; lane i updates a[k] for k > J
     T colv[16];
 #define GNMPC_BC(K) \
     if constexpr (K > J) colv[K] = row_bcast<K>(a[J]);
@@ -389,8 +395,7 @@ __device__ inline void chol_step(T (&a)[16], int lane, bool& ok) {
     GNMPC_BC(9) GNMPC_BC(10) GNMPC_BC(11) GNMPC_BC(12) GNMPC_BC(13) GNMPC_BC(14) GNMPC_BC(15)
 #undef GNMPC_BC
 #pragma unroll
-    for (int k = J + 1; k < 16; ++k)
-      if (lane >= k) a[k] -= a[J] * colv[k];
+    for (int k = J + 1; k < 16; ++k) a[k] -= a[J] * colv[k];
   }
 }
 
