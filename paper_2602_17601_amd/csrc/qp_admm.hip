@@ -74,7 +74,7 @@ __device__ inline T wave_max(T v) {
 
 // Shared block-wide reductions through a small LDS array.
 template <typename T>
-__device__ T block_max(T v, T* red) {
+__device__ __attribute__((always_inline)) T block_max(T v, T* red) {
   v = wave_max(v);
   int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
@@ -85,7 +85,7 @@ __device__ T block_max(T v, T* red) {
   return r;
 }
 template <typename T>
-__device__ T block_sum(T v, T* red) {
+__device__ __attribute__((always_inline)) T block_sum(T v, T* red) {
   v = wave_sum(v);
   int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
@@ -405,7 +405,7 @@ __device__ inline void chol_step(T (&a)[16], int lane, bool& ok) {
 // goes to tmp and lane c forward-substitutes column c of L^{-1}.  Writes
 // L^{-1} (lower, zeros above) to Dg; false on a nonpositive or non-finite pivot.
 template <typename T>
-__device__ bool diag_factor_invert(T* Dg, T* tmp) {
+__device__ __attribute__((always_inline)) bool diag_factor_invert(T* Dg, T* tmp) {
   const int lane = threadIdx.x & 63;
   const bool act = lane < 16;
   T a[16];
@@ -486,7 +486,7 @@ __device__ inline void bmma_rt(T acc[4], const T* A, const T* B, bool trans) {
 }
 
 template <typename T>
-__device__ bool factor_invert(const Work<T>& w, int nb) {
+__device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, int nb) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (wave == 0) {
     const bool ok = diag_factor_invert(w.mat, w.part);
@@ -663,7 +663,7 @@ __device__ bool factor_prepared(const QpArgs<Tin>& a, const Work<T>& w, T* knorm
 
 // Factor K(s) and invert; false if K is not positive definite.
 template <typename T, typename Tin>
-__device__ bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
+__device__ __attribute__((always_inline)) bool factor(const QpArgs<Tin>& a, const Work<T>& w, T s, T* knorm) {
   *knorm = form_K(a, w, s);
   __syncthreads();
   return factor_invert(w, nblocks(a.n));
