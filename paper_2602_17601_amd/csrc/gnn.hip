@@ -1114,7 +1114,7 @@ struct FwdMfmaArgs {
 // Column tiles of the forward pass hold kFwdCT * 16 node columns (Hd <= 128;
 // Hd = 256 uses one 16-column group): the weight fragments a wave loads feed
 // kFwdCT MFMA column groups.
-constexpr int kFwdCT = 4;
+constexpr int kFwdCT = 2;
 __host__ __device__ constexpr int fwd_groups(int Hd) { return Hd <= 128 ? kFwdCT : 1; }
 
 template <int MT>
@@ -1315,23 +1315,27 @@ __global__ void gnn_offset_kernel(int N, int M, int nu, long nnz, const int32_t*
   const float* xk = xhat + (size_t)k * M * NBX;
   float lin = 0.f;
   const int e0 = prow[i], e1 = prow[i + 1];
+  // row r of a block and a node's state are 6 floats at 8-byte aligned addresses: float2 loads
   for (int e = e0; e < e1; e += 4) {
-    float av[4][6], xv[4][6];
+    float2 av[4][3], xv[4][3];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int eu = e + u < e1 ? e + u : e;
-      const float* blk = A + ((size_t)k * nnz + eu) * 36 + r * 6;
-      const float* xj = xk + (size_t)pcol[eu] * NBX;
+      const float2* blk = reinterpret_cast<const float2*>(A + ((size_t)k * nnz + eu) * 36 + r * 6);
+      const float2* xj = reinterpret_cast<const float2*>(xk + (size_t)pcol[eu] * NBX);
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        av[u][d] = e + u < e1 ? blk[d] : 0.f;
+      for (int d = 0; d < 3; ++d) {
+        av[u][d] = e + u < e1 ? blk[d] : make_float2(0.f, 0.f);
         xv[u][d] = xj[d];
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int d = 0; d < 6; ++d) lin += av[u][d] * xv[u][d];
+      for (int d = 0; d < 3; ++d) {
+        lin += av[u][d].x * xv[u][d].x;
+        lin += av[u][d].y * xv[u][d].y;
+      }
   }
   const float* Bi = B + ((size_t)s * NBX + r) * nu;
   const float* u = uhat + (size_t)k * nu;
