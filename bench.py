@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the single instance: K independent instances of uneven size "
+                         "(M ~ U{50..1000}, N ~ U{10..30}) in one batched step; prints its own JSON line")
     ap.add_argument("--eager", action="store_true",
                     help="time eagerly launched steps instead of replays of the step captured as a HIP graph")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -149,6 +152,10 @@ def main():
         return
     from paper_2602_17601_amd import gnmpc as gn
     from paper_2602_17601_amd import workloads as wl
+
+    if args.batch:
+        bench_batch(args, torch, gn, wl)
+        return
 
     dev = "cuda"
     P = wl.gnn1000_bf16()
@@ -281,6 +288,80 @@ def main():
         "qp_status_gnn": qpi.status,
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(P, Pm),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, torch, gn, wl):
+    """K uneven instances (one shared BF16 GNN, Hd=128, L=2) per batched step,
+    captured once as a HIP graph and replayed; the same instances one after
+    another on one stream are timed beside it."""
+    probs = wl.batch_instances(args.batch, seed=4)
+
+    def t(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+    setups = []
+    for P in probs:
+        plan = gn.Plan(P.M, P.nu, P.N, 1, gn.F32)
+        plan.graph_set(P.row_ptr, P.col, P.gnn.L)
+        plan.model_set_gnn(P.gnn, P.act, dtype=gn.BF16)
+        n = P.N * P.nu
+        b = dict(xhat=t(P.xhat), uhat=t(P.uhat), x0=t(P.x0), Q=t(P.costs.Q), q=t(P.costs.q), R=t(P.costs.R),
+                 r=t(P.costs.r), lb=t(P.lb), ub=t(P.ub),
+                 A=torch.empty(P.N, plan.nnz, 6, 6, device="cuda"), B=torch.empty(P.N, P.M, 6, P.nu, device="cuda"),
+                 c=torch.empty(P.N, P.M, 6, device="cuda"), H=torch.empty(n, n, device="cuda"),
+                 g=torch.empty(n, device="cuda"), u=torch.empty(n, device="cuda"),
+                 info=torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device="cuda"))
+        setups.append((plan, b))
+    descs = [gn.step_desc(plan, b) for plan, b in setups]
+
+    def sequential():
+        for plan, b in setups:
+            plan.linearize(b["xhat"], b["uhat"], b["A"], b["B"], b["c"])
+            plan.condense(b["A"], b["B"], b["c"], b["x0"], b["Q"], b["q"], b["R"], b["r"], None, None, b["H"],
+                          b["g"], None, None)
+            plan.solve_box_qp(b["H"], b["g"], b["lb"], b["ub"], None, None, None, b["u"], b["info"])
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    el_b = timed(lambda: gn.step_batched(descs))
+    el_s = timed(sequential)
+    K = len(setups)
+    status = [gn.qp_info(b["info"]).status for _, b in setups]
+    out = {
+        "metric": "batched condensed MPC instance-steps/s (uneven GNN instances)",
+        "value": args.steps * K / el_b,
+        "unit": "instance-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_batch": el_b / args.steps * 1e3,
+        "higher_is_better": True,
+        "dtype": "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{K} instances: M ~ U{{50..1000}}, N ~ U{{10..30}}, 2-4 actuated nodes, "
+                               "shared GNN Hd=128 L=2 (BF16 MLPs), FP32 condensing, ADMM box QP, no state rows",
+                   "instances": K, "total_nodes": int(sum(P.M for P in probs)),
+                   "total_node_stages": int(sum(P.M * P.N for P in probs))},
+        "sequential_instance_steps_per_s": args.steps * K / el_s,
+        "qp_solved": int(sum(1 for s_ in status if s_ == gn.QP_SOLVED)),
+        "timing": "HIP graph replay (batched: one captured step_batched call; sequential: the same "
+                  "instances one after another on one stream)",
     }
     print(json.dumps(out), flush=True)
 

@@ -226,6 +226,36 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* plan, int32_t n, const void* H, cons
                                 const void* lc, const void* uc, const gnmpc_admm_settings* settings,
                                 void* u, gnmpc_qp_info* info, void* stream);
 
+/* ---------------- batched steps ---------------- */
+
+/* The device arrays of one instance's condensed MPC step: the arguments of
+ * gnmpc_linearize, gnmpc_condense and gnmpc_solve_box_qp for its plan, with
+ * the same shapes, dtypes and ownership (the caller owns them).  rowC, rowd,
+ * Ct, dt may be NULL when the plan has no state rows; lc, uc may be NULL
+ * (-inf / +inf). */
+typedef struct {
+  gnmpc_plan* plan;
+  const void *xhat, *uhat, *x0, *Q, *q, *R, *r, *rowC, *rowd, *lb, *ub, *lc, *uc;
+  int32_t Q_full;   /* 0: Q is diagonal [N+1][M][6]; 1: full blocks [N+1][M][6][6] */
+  int32_t reserved;
+  void *A, *B, *c, *H, *g, *Ct, *dt, *u;
+  gnmpc_qp_info* info; /* device, may be NULL */
+} gnmpc_step_desc;
+
+/* Batched step: linearize, condense and solve the box QP (Algorithm 1's
+ * linearization, condensing and "Solve QP" of one MPC iteration) for `count`
+ * independent instances of uneven sizes, each with its own plan on the same
+ * device.  The instances run concurrently: the work is forked from `stream`
+ * onto up to 4 library-owned streams (instance i on stream i mod 4) and joined
+ * back with events, so `stream` is ordered after every instance, and a HIP
+ * graph capture of `stream` records the whole batch (the library streams are
+ * created on the first call, which must not be captured).  Settings apply to
+ * every QP.  Each instance's arrays are validated as by the single calls; on
+ * an error the work already forked is still joined and the first failing
+ * status is returned (that plan's last_error names the cause). */
+gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count,
+                                const gnmpc_admm_settings* settings, void* stream);
+
 /* ---------------- per-phase GPU timers ---------------- */
 
 /* Phases timed by gnmpc_timers_*: hipEvents are recorded on the caller's stream

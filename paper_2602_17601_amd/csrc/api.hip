@@ -2,6 +2,7 @@
 // the host, plan workspace and launch sequencing.  Every check runs before any
 // HIP call, so invalid requests never touch the GPU.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -405,6 +406,66 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const v
     return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: bad settings");
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
+}
+
+// Library streams of the batched step, per device, created once (default priority).
+constexpr int kBatchStreams = 4;
+struct BatchStreams {
+  bool ready = false;
+  hipStream_t s[kBatchStreams];
+  hipEvent_t fork, join[kBatchStreams];
+};
+
+gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, const gnmpc_admm_settings* st,
+                                void* stream) {
+  static std::mutex mu;
+  static BatchStreams pool[64];
+  if (!descs || count < 0 || !st) return GNMPC_INVALID_ARG;
+  if (count == 0) return GNMPC_OK;
+  for (int32_t i = 0; i < count; ++i)
+    if (!descs[i].plan) return GNMPC_INVALID_ARG;
+  const int dev = descs[0].plan->device;
+  for (int32_t i = 1; i < count; ++i)
+    if (descs[i].plan->device != dev) return fail(descs[i].plan, GNMPC_INVALID_ARG, "step_batched: plans on different devices");
+  if (dev < 0 || dev >= 64) return GNMPC_INVALID_ARG;
+  gnmpc_plan* p0 = descs[0].plan;
+  GNMPC_HIP_TRY(p0, hipSetDevice(dev));
+  BatchStreams& bs = pool[dev];
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!bs.ready) {
+      for (int t = 0; t < kBatchStreams; ++t) {
+        GNMPC_HIP_TRY(p0, hipStreamCreateWithFlags(&bs.s[t], hipStreamNonBlocking));
+        GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.join[t], hipEventDisableTiming));
+      }
+      GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.fork, hipEventDisableTiming));
+      bs.ready = true;
+    }
+  }
+  const hipStream_t caller = (hipStream_t)stream;
+  const int used = std::min<int32_t>(count, kBatchStreams);
+  GNMPC_HIP_TRY(p0, hipEventRecord(bs.fork, caller));
+  for (int t = 0; t < used; ++t) GNMPC_HIP_TRY(p0, hipStreamWaitEvent(bs.s[t], bs.fork, 0));
+  gnmpc_status first = GNMPC_OK;
+  for (int32_t i = 0; i < count && first == GNMPC_OK; ++i) {
+    const gnmpc_step_desc& d = descs[i];
+    gnmpc_plan* p = d.plan;
+    void* si = (void*)bs.s[i % kBatchStreams];
+    const int32_t n = p->dims.N * p->dims.nu;
+    gnmpc_status s = gnmpc_linearize(p, d.xhat, d.uhat, d.A, d.B, d.c, nullptr, si);
+    if (s == GNMPC_OK)
+      s = gnmpc_condense(p, d.A, d.B, d.c, d.x0, d.Q, d.Q_full, d.q, d.R, d.r, d.rowC, d.rowd, d.H, d.g, d.Ct,
+                         d.dt, nullptr, si);
+    if (s == GNMPC_OK)
+      s = gnmpc_solve_box_qp(p, n, d.H, d.g, d.lb, d.ub, p->n_c, d.Ct, d.lc, d.uc, st, d.u, d.info, si);
+    first = s;
+  }
+  // join every forked stream, also after an error
+  for (int t = 0; t < used; ++t) {
+    GNMPC_HIP_TRY(p0, hipEventRecord(bs.join[t], bs.s[t]));
+    GNMPC_HIP_TRY(p0, hipStreamWaitEvent(caller, bs.join[t], 0));
+  }
+  return first;
 }
 
 }  // extern "C"

@@ -56,6 +56,13 @@ class QpInfo(C.Structure):
 
 QP_INFO_BYTES = C.sizeof(QpInfo)
 
+
+class StepDesc(C.Structure):
+    _fields_ = [("plan", C.c_void_p)] + [(f, C.c_void_p) for f in (
+        "xhat", "uhat", "x0", "Q", "q", "R", "r", "rowC", "rowd", "lb", "ub", "lc", "uc")] + [
+        ("Q_full", C.c_int32), ("reserved", C.c_int32)] + [(f, C.c_void_p) for f in (
+        "A", "B", "c", "H", "g", "Ct", "dt", "u")] + [("info", C.c_void_p)]
+
 _lib = None
 
 
@@ -87,6 +94,7 @@ def lib():
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
             "gnmpc_timers_enable": ([vp, i32], i32),
+            "gnmpc_step_batched": ([vp, i32, P(AdmmSettings), vp], i32),
             "gnmpc_timers_read": ([vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
@@ -281,6 +289,45 @@ def _timers_read(self):
 
 Plan.timers_enable = _timers_enable
 Plan.timers_read = _timers_read
+
+
+def step_desc(plan, b):
+    """The descriptor of one instance's step: `b` maps xhat, uhat, x0, Q, q, R,
+    r, rowC, rowd, lb, ub, (lc, uc), A, B, c, H, g, Ct, dt, u, (info) to tensors
+    of the plan's shapes (the same checks as the single calls)."""
+    M, N, nu, nc, n = plan.M, plan.N, plan.nu, plan.n_c, plan.N * plan.nu
+    full = 1 if b["Q"].dim() == 4 else 0
+    d = StepDesc()
+    d.plan = plan._h
+    dv = plan._dev
+    d.xhat, d.uhat = dv(b["xhat"], (N + 1, M, 6), "xhat"), dv(b["uhat"], (N, nu), "uhat")
+    d.x0 = dv(b["x0"], (M, 6), "x0")
+    d.Q = dv(b["Q"], (N + 1, M, 6, 6) if full else (N + 1, M, 6), "Q")
+    d.q, d.R, d.r = dv(b["q"], (N + 1, M, 6), "q"), dv(b["R"], (N, nu, nu), "R"), dv(b["r"], (N, nu), "r")
+    d.rowC = dv(b.get("rowC"), (nc, 6), "rowC", allow_none=nc == 0)
+    d.rowd = dv(b.get("rowd"), (nc,), "rowd", allow_none=nc == 0)
+    d.lb, d.ub = dv(b["lb"], (n,), "lb"), dv(b["ub"], (n,), "ub")
+    d.lc = dv(b.get("lc"), (nc,), "lc", allow_none=True)
+    d.uc = dv(b.get("uc"), (nc,), "uc", allow_none=True)
+    d.Q_full = full
+    d.A, d.B = dv(b["A"], (N, plan.nnz, 6, 6), "A"), dv(b["B"], (N, M, 6, nu), "B")
+    d.c, d.H, d.g = dv(b["c"], (N, M, 6), "c"), dv(b["H"], (n, n), "H"), dv(b["g"], (n,), "g")
+    d.Ct = dv(b.get("Ct"), (nc, n), "Ct", allow_none=nc == 0)
+    d.dt = dv(b.get("dt"), (nc,), "dt", allow_none=nc == 0)
+    d.u = dv(b["u"], (n,), "u")
+    d.info = dv(b.get("info"), (QP_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)
+    return d
+
+
+def step_batched(descs, settings=None, stream=None):
+    """gnmpc_step_batched over a list of StepDesc (see step_desc): every
+    instance's linearize, condense and QP, run concurrently and joined back
+    onto `stream`."""
+    arr = (StepDesc * len(descs))(*descs)
+    st = settings or default_admm_settings()
+    s = lib().gnmpc_step_batched(arr, len(descs), C.byref(st), _stream(stream))
+    if s != OK:
+        raise GnmpcError(s, "step_batched: " + status_string(s))
 
 
 def qp_info(t):

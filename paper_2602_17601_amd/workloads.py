@@ -340,3 +340,20 @@ def gnn1000_bf16(model: str = "gnn") -> Problem:
                         M=1000, hops=2, N=20, n_act=4, model=model, seed=3, Hd=128, L=3,
                         x0_sigma=0.02, walk=0.002, obstacle=True,
                         gnn_dtype="bf16" if model == "gnn" else "f32")
+
+
+def batch_instances(count: int, seed: int = 4, M_range=(50, 1000), N_range=(10, 30)) -> list[Problem]:
+    """A batch of independent instances of uneven size (the serving shape):
+    instance i draws M ~ U{M_range}, N ~ U{N_range} and 2, 3 or 4 actuated nodes
+    from ``default_rng(seed)``; all share one GNN (Hd=128, L=2, BF16 MLPs, FP32
+    condensing, weights from ``seed``), tracking costs, |u| <= 1 and no state rows."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        M = int(rng.integers(M_range[0], M_range[1] + 1))
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        n_act = int(rng.integers(2, 5))
+        out.append(make_problem(f"batch{seed}_{i}", M=M, hops=2, N=N, n_act=n_act, model="gnn",
+                                seed=seed * 100003 + i, weight_seed=seed, Hd=128, L=2, x0_sigma=0.02,
+                                walk=0.002, gnn_dtype="bf16"))
+    return out
