@@ -672,17 +672,19 @@ __device__ __attribute__((always_inline)) bool factor(const QpArgs<Tin>& a, cons
 
 // ---------------------------------------------------------------------------
 // Row passes over a row-major global matrix (Ct or H) for FP32 instances with
-// n, rows <= 256: every wave takes 4 rows at a time (16 lanes per row, lane
-// columns c = (lane & 15) + 16 j), and all of a lane's values are loaded into
+// n, rows <= 256 and n a multiple of 4: every wave takes 4 rows at a time (16
+// lanes per row; lane columns c = 4 (lane & 15) + 64 j + e, four consecutive
+// columns per 16-byte load), and all of a lane's values are loaded into
 // registers at once, so a pass pays one memory latency instead of one per row.
 constexpr int kMG = 4;   // row groups per wave held at once
 constexpr int kMH = 2;   // passes: kMG * kMH groups cover 4 * kWaves * kMG * kMH rows
-constexpr int kMJ = 16;  // 16-column slices per lane
+constexpr int kMJ = 16;  // columns per lane
+constexpr int kMQ = kMJ / 4;  // 4-column chunks per lane
 
 __device__ inline int rp_row(int g, int h) {
   return 4 * ((threadIdx.x >> 6) + kWaves * (g + kMG * h)) + ((threadIdx.x & 63) >> 4);
 }
-__device__ inline int rp_col(int j) { return (threadIdx.x & 15) + 16 * j; }
+__device__ inline int rp_col4(int j) { return 4 * (threadIdx.x & 15) + 64 * j; }
 
 template <typename Tin>
 __device__ inline void rp_load(float (&R)[kMG][kMJ], const Tin* Mat, int nr, int n, int h) {
@@ -690,9 +692,19 @@ __device__ inline void rp_load(float (&R)[kMG][kMJ], const Tin* Mat, int nr, int
   for (int g = 0; g < kMG; ++g) {
     const int r = rp_row(g, h);
 #pragma unroll
-    for (int j = 0; j < kMJ; ++j) {
-      const int c = rp_col(j);
-      R[g][j] = (r < nr && c < n) ? (float)Mat[(size_t)r * n + c] : 0.f;
+    for (int j = 0; j < kMQ; ++j) {
+      const int c = rp_col4(j);
+      const bool ok = r < nr && c < n;
+      if constexpr (sizeof(Tin) == 4) {
+        const float4 v = ok ? *reinterpret_cast<const float4*>(Mat + (size_t)r * n + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        R[g][4 * j] = v.x;
+        R[g][4 * j + 1] = v.y;
+        R[g][4 * j + 2] = v.z;
+        R[g][4 * j + 3] = v.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) R[g][4 * j + e] = ok ? (float)Mat[(size_t)r * n + c + e] : 0.f;
+      }
     }
   }
 }
@@ -707,9 +719,10 @@ __device__ inline float seg16_sum(float v) {
 __device__ inline float rp_dot(const float (&R)[kMG][kMJ], int g, const float* vec, int n) {
   float sum = 0.f;
 #pragma unroll
-  for (int j = 0; j < kMJ; ++j) {
-    const int c = rp_col(j);
-    sum += R[g][j] * vec[c < n ? c : 0];
+  for (int j = 0; j < kMQ; ++j) {
+    const int c = rp_col4(j);
+    const float4 v = c < n ? *reinterpret_cast<const float4*>(vec + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    sum += R[g][4 * j] * v.x + R[g][4 * j + 1] * v.y + R[g][4 * j + 2] * v.z + R[g][4 * j + 3] * v.w;
   }
   return seg16_sum(sum);
 }
@@ -725,8 +738,16 @@ __device__ inline void rp_flush(float (&acc)[kMJ], float* part, int n) {
     float v = acc[j];
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
-    const int c = rp_col(j);
-    if (lane < 16 && c < n) part[(size_t)wave * n + c] = v;
+    acc[j] = v;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < kMQ; ++j) {
+      const int c = rp_col4(j);
+      if (c < n)
+        *reinterpret_cast<float4*>(part + (size_t)wave * n + c) =
+            make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
+    }
   }
 }
 
@@ -821,7 +842,8 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   if (mode == 0 && threadIdx.x == 0) *a.flag = 0;
 
   const T sigma = (T)a.sigma, alpha = (T)a.alpha;
-  const bool use_regs = n <= 16 * kMJ && nc <= 4 * kWaves * kMG * kMH;
+  const bool use_regs = n <= 16 * kMJ && n % 4 == 0 && nc <= 4 * kWaves * kMG * kMH &&
+                        ((reinterpret_cast<uintptr_t>(a.H) | reinterpret_cast<uintptr_t>(a.Ct)) & 15) == 0;
   int status = GNMPC_QP_MAXITER;
   int iter = 0;
   T prim = T(0), dual = T(0);
