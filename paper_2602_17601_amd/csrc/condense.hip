@@ -15,6 +15,7 @@
 // Constraint rows (stacked-constraint formula of Sec. V-B):
 // Ct[t] = C_t S^{i_t}_{k_t}, dt[t] = d_t - C_t Gx^{i_t}_{k_t}.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "plan.hpp"
@@ -234,6 +235,30 @@ __device__ inline void tile_coords(int t, int& ta, int& tb) {
   tb = t - a * (a + 1) / 2;
 }
 
+// Live (tile, stage) pairs: S_k has k nu columns, so the tiles of stage k that
+// hold any of them are t < lt(k) = c (c + 1) / 2 with c = ceil(k nu / kT), a
+// prefix of the lower triangle.  The Gram grid enumerates only these pairs,
+// stage-major, so every launched workgroup has work.
+__host__ __device__ inline int live_tiles(int k, int nu, int nt) {
+  const int c0 = (k * nu + kT - 1) / kT, c = c0 < nt ? c0 : nt;
+  return c * (c + 1) / 2;
+}
+__host__ inline int live_pairs(const GramShape& sh) {
+  int tot = 0;
+  for (int k = 1; k <= sh.N; ++k) tot += live_tiles(k, sh.nu, sh.nt);
+  return tot;
+}
+// stage k and tile index of live pair idx (idx < live_pairs)
+__device__ inline int live_pair(const GramShape& sh, int idx, int& tile) {
+  int k = 1;
+  for (int lt = live_tiles(k, sh.nu, sh.nt); idx >= lt && k < sh.N; lt = live_tiles(k, sh.nu, sh.nt)) {
+    idx -= lt;
+    ++k;
+  }
+  tile = idx;
+  return k;
+}
+
 template <typename T>
 __device__ inline T qs_value(const T* Sk, const T* Qk, int Q_full, int cols, int row, int cb) {
   const int node = row / NBX, r = row - node * NBX;
@@ -246,9 +271,9 @@ __device__ inline T qs_value(const T* Sk, const T* Qk, int Q_full, int cols, int
   return v;
 }
 
-// FP32: matrix cores.  grid: x = H tile, y = stage k-1, z = row chunk.  Rows
+// FP32: matrix cores.  grid: x = live (tile, stage) pair, y = row chunk.  Rows
 // are staged 32 at a time (the a strip and the Q-weighted b strip, 64 columns
-// each) with independent loads; each wave owns a 32x32 quarter of the tile
+// each) with independent loads issued two blocks ahead; each wave owns a 32x32 quarter of the tile
 // (2 x 2 MFMA tiles) and runs 8 k-steps per staged block.
 constexpr int kRB = 32;
 __global__ void __launch_bounds__(256)
@@ -259,9 +284,10 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   __shared__ float Bs[kRB][kT + 4];
   __shared__ float Ws[kRB];        // w = Q_k Gx_k + q_k of the staged rows (diagonal tiles)
   __shared__ float Gp[4][kT];      // gradient partials of the 4 row quarters
-  const int k = blockIdx.y + 1, chunk = blockIdx.z;
+  int tile;
+  const int k = live_pair(sh, blockIdx.x, tile), chunk = blockIdx.y;
   int ta, tb;
-  tile_coords(blockIdx.x, ta, tb);
+  tile_coords(tile, ta, tb);
   if (k < first_stage(ta, sh.nu)) return;
   const int cols = k * sh.nu, rows = NBX * sh.M;
   const float* Sk = S_all + S_offset(k, sh.M, sh.nu);
@@ -281,37 +307,39 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   // this wave's quarter may lie entirely past the live columns
   const bool live = kT * ta + qa < cols && kT * tb + qb < cols;
   // staging: thread t owns column cc = t % kT of rows t / kT + 4 u (u < kRB / 4); with a
-  // diagonal Q the next row block is loaded into registers while this one is multiplied
+  // diagonal Q the row block two ahead is loaded into registers while one is multiplied
   constexpr int kPer = kRB * kT / 256;
   const int cc = threadIdx.x % kT, rr0 = threadIdx.x / kT;
   const int ca = kT * ta + cc, cb = kT * tb + cc;
-  float pa[kPer], pb[kPer], pq[kPer], pw = 0.f;
+  // two register sets: the block two ahead is in flight while one is multiplied
+  float pa[2][kPer], pb[2][kPer], pq[2][kPer], pw[2] = {0.f, 0.f};
   // lanes with threadIdx.x < kRB also fetch w for row rb + threadIdx.x (diagonal tiles)
-  auto fetch = [&](int rb) {
+  auto fetch = [&](int rb, auto slot) {
+    constexpr int sl = decltype(slot)::value;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int r = rb + rr0 + 4 * u;
       const bool vr = r < r1;
-      pa[u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
-      pb[u] = (vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
-      pq[u] = vr ? Qk[r] : 0.f;
+      pa[sl][u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
+      pb[sl][u] = (vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
+      pq[sl][u] = vr ? Qk[r] : 0.f;
     }
     if (diag && threadIdx.x < kRB) {
       const int r = rb + threadIdx.x;
-      pw = r < r1 ? Qk[r] * Gxk[r] + qk[r] : 0.f;
+      pw[sl] = r < r1 ? Qk[r] * Gxk[r] + qk[r] : 0.f;
     }
   };
-  if (!Q_full) fetch(r0);
-  for (int rb = r0; rb < r1; rb += kRB) {
+  auto block = [&](int rb, auto slot) {
+    constexpr int sl = decltype(slot)::value;
     __syncthreads();
     if (!Q_full) {
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        As[rr0 + 4 * u][cc] = pa[u];
-        Bs[rr0 + 4 * u][cc] = pq[u] * pb[u];
+        As[rr0 + 4 * u][cc] = pa[sl][u];
+        Bs[rr0 + 4 * u][cc] = pq[sl][u] * pb[sl][u];
       }
-      if (diag && threadIdx.x < kRB) Ws[threadIdx.x] = pw;
-      if (rb + kRB < r1) fetch(rb + kRB);
+      if (diag && threadIdx.x < kRB) Ws[threadIdx.x] = pw[sl];
+      if (rb + 2 * kRB < r1) fetch(rb + 2 * kRB, slot);
     } else {
       for (int t = threadIdx.x; t < kRB * kT; t += 256) {
         const int rr = t / kT, c2 = t % kT, r = rb + rr;
@@ -352,6 +380,16 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
           for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
       }
     }
+  };
+  const std::integral_constant<int, 0> s0;
+  const std::integral_constant<int, 1> s1;
+  if (!Q_full) {
+    fetch(r0, s0);
+    if (r0 + kRB < r1) fetch(r0 + kRB, s1);
+  }
+  for (int rb = r0; rb < r1; rb += 2 * kRB) {
+    block(rb, s0);
+    if (rb + kRB < r1) block(rb + kRB, s1);
   }
   if (diag) {
     Gp[rr0][cc] = gacc;
@@ -361,7 +399,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
           ((Gp[0][threadIdx.x] + Gp[1][threadIdx.x]) + Gp[2][threadIdx.x]) + Gp[3][threadIdx.x];
   }
   // C layout: lane holds rows 4 (lane >> 4) + i of each 16x16 tile, column lane & 15
-  float* out = part + (((size_t)blockIdx.x * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
+  float* out = part + (((size_t)tile * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -375,15 +413,16 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
 __global__ void __launch_bounds__(256)
 gram_kernel_f64(GramShape sh, const double* __restrict__ S_all, const double* __restrict__ Q, int Q_full,
                 double* __restrict__ part) {
-  const int k = blockIdx.y + 1, chunk = blockIdx.z;
+  int tile;
+  const int k = live_pair(sh, blockIdx.x, tile), chunk = blockIdx.y;
   int ta, tb;
-  tile_coords(blockIdx.x, ta, tb);
+  tile_coords(tile, ta, tb);
   if (k < first_stage(ta, sh.nu)) return;
   const int cols = k * sh.nu, rows = NBX * sh.M;
   const double* Sk = S_all + S_offset(k, sh.M, sh.nu);
   const double* Qk = Q + (size_t)k * sh.M * NBX * (Q_full ? NBX : 1);
   const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
-  double* out = part + (((size_t)blockIdx.x * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
+  double* out = part + (((size_t)tile * sh.N + (k - 1)) * sh.nchunks + chunk) * (kT * kT);
   for (int e = threadIdx.x; e < kT * kT; e += 256) {
     const int ca = kT * ta + e / kT, cb = kT * tb + e % kT;
     double acc = 0.0;
@@ -583,7 +622,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   phase_begin(p, GNMPC_PH_CONDENSE_GRAM, s);
   T* part = (T*)p->d_part;
   T* gpart = part + (size_t)sh.ntiles * N * sh.nchunks * kT * kT;
-  dim3 grid(sh.ntiles, N, sh.nchunks);
+  dim3 grid(live_pairs(sh), sh.nchunks);
   T* gstage = gpart + (size_t)N * sh.ngchunks * sh.n;
   const T* gtile = nullptr;
   if (sizeof(T) == 4) {

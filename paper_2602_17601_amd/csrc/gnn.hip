@@ -875,13 +875,19 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         for (int kb = 0; kb < KB; ++kb) aa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb], wa[kb], aa, 0, 0, 0);
         const uint32_t tbl[16] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w,
                                   t2.x, t2.y, t2.z, t2.w, t3.x, t3.y, t3.z, t3.w};
+        // receivers tested four at a time: a sender's receivers sit in few groups
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q) {
-          if ((rcv >> q) & 1u) {
-            // 1.0f where the edge's ReLU is on for this lane's feature, else 0
-            const float mf = __uint_as_float((uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], mpos, 1) & 0x3F800000u);
+        for (int q4 = 0; q4 < MAXV; q4 += 4) {
+          if ((rcv >> q4) & 15u) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[q][i] = __builtin_fmaf(-mf, ay[i], acc[q][i]);
+            for (int q = q4; q < q4 + 4; ++q) {
+              if (__builtin_expect((rcv >> q) & 1u, 1)) {
+                // 1.0f where the edge's ReLU is on for this lane's feature, else 0
+                const float mf = __uint_as_float((uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], mpos, 1) & 0x3F800000u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[q][i] = __builtin_fmaf(-mf, ay[i], acc[q][i]);
+              }
+            }
           }
         }
 #pragma unroll
