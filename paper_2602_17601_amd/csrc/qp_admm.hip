@@ -36,6 +36,7 @@ struct QpArgs {
   const double* G;   // [n][n]: diag(rho_rel box) + Ct' diag(rho_rel rows) Ct
   double* gmat;      // global fallback storage for the packed factor (doubles)
   double* Kp;        // K = H + sigma I + rho G in the block storage, written by qp_prep_kernel
+  float* Kf;         // the same K rounded to FP32, for the FP32 pass
   int32_t* flag;     // [0]: FP64 pass required; [1]: non-finite H or Ct seen by qp_prep_kernel
   double rho, sigma, alpha, eps_abs, eps_rel, kappa_fp64;
   int max_iter, check_every;
@@ -240,6 +241,7 @@ __global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) 
     if (!isfinite(kv)) __hip_atomic_fetch_or(a.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   a.Kp[(size_t)b * 256 + e] = kv;
+  a.Kf[(size_t)b * 256 + e] = (float)kv;
 }
 
 // Four consecutive elements of a 16-byte aligned array.
@@ -645,15 +647,22 @@ __device__ T knorm1(const Work<T>& w, int n) {
 }
 
 // Factor the K prepared by qp_prep_kernel and invert; false if not positive definite.
+// The copy keeps 16 loads of 16 bytes in flight per thread (one CU reads K from L2/MALL).
 template <typename T, typename Tin>
 __device__ bool factor_prepared(const QpArgs<Tin>& a, const Work<T>& w, T* knorm) {
-  const long total2 = (long)bo(nblocks(a.n), 0) / 2;
-  const double2* src = reinterpret_cast<const double2*>(a.Kp);
-#pragma unroll 8
-  for (long t = threadIdx.x; t < total2; t += kQpThreads) {
-    const double2 v = src[t];
-    w.mat[2 * t] = (T)v.x;
-    w.mat[2 * t + 1] = (T)v.y;
+  const long total = (long)bo(nblocks(a.n), 0);
+  if constexpr (sizeof(T) == 4) {
+    const float4* src = reinterpret_cast<const float4*>(a.Kf);
+#pragma unroll 16
+    for (long t = threadIdx.x; t < total / 4; t += kQpThreads) reinterpret_cast<float4*>(w.mat)[t] = src[t];
+  } else {
+    const double2* src = reinterpret_cast<const double2*>(a.Kp);
+#pragma unroll 16
+    for (long t = threadIdx.x; t < total / 2; t += kQpThreads) {
+      const double2 v = src[t];
+      w.mat[2 * t] = (T)v.x;
+      w.mat[2 * t + 1] = (T)v.y;
+    }
   }
   __syncthreads();
   *knorm = knorm1(w, a.n);
@@ -1214,6 +1223,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.G = (const double*)ws;
   a.gmat = (double*)(ws + (sizeof(double) * (size_t)n * n + 255) / 256 * 256);  // 256-byte aligned
   a.Kp = a.gmat + nbo;
+  a.Kf = reinterpret_cast<float*>(a.Kp + nbo);
   a.flag = p->d_qp_flag;
   a.rho = st->rho;
   a.sigma = st->sigma;
@@ -1242,7 +1252,8 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
 
 size_t qp_workspace_bytes(int n, int n_c) {
   (void)n_c;
-  return (sizeof(double) * (size_t)n * n + 255) / 256 * 256 + sizeof(double) * (2 * bo(nblocks(n), 0) + 64);
+  return (sizeof(double) * (size_t)n * n + 255) / 256 * 256 + sizeof(double) * (2 * bo(nblocks(n), 0) + 64) +
+         sizeof(float) * bo(nblocks(n), 0);
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
