@@ -192,7 +192,7 @@ __device__ inline void bmma(double acc[4], const double* A, const double* B) {
 // (FP64, rows summed in order, full symmetric, kept for refactorizations) and
 // the first K = H + sigma I + rho G in the block storage; non-finite H or Ct
 // raise flag[1].  Column slices of Ct are staged through LDS 64 rows at a time.
-constexpr int kPrepRows = 64;
+constexpr int kPrepRows = 224;  // rows staged per pass (every load of a pass in flight at once)
 template <typename Tin>
 __global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) {
   __shared__ double ci[kPrepRows][16], cj[kPrepRows][16], rr[kPrepRows];
@@ -203,15 +203,24 @@ __global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) 
   while (I * (I + 1) / 2 > b) --I;
   const int J = b - I * (I + 1) / 2;
   const int i = kBS * I + (e >> 4), j = kBS * J + (e & 15);
+  const bool in = j <= i && i < n && j < n;
+  const double h = in ? (double)a.H[(size_t)i * n + j] : 0.0;  // issued before the row loop
   double sg = 0.0;
+  constexpr int kPer = kPrepRows * 32 / 256;
   for (int r0 = 0; r0 < a.n_c; r0 += kPrepRows) {
     __syncthreads();
-    for (int t = e; t < kPrepRows * 32; t += 256) {
-      const int rl = t >> 5, c = t & 31, r = r0 + rl;
+    Tin v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = e + 256 * u, rl = t >> 5, c = t & 31, r = r0 + rl;
       const int col = c < 16 ? kBS * I + c : kBS * J + (c - 16);
-      const double v = (r < a.n_c && col < n) ? (double)a.Ct[(size_t)r * n + col] : 0.0;
-      if (c < 16) ci[rl][c] = v;
-      else cj[rl][c - 16] = v;
+      v[u] = (r < a.n_c && col < n) ? a.Ct[(size_t)r * n + col] : Tin(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = e + 256 * u, rl = t >> 5, c = t & 31;
+      if (c < 16) ci[rl][c] = (double)v[u];
+      else cj[rl][c - 16] = (double)v[u];
     }
     for (int t = e; t < kPrepRows; t += 256) {
       const int r = r0 + t;
@@ -236,7 +245,6 @@ __global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) 
     if (i == j) sg += rho_rel((double)a.lb[i], (double)a.ub[i]);
     G[(size_t)i * n + j] = sg;
     G[(size_t)j * n + i] = sg;
-    const double h = (double)a.H[(size_t)i * n + j];
     kv = h + a.rho * sg + (i == j ? a.sigma : 0.0);
     if (!isfinite(kv)) __hip_atomic_fetch_or(a.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
