@@ -211,6 +211,190 @@ sprop_block_kernel(int k, int M, int nu, int nbn, int rstride, int umax, int ema
     }
 }
 
+// Two stages per launch: a block recomputes S_{k+1} (and Gx_{k+1}) on U1, the union of
+// its pattern columns, from S_k on U2, in the same order of operations as the one-stage
+// kernel (so the values are the same bit for bit), writes the rows of its own nodes, then
+// forms S_{k+2} (and Gx_{k+2}) of its nodes from the staged U1 rows.  This halves the
+// chain of dependent launches of the recursion.
+struct Prop2Layout {
+  int rs, es1, u1, r1, g1, es2, u2, stride;
+};
+__host__ __device__ inline Prop2Layout prop2_layout(int nb, int emax, int u1max, int e1max, int u2max) {
+  Prop2Layout L;
+  L.rs = 8;                  // block row starts [nb + 1]
+  L.es1 = L.rs + nb + 1;     // block entry -> position of its column in U1 [emax]
+  L.u1 = L.es1 + emax;       // U1 nodes [u1max]
+  L.r1 = L.u1 + u1max;       // row starts of U1's nodes in the U1 entry list [u1max + 1]
+  L.g1 = L.r1 + u1max + 1;   // global pattern entry of each U1 entry [e1max]
+  L.es2 = L.g1 + e1max;      // U1 entry -> position of its column in U2 [e1max]
+  L.u2 = L.es2 + e1max;      // U2 nodes [u2max]
+  L.stride = (L.u2 + u2max + 3) / 4 * 4;
+  return L;
+}
+inline size_t prop2_lds_bytes(const Prop2Layout& L, size_t elem, int emax, int u1max, int e1max, int u2max) {
+  return elem * ((size_t)(u1max + u2max) * NBX * kPropCW + (size_t)(e1max + emax) * 36 +
+                 (size_t)(u1max + u2max) * NBX) +
+         sizeof(int32_t) * (size_t)L.stride;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+sprop2_block_kernel(int k, int M, int nu, int nbn, int emax, int u1max, int e1max, int u2max,
+                    const int32_t* __restrict__ rec, const T* __restrict__ A_k, const T* __restrict__ A_k1,
+                    const T* __restrict__ B_k, const T* __restrict__ B_k1, const T* __restrict__ c_k,
+                    const T* __restrict__ c_k1, const T* __restrict__ S_in, T* __restrict__ S_mid,
+                    T* __restrict__ S_out, const T* __restrict__ Gx_in, T* __restrict__ Gx_mid,
+                    T* __restrict__ Gx_out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pb2[];
+  const Prop2Layout L = prop2_layout(nbn, emax, u1max, e1max, u2max);
+  const int b = blockIdx.x, c0 = blockIdx.y * kPropCW;
+  const int node0 = b * nbn;
+  const int cin = k * nu, cmid = cin + nu, cout = cmid + nu;
+  T* S2s = reinterpret_cast<T*>(smem_pb2);          // [u2max][6][kPropCW]: S_k of U2
+  T* S1s = S2s + (size_t)u2max * NBX * kPropCW;     // [u1max][6][kPropCW]: S_{k+1} of U1
+  T* A1s = S1s + (size_t)u1max * NBX * kPropCW;     // [e1max][36]: A_k of U1's entries
+  T* A2s = A1s + (size_t)e1max * 36;                // [emax][36]: A_{k+1} of the block's entries
+  T* G2s = A2s + (size_t)emax * 36;                 // [u2max][6]: Gx_k of U2
+  T* G1s = G2s + (size_t)u2max * NBX;               // [u1max][6]: Gx_{k+1} of U1
+  int32_t* Rr = reinterpret_cast<int32_t*>(G1s + (size_t)u1max * NBX);
+  for (int t = threadIdx.x; t < L.stride; t += 256) Rr[t] = rec[(size_t)b * L.stride + t];
+  __syncthreads();
+  const int e0 = Rr[0], ne = Rr[1], nn = Rr[2], u1c = Rr[3], u2c = Rr[4], n1e = Rr[5];
+  const int32_t* Rs = Rr + L.rs;
+  const int32_t* Es1 = Rr + L.es1;
+  const int32_t* U1 = Rr + L.u1;
+  const int32_t* R1 = Rr + L.r1;
+  const int32_t* G1 = Rr + L.g1;
+  const int32_t* Es2 = Rr + L.es2;
+  const int32_t* U2 = Rr + L.u2;
+  for (int t0 = threadIdx.x; t0 < n1e * 36; t0 += 256 * kStageBatch) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + 256 * u;
+      v[u] = t < n1e * 36 ? A_k[(size_t)G1[t / 36] * 36 + t % 36] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (t0 + 256 * u < n1e * 36) A1s[t0 + 256 * u] = v[u];
+  }
+  for (int t0 = threadIdx.x; t0 < ne * 36; t0 += 256 * kStageBatch) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + 256 * u;
+      v[u] = t < ne * 36 ? A_k1[(size_t)e0 * 36 + t] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (t0 + 256 * u < ne * 36) A2s[t0 + 256 * u] = v[u];
+  }
+  const int cw = max(0, min(kPropCW, cin - c0));  // staged columns of S_k
+  if (cw > 0) {
+    const int c = threadIdx.x % kPropCW, rq = threadIdx.x / kPropCW;
+    for (int row0 = rq; row0 < u2c * NBX; row0 += 4 * kRowBatch) {
+      T v[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int row = row0 + 4 * u;
+        const bool ok = row < u2c * NBX && c < cw;
+        const int uu = ok ? row / NBX : 0, sr = ok ? row - uu * NBX : 0;
+        v[u] = ok ? S_in[((size_t)U2[uu] * NBX + sr) * cin + c0 + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (row0 + 4 * u < u2c * NBX) S2s[(size_t)(row0 + 4 * u) * kPropCW + c] = v[u];
+    }
+  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < u2c * NBX; t += 256) G2s[t] = Gx_in[(size_t)U2[t / NBX] * NBX + t % NBX];
+  __syncthreads();
+  // stage k -> k+1 on U1, one thread per (node of U1, column of the slice)
+  for (int it = threadIdx.x; it < u1c * kPropCW; it += 256) {
+    const int lu = it / kPropCW, cl = it - lu * kPropCW, col = c0 + cl, u = U1[lu];
+    T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (col < cin) {
+      for (int e = R1[lu]; e < R1[lu + 1]; ++e) {
+        const T* Ae = A1s + (size_t)e * 36;
+        const T* Su = S2s + (size_t)Es2[e] * NBX * kPropCW + cl;
+        T sv[6], av[36];
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) sv[sr] = Su[sr * kPropCW];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ld4v(Ae + 4 * q, *reinterpret_cast<T(*)[4]>(av + 4 * q));
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int sr = 0; sr < 6; ++sr) o[r] += av[r * 6 + sr] * sv[sr];
+      }
+    } else if (col < cmid) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) o[r] = B_k[((size_t)u * NBX + r) * nu + (col - cin)];
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) S1s[((size_t)lu * NBX + r) * kPropCW + cl] = o[r];
+    if (u >= node0 && u < node0 + nn && col < cmid) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) S_mid[((size_t)u * NBX + r) * cmid + col] = o[r];
+    }
+  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < u1c * NBX; t += 256) {
+      const int lu = t / NBX, r = t - lu * NBX, u = U1[lu];
+      T v = T(0);
+      for (int e = R1[lu]; e < R1[lu + 1]; ++e) {
+        const T* Ae = A1s + (size_t)e * 36 + r * 6;
+        const T* xj = G2s + (size_t)Es2[e] * NBX;
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) v += Ae[sr] * xj[sr];
+      }
+      v = v + c_k[(size_t)u * NBX + r];
+      G1s[t] = v;
+      if (u >= node0 && u < node0 + nn) Gx_mid[(size_t)u * NBX + r] = v;
+    }
+  __syncthreads();
+  // stage k+1 -> k+2 on the block
+  for (int it = threadIdx.x; it < nn * kPropCW; it += 256) {
+    const int ln = it / kPropCW, cl = it - ln * kPropCW, col = c0 + cl, i = node0 + ln;
+    if (col >= cout) continue;
+    if (col < cmid) {
+      T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      const int rs = Rs[ln], w = Rs[ln + 1] - rs;
+      for (int e = 0; e < w; ++e) {
+        const T* Ae = A2s + (size_t)(rs + e) * 36;
+        const T* Su = S1s + (size_t)Es1[rs + e] * NBX * kPropCW + cl;
+        T sv[6], av[36];
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) sv[sr] = Su[sr * kPropCW];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ld4v(Ae + 4 * q, *reinterpret_cast<T(*)[4]>(av + 4 * q));
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int sr = 0; sr < 6; ++sr) o[r] += av[r * 6 + sr] * sv[sr];
+      }
+#pragma unroll
+      for (int r = 0; r < 6; ++r) S_out[((size_t)i * NBX + r) * cout + col] = o[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+        S_out[((size_t)i * NBX + r) * cout + col] = B_k1[((size_t)i * NBX + r) * nu + (col - cmid)];
+    }
+  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < nn * NBX; t += 256) {
+      const int ln = t / NBX, r = t - ln * NBX, i = node0 + ln;
+      T v = T(0);
+      for (int e = Rs[ln]; e < Rs[ln + 1]; ++e) {
+        const T* Ae = A2s + (size_t)e * 36 + r * 6;
+        const T* xj = G1s + (size_t)Es1[e] * NBX;
+#pragma unroll
+        for (int sr = 0; sr < 6; ++sr) v += Ae[sr] * xj[sr];
+      }
+      Gx_out[(size_t)i * NBX + r] = v + c_k1[(size_t)i * NBX + r];
+    }
+}
+
 // ---------------------------------------------------------------- Gram + gradient
 // H: 32x32 output tiles of the lower triangle, one workgroup per (tile, stage,
 // row chunk); each of the 4 waves owns a 16x16 quarter and runs
@@ -596,8 +780,27 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   if (use_blocks)
     GNMPC_HIP_TRY(p, set_max_lds((const void*)sprop_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)pb_lds));
+  const bool use2 = use_blocks && p->pb2_stride > 0;
+  size_t pb2_lds = 0;
+  if (use2) {
+    const Prop2Layout L2 = prop2_layout(p->pb_nodes, p->pb_emax, p->pb2_u1max, p->pb2_e1max, p->pb2_u2max);
+    pb2_lds = prop2_lds_bytes(L2, sizeof(T), p->pb_emax, p->pb2_u1max, p->pb2_e1max, p->pb2_u2max);
+    GNMPC_HIP_TRY(p, set_max_lds((const void*)sprop2_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)pb2_lds));
+  }
   for (int k = 0; k < N; ++k) {
     const T* S_in = k ? S + S_offset(k, M, nu) : nullptr;
+    if (use2 && k + 1 < N) {  // stages k and k + 1 in one launch
+      dim3 grid(p->pb_count, ceil_div((k + 2) * nu, kPropCW));
+      const size_t sA = (size_t)p->nnz * 36, sB = (size_t)M * NBX * nu, sG = (size_t)M * NBX;
+      sprop2_block_kernel<T><<<grid, 256, pb2_lds, s>>>(
+          k, M, nu, p->pb_nodes, p->pb_emax, p->pb2_u1max, p->pb2_e1max, p->pb2_u2max, p->d_pb2_rec,
+          (const T*)A + k * sA, (const T*)A + (k + 1) * sA, (const T*)B + k * sB, (const T*)B + (k + 1) * sB,
+          (const T*)c + k * sG, (const T*)c + (k + 1) * sG, S_in, S + S_offset(k + 1, M, nu),
+          S + S_offset(k + 2, M, nu), G + k * sG, G + (k + 1) * sG, G + (k + 2) * sG);
+      ++k;
+      continue;
+    }
     if (use_blocks) {
       dim3 grid(p->pb_count, ceil_div((k + 1) * nu, kPropCW));
       sprop_block_kernel<T><<<grid, 256, pb_lds, s>>>(
@@ -660,6 +863,11 @@ void prop_blocks_free(gnmpc_plan* p) {
     (void)hipFree(p->d_pb_rec);
     p->d_pb_rec = nullptr;
   }
+  if (p->d_pb2_rec) {
+    (void)hipFree(p->d_pb2_rec);
+    p->d_pb2_rec = nullptr;
+  }
+  p->pb2_stride = p->pb2_u1max = p->pb2_u2max = p->pb2_e1max = 0;
   p->pb_nodes = p->pb_count = p->pb_umax = p->pb_emax = p->pb_rec_stride = 0;
 }
 
@@ -667,6 +875,8 @@ void prop_blocks_free(gnmpc_plan* p) {
 // 1 nodes: one thread per node and column of a 64-column slice) whose staged
 // union and A blocks fit 64 KB of LDS in the plan's precision; pb_nodes = 0 if
 // even single nodes do not fit.
+gnmpc_status prop_blocks2_build(gnmpc_plan* p);
+
 gnmpc_status prop_blocks_build(gnmpc_plan* p) {
   prop_blocks_free(p);
   const int M = p->M;
@@ -712,8 +922,84 @@ gnmpc_status prop_blocks_build(gnmpc_plan* p) {
     p->pb_umax = umax;
     p->pb_emax = emax;
     p->pb_rec_stride = stride;
-    return GNMPC_OK;
+    return prop_blocks2_build(p);
   }
+  return GNMPC_OK;
+}
+
+// Two-stage records of the propagation blocks: U1 = the union of the block's pattern
+// columns (the nodes whose S_{k+1} rows the block's S_{k+2} rows read), U1's pattern
+// entries (global index, position of the column in U2) and U2 = the union of U1's
+// pattern columns.  Layout per block (int32): e0, ne, nn, |U1|, |U2|, U1 entry count, 0, 0,
+// then the arrays at the offsets of Prop2Layout.  Not used (pb2_stride = 0) when the
+// staged rows do not fit 64 KB of LDS.
+gnmpc_status prop_blocks2_build(gnmpc_plan* p) {
+  if (p->d_pb2_rec) {
+    (void)hipFree(p->d_pb2_rec);
+    p->d_pb2_rec = nullptr;
+  }
+  p->pb2_stride = p->pb2_u1max = p->pb2_u2max = p->pb2_e1max = 0;
+  const int M = p->M, nb = p->pb_nodes;
+  if (nb <= 0) return GNMPC_OK;
+  const int nblk = p->pb_count;
+  std::vector<std::vector<int32_t>> U1(nblk), U2(nblk), E1(nblk), P2(nblk), R1(nblk);
+  int u1max = 0, u2max = 0, e1max = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int node0 = b * nb, node1 = std::min(M, node0 + nb);
+    const int e0 = p->h_prow[node0], e1 = p->h_prow[node1];
+    std::vector<int32_t>& u1 = U1[b];
+    u1.assign(p->h_pcol.begin() + e0, p->h_pcol.begin() + e1);
+    std::sort(u1.begin(), u1.end());
+    u1.erase(std::unique(u1.begin(), u1.end()), u1.end());
+    std::vector<int32_t>& u2 = U2[b];
+    R1[b].push_back(0);
+    for (int32_t u : u1) {
+      for (int e = p->h_prow[u]; e < p->h_prow[u + 1]; ++e) {
+        E1[b].push_back(e);
+        u2.push_back(p->h_pcol[e]);
+      }
+      R1[b].push_back((int32_t)E1[b].size());
+    }
+    std::sort(u2.begin(), u2.end());
+    u2.erase(std::unique(u2.begin(), u2.end()), u2.end());
+    for (int32_t e : E1[b])
+      P2[b].push_back((int32_t)(std::lower_bound(u2.begin(), u2.end(), p->h_pcol[e]) - u2.begin()));
+    u1max = std::max(u1max, (int)u1.size());
+    u2max = std::max(u2max, (int)u2.size());
+    e1max = std::max(e1max, (int)E1[b].size());
+  }
+  const Prop2Layout L = prop2_layout(nb, p->pb_emax, u1max, e1max, u2max);
+  const size_t lds = prop2_lds_bytes(L, (size_t)p->elem, p->pb_emax, u1max, e1max, u2max);
+  if (lds > 64 * 1024) return GNMPC_OK;
+  std::vector<int32_t> rec((size_t)nblk * L.stride, 0);
+  for (int b = 0; b < nblk; ++b) {
+    int32_t* r = rec.data() + (size_t)b * L.stride;
+    const int node0 = b * nb, node1 = std::min(M, node0 + nb);
+    const int e0 = p->h_prow[node0], e1 = p->h_prow[node1];
+    r[0] = e0;
+    r[1] = e1 - e0;
+    r[2] = node1 - node0;
+    r[3] = (int32_t)U1[b].size();
+    r[4] = (int32_t)U2[b].size();
+    r[5] = (int32_t)E1[b].size();
+    for (int t = 0; t <= node1 - node0; ++t) r[L.rs + t] = p->h_prow[node0 + t] - e0;
+    for (int e = e0; e < e1; ++e)
+      r[L.es1 + (e - e0)] = (int32_t)(std::lower_bound(U1[b].begin(), U1[b].end(), p->h_pcol[e]) - U1[b].begin());
+    for (size_t t = 0; t < U1[b].size(); ++t) r[L.u1 + t] = U1[b][t];
+    for (size_t t = 0; t < R1[b].size(); ++t) r[L.r1 + t] = R1[b][t];
+    for (size_t t = 0; t < E1[b].size(); ++t) {
+      r[L.g1 + t] = E1[b][t];
+      r[L.es2 + t] = P2[b][t];
+    }
+    for (size_t t = 0; t < U2[b].size(); ++t) r[L.u2 + t] = U2[b][t];
+  }
+  GNMPC_HIP_TRY(p, hipMalloc((void**)&p->d_pb2_rec, sizeof(int32_t) * std::max<size_t>(rec.size(), 1)));
+  if (!rec.empty())
+    GNMPC_HIP_TRY(p, hipMemcpy(p->d_pb2_rec, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice));
+  p->pb2_stride = L.stride;
+  p->pb2_u1max = u1max;
+  p->pb2_u2max = u2max;
+  p->pb2_e1max = e1max;
   return GNMPC_OK;
 }
 

@@ -28,6 +28,10 @@ struct gnmpc_plan {
   // per pattern entry, the position of its column in that union)
   int pb_nodes = 0, pb_count = 0, pb_umax = 0, pb_emax = 0, pb_rec_stride = 0;
   int32_t* d_pb_rec = nullptr;
+  // two-stage records of the same blocks (0 = not used): the block's union U1, the
+  // union U2 of U1's pattern rows, U1's entries with their positions in U2
+  int pb2_stride = 0, pb2_u1max = 0, pb2_u2max = 0, pb2_e1max = 0;
+  int32_t* d_pb2_rec = nullptr;
 
   // model
   int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN

@@ -133,6 +133,7 @@ def _random_blocks(rng, M, hops, L, N, nu, spread=0.6):
     (37, 2, 2, 7, 9, 11, True, torch.float64),
     (37, 2, 2, 7, 9, 11, False, torch.float32),
     (130, 1, 3, 5, 6, 0, False, torch.float32),     # more than one node chunk, ragged tiles
+    (50, 1, 1, 9, 4, 5, True, torch.float64),       # two-stage recursion launches, odd N (last stage alone)
     (1, 1, 1, 4, 3, 2, True, torch.float64),        # a single node (textbook dense condensing)
     (20, 2, 1, 1, 6, 3, False, torch.float64),      # horizon one
 ])
