@@ -195,6 +195,20 @@ gnmpc_status gnmpc_rows_set(gnmpc_plan* plan, int32_t n_c, const int32_t* node, 
 gnmpc_status gnmpc_linearize(gnmpc_plan* plan, const void* xhat, const void* uhat,
                              void* A, void* B, void* c, void* fnext, void* stream);
 
+/* Tangent maps of the linearized one-step model x_{k+1} = f(x_k, u_k) of Sec. V-A,
+ * from the blocks gnmpc_linearize produced (A [N][nnz][6][6], B [N][M][6][nu], in
+ * the plan's pattern and dtype).  Device arrays of the plan dtype, all N stages:
+ *   gnmpc_jvp: out[k] = A_k dx[k] + B_k du[k]       dx, out [N][M][6]; du [N][nu]
+ *   gnmpc_vjp: gx[k] = A_k' g[k], gu[k] = B_k' g[k] g, gx [N][M][6]; gu [N][nu]
+ * (the directional derivative and the gradient of g . f at the linearization
+ * points).  Every output element is one fixed-order sum, so repeated calls give
+ * bitwise identical results.  Outputs may not alias inputs.  GNMPC_NOT_READY
+ * before gnmpc_graph_set; GNMPC_INVALID_ARG for a NULL array. */
+gnmpc_status gnmpc_jvp(gnmpc_plan* plan, const void* A, const void* B, const void* dx, const void* du,
+                       void* out, void* stream);
+gnmpc_status gnmpc_vjp(gnmpc_plan* plan, const void* A, const void* B, const void* g, void* gx, void* gu,
+                       void* stream);
+
 /* Condense the linear time-varying OCP (Sec. V-B): propagate the sensitivities
  * S^i_{k+1} = sum_{j in N~_i} A^{ij}_k S^j_k (+ B^i_k in column block k) and
  * Gx^i_{k+1} = sum_j A^{ij}_k Gx^j_k + c^i_k from S_0 = 0, Gx_0 = x0, then form

@@ -230,6 +230,8 @@ void gnmpc_plan_destroy(gnmpc_plan* p) {
   dfree(p->d_pcol);
   dfree(p->d_erow);
   dfree(p->d_diag);
+  dfree(p->d_cptr);
+  dfree(p->d_cent);
   prop_blocks_free(p);
   dfree(p->d_act_of_node);
   dfree(p->d_row_node);
@@ -263,6 +265,14 @@ gnmpc_status gnmpc_graph_set(gnmpc_plan* p, const int32_t* row_ptr, const int32_
     }
   }
   if (wmax > kMaxWidth) return fail(p, GNMPC_UNSUPPORTED, "graph_set: Jacobian pattern row wider than 64 blocks");
+  // the pattern by column (entries of column node j in increasing order), for the VJP
+  std::vector<int32_t> cptr(M + 1, 0), cent(pcol.size());
+  for (int32_t c : pcol) ++cptr[c + 1];
+  for (int32_t j = 0; j < M; ++j) cptr[j + 1] += cptr[j];
+  {
+    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (size_t e = 0; e < pcol.size(); ++e) cent[fill[pcol[e]]++] = (int32_t)e;
+  }
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   p->graph_ready = false;
   p->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
@@ -280,6 +290,8 @@ gnmpc_status gnmpc_graph_set(gnmpc_plan* p, const int32_t* row_ptr, const int32_
   if ((s = upload(p, p->d_pcol, pcol.data(), pcol.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_erow, erow.data(), erow.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_diag, diag.data(), diag.size())) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_cptr, cptr.data(), cptr.size())) != GNMPC_OK) return s;
+  if ((s = upload(p, p->d_cent, cent.data(), cent.size())) != GNMPC_OK) return s;
   if ((s = prop_blocks_build(p)) != GNMPC_OK) return s;
   p->graph_ready = true;
   p->model = 0;  // a model must be (re)bound to the new graph
@@ -406,6 +418,24 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const v
     return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: bad settings");
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
+}
+
+gnmpc_status gnmpc_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
+                       void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!A || !B || !dx || !du || !out) return fail(p, GNMPC_INVALID_ARG, "jvp: null array");
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "jvp: graph must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_jvp(p, A, B, dx, du, out, (hipStream_t)stream);
+}
+
+gnmpc_status gnmpc_vjp(gnmpc_plan* p, const void* A, const void* B, const void* g, void* gx, void* gu,
+                       void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!A || !B || !g || !gx || !gu) return fail(p, GNMPC_INVALID_ARG, "vjp: null array");
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "vjp: graph must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_vjp(p, A, B, g, gx, gu, (hipStream_t)stream);
 }
 
 // Library streams of the batched step, per device, created once (default priority).

@@ -22,6 +22,7 @@ struct gnmpc_plan {
   std::vector<int32_t> h_row_ptr, h_col, h_prow, h_pcol;
   int32_t *d_row_ptr = nullptr, *d_col = nullptr;
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_erow = nullptr, *d_diag = nullptr;
+  int32_t *d_cptr = nullptr, *d_cent = nullptr;  // the pattern by column: entries of column node j
   // propagation blocks: pb_nodes consecutive nodes per block; one record of
   // pb_rec_stride words per block (first pattern entry, entry count, union
   // size, node count, row starts, the union of the nodes' pattern columns and,
@@ -121,6 +122,11 @@ void prop_blocks_free(gnmpc_plan* p);
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
                        int n_c, const void* Ct, const void* lc, const void* uc,
                        const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
+// tangent.hip
+gnmpc_status launch_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
+                        hipStream_t s);
+gnmpc_status launch_vjp(gnmpc_plan* p, const void* A, const void* B, const void* g, void* gx, void* gu,
+                        hipStream_t s);
 // gnn.hip
 gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w);
 void gnn_free(gnmpc_plan* p);

@@ -90,6 +90,8 @@ def lib():
             "gnmpc_model_set_gnn": ([vp, P(GnnDesc), vp, i64, vp, i32], i32),
             "gnmpc_rows_set": ([vp, i32, vp, vp], i32),
             "gnmpc_linearize": ([vp] + [vp] * 7, i32),
+            "gnmpc_jvp": ([vp] * 7, i32),
+            "gnmpc_vjp": ([vp] * 7, i32),
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
@@ -247,6 +249,20 @@ class Plan:
                 self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
                 self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True)]
         self._check(lib().gnmpc_linearize(self._h, *args, _stream(stream)), "linearize")
+
+    def jvp(self, A, B, dx, du, out, stream=None):
+        """out[k] = A_k dx[k] + B_k du[k] (gnmpc_jvp)."""
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(dx, (N, M, 6), "dx"), self._dev(du, (N, nu), "du"), self._dev(out, (N, M, 6), "out")]
+        self._check(lib().gnmpc_jvp(self._h, *args, _stream(stream)), "jvp")
+
+    def vjp(self, A, B, g, gx, gu, stream=None):
+        """gx[k] = A_k' g[k], gu[k] = B_k' g[k] (gnmpc_vjp)."""
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(g, (N, M, 6), "g"), self._dev(gx, (N, M, 6), "gx"), self._dev(gu, (N, nu), "gu")]
+        self._check(lib().gnmpc_vjp(self._h, *args, _stream(stream)), "vjp")
 
     def condense(self, A, B, c, x0, Q, q, R, r, rowC, rowd, H, g, Ct, dt, Gx=None, stream=None):
         M, N, nu, nc = self.M, self.N, self.nu, self.n_c
