@@ -288,8 +288,40 @@ def main():
         "qp_status_gnn": qpi.status,
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(P, Pm),
+        "tangent": tangent_rates(gn, plan_g, bg, args.steps),
     }
     print(json.dumps(out), flush=True)
+
+
+def tangent_rates(gn, plan, b, reps):
+    """gnmpc_jvp and gnmpc_vjp on the step's GNN blocks (A, B of all 20 stages),
+    timed with HIP events on the stream they run on; algorithmic HBM bytes per call
+    (each block read once, each vector read or written once) over the average time."""
+    import torch
+    N, M, nu, nnz = plan.N, plan.M, plan.nu, plan.nnz
+    A, B = b["A"], b["B"]
+    dx = torch.randn(N, M, 6, device="cuda")
+    du = torch.randn(N, nu, device="cuda")
+    out = torch.empty(N, M, 6, device="cuda")
+    gx = torch.empty(N, M, 6, device="cuda")
+    gu = torch.empty(N, nu, device="cuda")
+    blocks = 4 * (N * nnz * 36 + N * M * 6 * nu)
+    vec = 4 * (N * M * 6)
+    res = {}
+    for name, fn, nbytes in (("jvp", lambda: plan.jvp(A, B, dx, du, out), blocks + 2 * vec + 4 * N * nu),
+                             ("vjp", lambda: plan.vjp(A, B, out, gx, gu), blocks + 2 * vec + 4 * N * nu)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": ms, "bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / 8e12}
+    return res
 
 
 def bench_batch(args, torch, gn, wl):
