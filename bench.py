@@ -136,7 +136,7 @@ def main():
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
+        print("bench.py runs the hot path on one GPU only; multi-GPU runs are not supported "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ typedef enum {
   GNMPC_INVALID_ARG = 1,     /* null pointer, non-positive size, bad enum      */
   GNMPC_BAD_GRAPH = 2,       /* malformed CSR: unsorted, duplicate, self loop, out of range */
   GNMPC_SHAPE = 3,           /* size disagrees with the plan                     */
-  GNMPC_UNSUPPORTED = 4,     /* valid request outside what this build supports  */
+  GNMPC_UNSUPPORTED = 4,     /* valid request outside what the library supports */
   GNMPC_HIP_ERROR = 5,       /* a HIP runtime call failed                       */
   GNMPC_BAD_CONSTRAINT = 6,  /* state row on stage 0 or outside 1..N, bad node  */
   GNMPC_NOT_READY = 7,       /* graph / model / rows not set yet                */
