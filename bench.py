@@ -97,7 +97,7 @@ def cpu_baseline(P, Pm):
     stages, nodes = [3, 7, 11, 15, 19], list(range(300, 500))
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes, rounding="bf16")
+        gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes)
         t_lin = (time.perf_counter() - t0) / (len(stages) * len(nodes)) * P.N * P.M
         prow, pcol = jacobian_pattern(P.row_ptr, P.col, P.M, P.gnn.L)
         mrow, mcol, Am, Bm, cm = msd_linearize(Pm.xhat, Pm.uhat, Pm.row_ptr, Pm.col, Pm.act, Pm.msd)

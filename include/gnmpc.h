@@ -98,7 +98,10 @@ typedef struct {
 typedef struct {
   int32_t Hd;       /* hidden width: 64, 128, 192 or 256                          */
   int32_t L;        /* message-passing rounds (must equal the graph's L)          */
-  int32_t dtype;    /* GNMPC_F32 or GNMPC_BF16 (BF16 operands, FP32 accumulate)   */
+  int32_t dtype;    /* GNMPC_F32, or GNMPC_BF16: weights rounded to bfloat16; the  */
+                    /* forward pass keeps activations at FP32 accuracy (so the   */
+                    /* ReLU decisions are FP32's), the Jacobian's tangent        */
+                    /* products take bfloat16 operands with FP32 accumulation    */
   int32_t reserved;
   double dt;
 } gnmpc_gnn_desc;
@@ -266,7 +269,11 @@ typedef struct {
  * created on the first call, which must not be captured).  Settings apply to
  * every QP.  Each instance's arrays are validated as by the single calls; on
  * an error the work already forked is still joined and the first failing
- * status is returned (that plan's last_error names the cause). */
+ * status is returned (that plan's last_error names the cause).  Every plan
+ * may appear in one descriptor only (GNMPC_INVALID_ARG otherwise, before
+ * anything is enqueued): a plan's workspace serves one instance at a time.
+ * Concurrent calls from several host threads are serialized while they
+ * enqueue. */
 gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count,
                                 const gnmpc_admm_settings* settings, void* stream);
 

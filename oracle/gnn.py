@@ -18,31 +18,18 @@ derivative mask is z > 0).  The offset is c = f(xhat,uhat) - sum_j A^{ij} xhat^j
 ``activation='identity'`` replaces every ReLU by the identity; it exists only
 so the tests can compare against a closed-form affine model.
 
-``rounding='bf16'`` is for comparisons with a kernel that runs the MLPs on
-bfloat16 operands.  A ReLU mask is a bit decided by floating point, so the
-oracle then takes that decision in the kernel's precision: the *values* of the
-forward pass use operands rounded to bfloat16 at the points where the kernel
-rounds them (the node input [x; Pu], every hidden state h and every message
-sum), while all arithmetic stays FP64 and the *tangents* stay exact.  Given the
-masks, the Jacobian is then the exact derivative.
+``gnn_kink_margin`` reports, per node, how close the model is to a ReLU kink
+anywhere in the node's receptive field: the smallest ratio |z| / scale(z) over
+every pre-activation z that f^i depends on, scale(z) being the sum of the
+absolute values of the terms of z (|W| |operand| summed, plus |b|).  A
+computation that carries the activations with relative rounding error eps can
+take a different ReLU decision only where this ratio is of order eps.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .graph import ball, in_neighbours, jacobian_pattern
-
-
-def _round(v, rounding):
-    """Round a value operand to the given storage precision (None = exact FP64)."""
-    if rounding is None:
-        return v
-    if rounding == "bf16":
-        f = np.ascontiguousarray(np.asarray(v, dtype=np.float32))
-        u = f.view(np.uint32).astype(np.uint64)
-        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-        return u.astype(np.uint32).view(np.float32).astype(np.float64)
-    raise ValueError(rounding)
 
 
 def _act(z, activation):
@@ -62,29 +49,75 @@ def node_input(x, u, i, act):
     return np.concatenate([x[i], f])
 
 
-def gnn_forward(x, u, W, row_ptr, col, act, activation="relu", rounding=None):
-    """One step x -> x+ for every node; x is [M][6], returns [M][6]."""
+def _edges(row_ptr, col):
+    """Receiver and sender of every edge, in CSR order (edge e runs col[e] -> its row)."""
+    recv = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    return recv, np.asarray(col, dtype=np.int64)
+
+
+def gnn_forward(x, u, W, row_ptr, col, act, activation="relu", margins=False):
+    """One step x -> x+ for every node; x is [M][6], returns [M][6].
+
+    With ``margins=True`` also returns the margin |z| / scale(z) of every
+    pre-activation: a dict with 'enc' [M][Hd] and, per round l, 'edge'[l]
+    [E][Hd] (CSR edge order) and 'node'[l] [M][Hd].
+    """
     M = x.shape[0]
-    inp = _round(np.stack([node_input(x, u, i, act) for i in range(M)]), rounding)
-    h, _ = _act(inp @ W.W_enc.T + W.b_enc, activation)
-    h = _round(h, rounding)
+    inp = np.stack([node_input(x, u, i, act) for i in range(M)])
+    z = inp @ W.W_enc.T + W.b_enc
+    out = {"enc": np.abs(z) / (np.abs(inp) @ np.abs(W.W_enc).T + np.abs(W.b_enc)), "edge": [], "node": []}
+    h, _ = _act(z, activation)
+    recv, send = _edges(row_ptr, col)
     for l in range(W.L):
+        e_in = np.concatenate([h[recv], h[recv] - h[send]], axis=1)   # [h_i; h_i - h_j] per edge
+        ze = e_in @ W.W_edge[l].T + W.b_edge[l]
+        m, _ = _act(ze, activation)
         agg = np.zeros_like(h)
-        for i in range(M):
-            for j in in_neighbours(row_ptr, col, i):
-                e = np.concatenate([h[i], h[i] - h[j]])
-                m, _ = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
-                agg[i] += m
-        agg = _round(agg, rounding)
-        h, _ = _act(np.concatenate([h, agg], axis=1) @ W.W_node[l].T + W.b_node[l], activation)
-        h = _round(h, rounding)
+        np.add.at(agg, recv, m)                                         # sum over j in N_i
+        # terms of z_e: W1 h_i + W2 h_i - W2 h_j + b, each taken in absolute value
+        W1, W2 = np.abs(W.W_edge[l][:, :W.Hd]), np.abs(W.W_edge[l][:, W.Hd:])
+        se = np.abs(h[recv]) @ (W1 + W2).T + np.abs(h[send]) @ W2.T + np.abs(W.b_edge[l])
+        out["edge"].append(np.abs(ze) / se)
+        n_in = np.concatenate([h, agg], axis=1)
+        zn = n_in @ W.W_node[l].T + W.b_node[l]
+        out["node"].append(np.abs(zn) / (np.abs(n_in) @ np.abs(W.W_node[l]).T + np.abs(W.b_node[l])))
+        h, _ = _act(zn, activation)
     o = h @ W.W_dec.T + W.b_dec
     vn = x[:, 3:] + W.dt * o[:, 3:6]
     pn = x[:, :3] + W.dt * vn
-    return np.concatenate([pn, vn], axis=1)
+    f = np.concatenate([pn, vn], axis=1)
+    return (f, out) if margins else f
 
 
-def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", rounding=None):
+def gnn_kink_margin(x, u, W, row_ptr, col, act, nodes=None):
+    """Smallest pre-activation margin in the receptive field of each node.
+
+    f^i depends on the encoder of every node within L hops of i and, in round
+    l (0-based), on the node update of every node within L-1-l hops of i and
+    on the edges into those nodes.  Returns an array over ``nodes`` (all by
+    default).  A zero scale (every term zero) counts as margin +inf.
+    """
+    M = x.shape[0]
+    _, mg = gnn_forward(x, u, W, row_ptr, col, act, margins=True)
+    recv, _ = _edges(row_ptr, col)
+    with np.errstate(invalid="ignore"):
+        enc = np.nan_to_num(mg["enc"].min(axis=1), nan=np.inf)
+        edge = [np.nan_to_num(e.min(axis=1), nan=np.inf) for e in mg["edge"]]
+        node = [np.nan_to_num(n.min(axis=1), nan=np.inf) for n in mg["node"]]
+    res = []
+    for i in (range(M) if nodes is None else nodes):
+        best = enc[ball(row_ptr, col, i, W.L)].min()
+        for l in range(W.L):
+            near = ball(row_ptr, col, i, W.L - 1 - l)
+            best = min(best, node[l][near].min())
+            sel = np.isin(recv, near)
+            if sel.any():
+                best = min(best, edge[l][sel].min())
+        res.append(best)
+    return np.asarray(res)
+
+
+def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu"):
     """Forward-mode derivative of f^i on node i's receptive subgraph.
 
     Returns (f_i [6], S (sorted receptive nodes), J [6][6|S| + nu]) where the
@@ -106,7 +139,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", roundin
     # encoder on every node of the receptive set
     h, dh = {}, {}
     for j in S:
-        inp = _round(node_input(x, u, j, act), rounding)
+        inp = node_input(x, u, j, act)
         dinp = np.vstack([seed_x(j), np.zeros((3, T))])
         hit = np.nonzero(np.asarray(act) == j)[0]
         if hit.size:
@@ -114,7 +147,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", roundin
             dinp[6:9] = du[3 * a:3 * a + 3]
         z = W.W_enc @ inp + W.b_enc
         hv, mask = _act(z, activation)
-        h[j], dh[j] = _round(hv, rounding), mask[:, None] * (W.W_enc @ dinp)
+        h[j], dh[j] = hv, mask[:, None] * (W.W_enc @ dinp)
     # message-passing rounds: after round l only nodes within L-1-l hops are needed
     for l in range(L):
         keep = ball(row_ptr, col, i, L - 1 - l)
@@ -128,10 +161,9 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", roundin
                 m, mask = _act(W.W_edge[l] @ e + W.b_edge[l], activation)
                 agg += m
                 dagg += mask[:, None] * (W.W_edge[l] @ de)
-            agg = _round(agg, rounding)
             z = W.W_node[l] @ np.concatenate([h[n], agg]) + W.b_node[l]
             hv, mask = _act(z, activation)
-            nh[n] = _round(hv, rounding)
+            nh[n] = hv
             ndh[n] = mask[:, None] * (W.W_node[l] @ np.vstack([dh[n], dagg]))
         h, dh = nh, ndh
     o = W.W_dec @ h[i] + W.b_dec
@@ -145,7 +177,7 @@ def gnn_linearize_node(x, u, W, row_ptr, col, act, i, activation="relu", roundin
 
 
 def gnn_linearize(xhat, uhat, W, row_ptr, col, act, stages=None, nodes=None,
-                  activation="relu", rounding=None):
+                  activation="relu"):
     """A^{ij}_k (L-hop pattern, ascending), B^i_k, c^i_k and f^i_k.
 
     Only the requested (stage, node) pairs are computed (all by default); the
@@ -161,7 +193,7 @@ def gnn_linearize(xhat, uhat, W, row_ptr, col, act, stages=None, nodes=None,
     f = np.full((N, M, 6), np.nan)
     for k in (range(N) if stages is None else stages):
         for i in (range(M) if nodes is None else nodes):
-            fi, S, J = gnn_linearize_node(xhat[k], uhat[k], W, row_ptr, col, act, i, activation, rounding)
+            fi, S, J = gnn_linearize_node(xhat[k], uhat[k], W, row_ptr, col, act, i, activation)
             assert list(pcol[prow[i]:prow[i + 1]]) == S
             lin = J[:, 6 * len(S):] @ uhat[k]
             for p, j in enumerate(S):

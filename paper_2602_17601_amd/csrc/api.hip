@@ -457,20 +457,30 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
   const int dev = descs[0].plan->device;
   for (int32_t i = 1; i < count; ++i)
     if (descs[i].plan->device != dev) return fail(descs[i].plan, GNMPC_INVALID_ARG, "step_batched: plans on different devices");
+  // a plan's workspace serves one instance at a time: a repeated plan would race with itself
+  {
+    std::vector<const gnmpc_plan*> seen(count);
+    for (int32_t i = 0; i < count; ++i) seen[i] = descs[i].plan;
+    std::sort(seen.begin(), seen.end());
+    for (int32_t i = 1; i < count; ++i)
+      if (seen[i] == seen[i - 1])
+        return fail(const_cast<gnmpc_plan*>(seen[i]), GNMPC_INVALID_ARG, "step_batched: a plan appears in two descriptors");
+  }
   if (dev < 0 || dev >= 64) return GNMPC_INVALID_ARG;
   gnmpc_plan* p0 = descs[0].plan;
   GNMPC_HIP_TRY(p0, hipSetDevice(dev));
   BatchStreams& bs = pool[dev];
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    if (!bs.ready) {
-      for (int t = 0; t < kBatchStreams; ++t) {
-        GNMPC_HIP_TRY(p0, hipStreamCreateWithFlags(&bs.s[t], hipStreamNonBlocking));
-        GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.join[t], hipEventDisableTiming));
-      }
-      GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.fork, hipEventDisableTiming));
-      bs.ready = true;
+  // The fork and join events of a device are shared by every call, so one call's
+  // record-then-wait sequence must not interleave with another's: the whole
+  // enqueue runs under the lock (enqueueing does not wait for the GPU).
+  std::lock_guard<std::mutex> lock(mu);
+  if (!bs.ready) {
+    for (int t = 0; t < kBatchStreams; ++t) {
+      GNMPC_HIP_TRY(p0, hipStreamCreateWithFlags(&bs.s[t], hipStreamNonBlocking));
+      GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.join[t], hipEventDisableTiming));
     }
+    GNMPC_HIP_TRY(p0, hipEventCreateWithFlags(&bs.fork, hipEventDisableTiming));
+    bs.ready = true;
   }
   const hipStream_t caller = (hipStream_t)stream;
   const int used = std::min<int32_t>(count, kBatchStreams);

@@ -16,8 +16,11 @@
 // hops of the seeds, so the workgroup carries exactly those nodes (lists built
 // on the host), and after the decoder it owns the blocks A^{is} and B^i of
 // every node i reached by its seeds.  No tangent ever leaves the chip.
-// In BF16 mode every GEMM operand (weights, activations, tangents) is rounded
-// to bfloat16 (round to nearest even) and products are accumulated in FP32.
+// In BF16 mode the weights are bfloat16 (round to nearest even).  The forward
+// pass keeps the activations in FP32 -- on the matrix cores each FP32 operand
+// enters as three bf16 terms hi + mid + lo, so the products are exact and the
+// sums FP32 -- and therefore takes every ReLU decision at FP32 accuracy; the
+// Jacobian pass rounds the tangents to bfloat16 and accumulates in FP32.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -61,8 +64,7 @@ struct GnnState {
   int32_t *img_src = nullptr, *t2_meta = nullptr, *t2_V = nullptr, *t2_Vself = nullptr, *t2_colmap = nullptr;
   uint32_t* img = nullptr;  // stage images [N][img_words]
   long img_words = 0;
-  // matrix-core forward pass (BF16): hidden states as bf16, node column tiles
-  uint16_t* h16 = nullptr;        // [L+1][N][M][Hd]
+  // matrix-core forward pass (BF16 weights): node column tiles
   uint8_t* cnt = nullptr;         // [L][N][M][Hd] active in-edges of each node per feature
   int n_ftiles = 0, fedge_cap = 0;
   int32_t *fcols = nullptr;       // [n_ftiles][NC] node of each column (-1 = empty)
@@ -151,10 +153,10 @@ __global__ void fwd_enc_kernel(FwdArgs a) {
   for (int d = 0; d < 3; ++d) in[6 + d] = act >= 0 ? a.uhat[(size_t)k * a.nu + 3 * act + d] : 0.f;
   float z = a.benc[f];
 #pragma unroll
-  for (int d = 0; d < 9; ++d) z += a.encT[d * a.Hd + f] * (a.bf16 ? bf16r(in[d]) : in[d]);
+  for (int d = 0; d < 9; ++d) z += a.encT[d * a.Hd + f] * in[d];
   bool on = z > 0.f;
   float hv = on ? z : 0.f;
-  a.h[(size_t)s * a.Hd + f] = a.bf16 ? bf16r(hv) : hv;
+  a.h[(size_t)s * a.Hd + f] = hv;
   store_mask(a.mask_enc + (size_t)s * (a.Hd / 32), f, on);
 }
 
@@ -189,7 +191,7 @@ __global__ void fwd_layer_kernel(FwdArgs a, int l) {
     store_mask(me + (size_t)(e0 + t) * (Hd / 32), f, on);
   }
   float* sagg = sh + (size_t)(1 + deg) * Hd;  // after the inputs
-  sagg[f] = a.bf16 ? bf16r(agg) : agg;
+  sagg[f] = agg;
   __syncthreads();
   const float* W1 = a.Wn1T + (size_t)l * Hd * Hd;
   const float* W2 = a.Wn2T + (size_t)l * Hd * Hd;
@@ -197,7 +199,7 @@ __global__ void fwd_layer_kernel(FwdArgs a, int l) {
   for (int q = 0; q < Hd; ++q) z += W1[q * Hd + f] * sh[q] + W2[q * Hd + f] * sagg[q];
   bool on = z > 0.f;
   float hv = on ? z : 0.f;
-  a.h[((size_t)(l + 1) * a.N * a.M + s) * Hd + f] = a.bf16 ? bf16r(hv) : hv;
+  a.h[((size_t)(l + 1) * a.N * a.M + s) * Hd + f] = hv;
   store_mask(a.mask_node + ((size_t)l * a.N * a.M + s) * (Hd / 32), f, on);
 }
 
@@ -1043,34 +1045,29 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
 
 
 // ---------------------------------------------------------------------------
-// Forward pass on the matrix cores (BF16 operands, FP32 accumulation).  One
-// workgroup per (column tile, stage): a tile is 16 node columns -- the target
-// nodes whose next hidden state it produces plus the senders of their edges --
-// so each round is two 16-column GEMMs per tile: [W_a; W_b] h (edge terms) and
-// [W_n1 W_n2] [h; agg] (node update).  ReLU masks leave as 4-bit groups staged
-// in LDS bytes and packed into the same bit layout as the VALU path.
-__global__ void fwd_enc_bf16_kernel(FwdArgs a, uint16_t* h0) {
-  const int s = blockIdx.x;
-  const int k = s / a.M, i = s - k * a.M;
-  const int f = threadIdx.x;
-  float in[9];
-  const float* x = a.xhat + (size_t)s * NBX;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) in[d] = x[d];
-  const int act = a.act_of_node[i];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) in[6 + d] = act >= 0 ? a.uhat[(size_t)k * a.nu + 3 * act + d] : 0.f;
-  float z = a.benc[f];
-#pragma unroll
-  for (int d = 0; d < 9; ++d) z += a.encT[d * a.Hd + f] * bf16r(in[d]);
-  const bool on = z > 0.f;
-  h0[(size_t)s * a.Hd + f] = (uint16_t)(__float_as_uint(bf16r(on ? z : 0.f)) >> 16);
-  store_mask(a.mask_enc + (size_t)s * (a.Hd / 32), f, on);
+// Forward pass on the matrix cores: bf16 weights, FP32 activations.  An FP32
+// operand v enters an MFMA as three bf16 terms, hi = bf16(v), mid =
+// bf16(v - hi), lo = bf16(v - hi - mid) (each residual is exact in FP32), so
+// hi + mid + lo equals v to about 2^-24 relative; the bf16 x bf16 products
+// are exact and the sums FP32, which keeps every ReLU decision at FP32
+// accuracy.  One workgroup per (column tile, stage): a tile is 16 or 32 node
+// columns -- the target nodes whose next hidden state it produces plus the
+// senders of their edges -- so each round is two GEMMs per tile: [W_a; W_b] h
+// (edge terms) and [W_n1 W_n2] [h; agg] (node update).  ReLU masks leave as
+// 4-bit groups staged in LDS bytes and packed into the same bit layout as the
+// VALU path.
+
+// Three-term bf16 split of an FP32 pair, each term packed (a | b << 16).
+__device__ inline void split3_bf16x2(float a, float b, uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  p0 = pack_bf16x2(a, b);
+  const float ra = a - __uint_as_float(p0 << 16), rb = b - __uint_as_float(p0 & 0xFFFF0000u);
+  p1 = pack_bf16x2(ra, rb);
+  p2 = pack_bf16x2(ra - __uint_as_float(p1 << 16), rb - __uint_as_float(p1 & 0xFFFF0000u));
 }
 
 // Decoder velocity rows on the last hidden state: 16 lanes per (stage, node),
 // each taking 8 consecutive features, reduced across the 16 lanes.
-__global__ void fwd_dec_bf16_kernel(FwdArgs a, const uint16_t* hL) {
+__global__ void fwd_dec_coop_kernel(FwdArgs a, const float* hL) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long s = t >> 4;
   const int sub = (int)(t & 15);
@@ -1078,14 +1075,13 @@ __global__ void fwd_dec_bf16_kernel(FwdArgs a, const uint16_t* hL) {
   float o[3] = {0.f, 0.f, 0.f};
   if (live) {
     for (int f0 = 8 * sub; f0 < a.Hd; f0 += 128) {
-      const uint4 hv = *reinterpret_cast<const uint4*>(hL + (size_t)s * a.Hd + f0);
-      const uint32_t w[4] = {hv.x, hv.y, hv.z, hv.w};
+      const float4* hp = reinterpret_cast<const float4*>(hL + (size_t)s * a.Hd + f0);
+      const float4 h0 = hp[0], h1 = hp[1];
+      const float h[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float h = __uint_as_float(q & 1 ? (w[q >> 1] & 0xFFFF0000u) : (w[q >> 1] << 16));
+      for (int q = 0; q < 8; ++q)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) o[r] += a.decT[(f0 + q) * 6 + 3 + r] * h;
-      }
+        for (int r = 0; r < 3; ++r) o[r] += a.decT[(f0 + q) * 6 + 3 + r] * h[q];
     }
   }
 #pragma unroll
@@ -1108,8 +1104,8 @@ __global__ void fwd_dec_bf16_kernel(FwdArgs a, const uint16_t* hL) {
 
 struct FwdMfmaArgs {
   int N, M, E, l, fedge_cap;
-  const uint16_t *hin;
-  uint16_t* hout;
+  const float* hin;                     // this round's input activations [N][M][Hd]
+  float* hout;                          // its output activations
   const uint16_t *Wa, *Wb, *Wn1, *Wn2;  // this round's weights, bf16 row-major (out, in)
   const float *be, *bn;                 // this round's biases
   uint32_t *mask_edge, *mask_node;      // this round, all stages
@@ -1122,31 +1118,52 @@ struct FwdMfmaArgs {
 // kFwdCT MFMA column groups.
 constexpr int kFwdCT = 2;
 __host__ __device__ constexpr int fwd_groups(int Hd) { return Hd <= 128 ? kFwdCT : 1; }
+// Dynamic LDS of fwd_mfma_layer_kernel: three bf16 planes of the layer input and
+// of the aggregates, the FP32 W_b h of every column, then the staged mask groups.
+__host__ __device__ constexpr size_t fwd_planes_bytes(int Hd) { return (size_t)16 * fwd_groups(Hd) * Hd * 2; }
+size_t fwd_lds_bytes(int Hd, int fedge_cap) {
+  const int NC = 16 * fwd_groups(Hd);
+  return 6 * fwd_planes_bytes(Hd) + (size_t)NC * Hd * 4 + (size_t)(fedge_cap + NC) * (Hd / 4);
+}
 
 template <int MT>
 __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   constexpr int Hd = MT * 64, KB = Hd / 32, RW = Hd / 4, CB = Hd * 2, HW = Hd / 32, NQ = Hd / 4;
   constexpr int CT = fwd_groups(Hd), NC = 16 * CT;
-  __shared__ __attribute__((aligned(16))) unsigned char Hs[NC * CB];   // layer input, bf16 columns
-  __shared__ __attribute__((aligned(16))) unsigned char Ag[NC * CB];   // aggregates, bf16 columns
-  __shared__ __attribute__((aligned(16))) float Ybs[NC * Hd];          // W_b h per column, fp32
-  extern __shared__ unsigned char qmask[];                            // [edges + NC][NQ] 4-bit groups
+  constexpr int PL = NC * CB;  // bytes of one bf16 plane
+  extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+  unsigned char* Hs = fsm;                                 // [3][NC][CB] layer input: hi, mid, lo
+  unsigned char* Ag = Hs + 3 * PL;                         // [3][NC][CB] aggregates: hi, mid, lo
+  float* Ybs = reinterpret_cast<float*>(Ag + 3 * PL);      // [NC][Hd] W_b h per column
+  unsigned char* qmask = reinterpret_cast<unsigned char*>(Ybs + NC * Hd);  // [edges + NC][NQ] 4-bit groups
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* fm = a.fmeta + (size_t)tile * 4;
   const int nt = fm[0], eb = fm[1], ec = fm[2];
   const int32_t* cols = a.fcols + (size_t)tile * NC;
-  // ---- gather the input columns
-  for (int t = threadIdx.x; t < NC * CB / 16; t += 256) {
-    const int c = t / (CB / 16), ch = t % (CB / 16);
+  // ---- gather the input columns, 8 features (one 16-byte chunk per plane) per item
+  for (int t = threadIdx.x; t < NC * (Hd / 8); t += 256) {
+    const int c = t / (Hd / 8), ch = t % (Hd / 8);
     const int node = cols[c];
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (node >= 0) v = reinterpret_cast<const uint4*>(a.hin + ((size_t)k * a.M + node) * Hd)[ch];
-    *reinterpret_cast<uint4*>(Hs + c * CB + swz(16 * ch, c)) = v;
+    float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+    if (node >= 0) {
+      const float4* src = reinterpret_cast<const float4*>(a.hin + ((size_t)k * a.M + node) * Hd + 8 * ch);
+      v0 = src[0];
+      v1 = src[1];
+    }
+    uint4 p0, p1, p2;
+    split3_bf16x2(v0.x, v0.y, p0.x, p1.x, p2.x);
+    split3_bf16x2(v0.z, v0.w, p0.y, p1.y, p2.y);
+    split3_bf16x2(v1.x, v1.y, p0.z, p1.z, p2.z);
+    split3_bf16x2(v1.z, v1.w, p0.w, p1.w, p2.w);
+    const int off = c * CB + swz(16 * ch, c);
+    *reinterpret_cast<uint4*>(Hs + off) = p0;
+    *reinterpret_cast<uint4*>(Hs + PL + off) = p1;
+    *reinterpret_cast<uint4*>(Hs + 2 * PL + off) = p2;
   }
   __syncthreads();
-  // ---- edge GEMMs: Yb = W_b h, P = W_a h + Yb
+  // ---- edge GEMMs: Yb = W_b h, P = W_a h + Yb (smallest term first)
   floatx4_t ap[CT][MT], ay[CT][MT];
   {
 #pragma unroll
@@ -1168,12 +1185,17 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + col;
-        const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(Hs + c * CB + swz(64 * kb + 16 * grp, c));
+        const int off = c * CB + swz(64 * kb + 16 * grp, c);
+        bf16x8_t bfr[3];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          ay[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[m], bfr, ay[ct][m], 0, 0, 0);
-          ap[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[m], bfr, ap[ct][m], 0, 0, 0);
-        }
+        for (int pl = 0; pl < 3; ++pl) bfr[pl] = *reinterpret_cast<const bf16x8_t*>(Hs + pl * PL + off);
+#pragma unroll
+        for (int pl = 2; pl >= 0; --pl)
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            ay[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[m], bfr[pl], ay[ct][m], 0, 0, 0);
+            ap[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[m], bfr[pl], ap[ct][m], 0, 0, 0);
+          }
       }
     }
 #pragma unroll
@@ -1230,10 +1252,13 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int f0 = wave * RW + 16 * m + 4 * grp;
-      uint2 v;
-      v.x = pack_bf16x2(agg[m][0], agg[m][1]);
-      v.y = pack_bf16x2(agg[m][2], agg[m][3]);
-      *reinterpret_cast<uint2*>(Ag + c * CB + swz(2 * f0, c)) = v;
+      uint32_t h0, h1, h2, g0, g1, g2;
+      split3_bf16x2(agg[m][0], agg[m][1], h0, h1, h2);
+      split3_bf16x2(agg[m][2], agg[m][3], g0, g1, g2);
+      const int off = c * CB + swz(2 * f0, c);
+      *reinterpret_cast<uint2*>(Ag + off) = make_uint2(h0, g0);
+      *reinterpret_cast<uint2*>(Ag + PL + off) = make_uint2(h1, g1);
+      *reinterpret_cast<uint2*>(Ag + 2 * PL + off) = make_uint2(h2, g2);
     }
   }
   __syncthreads();
@@ -1256,13 +1281,20 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + col;
-        const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(Hs + c * CB + swz(64 * kb + 16 * grp, c));
-        const bf16x8_t bg = *reinterpret_cast<const bf16x8_t*>(Ag + c * CB + swz(64 * kb + 16 * grp, c));
+        const int off = c * CB + swz(64 * kb + 16 * grp, c);
+        bf16x8_t bh[3], bg[3];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], bh, acc[ct][m], 0, 0, 0);
-          acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m], bg, acc[ct][m], 0, 0, 0);
+        for (int pl = 0; pl < 3; ++pl) {
+          bh[pl] = *reinterpret_cast<const bf16x8_t*>(Hs + pl * PL + off);
+          bg[pl] = *reinterpret_cast<const bf16x8_t*>(Ag + pl * PL + off);
         }
+#pragma unroll
+        for (int pl = 2; pl >= 0; --pl)
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], bh[pl], acc[ct][m], 0, 0, 0);
+            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m], bg[pl], acc[ct][m], 0, 0, 0);
+          }
       }
     }
 #pragma unroll
@@ -1282,10 +1314,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
             hv[i] = on ? z : 0.f;
             nib |= (on ? 1u : 0u) << i;
           }
-          uint2 v;
-          v.x = pack_bf16x2(hv[0], hv[1]);
-          v.y = pack_bf16x2(hv[2], hv[3]);
-          *reinterpret_cast<uint2*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = v;
+          *reinterpret_cast<float4*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = make_float4(hv[0], hv[1], hv[2], hv[3]);
           qmask[(size_t)(a.fedge_cap + c) * NQ + f0 / 4] = (unsigned char)nib;
         }
       }
@@ -1867,8 +1896,12 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
       fmeta.push_back(0);
       ++g.n_ftiles;
     }
+    if (fwd_lds_bytes(Hd, g.fedge_cap) > 160 * 1024) {
+      p->last_error = "model_set_gnn: a forward column tile's edges exceed LDS";
+      gnn_free(p);
+      return GNMPC_UNSUPPORTED;
+    }
     UP(fcols, fcols) UP(fmeta, fmeta) UP(fecnt, fecnt) UP(fepre, fepre) UP(fesrc, fesrc) UP(feid, feid)
-    if ((s = dalloc(p, g.h16, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
     if ((s = dalloc(p, g.cnt, (size_t)L * NM * Hd)) != GNMPC_OK) return s;
   }
   UP(meta, tp.meta) UP(seed, tp.seed) UP(seedcol, tp.seedcol) UP(seedact, tp.seedact) UP(V, tp.V)
@@ -1914,7 +1947,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   phase_begin(p, GNMPC_PH_GNN_FORWARD, s);
   if (g.mfma) {
     const size_t NM = (size_t)N * M;
-    fwd_enc_bf16_kernel<<<N * M, Hd, 0, s>>>(fa, g.h16);
+    fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
     for (int l = 0; l < g.L; ++l) {
       FwdMfmaArgs f;
       f.N = N;
@@ -1922,8 +1955,8 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       f.E = g.E;
       f.l = l;
       f.fedge_cap = g.fedge_cap;
-      f.hin = g.h16 + (size_t)l * NM * Hd;
-      f.hout = g.h16 + (size_t)(l + 1) * NM * Hd;
+      f.hin = g.h + (size_t)l * NM * Hd;
+      f.hout = g.h + (size_t)(l + 1) * NM * Hd;
       const size_t wo = (size_t)l * Hd * Hd;
       f.Wa = g.Wa16 + wo;
       f.Wb = g.Wb16 + wo;
@@ -1940,7 +1973,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       f.fepre = g.fepre;
       f.fesrc = g.fesrc;
       f.feid = g.feid;
-      const size_t qbytes = (size_t)(g.fedge_cap + 16 * fwd_groups(Hd)) * (Hd / 4);
+      const size_t qbytes = fwd_lds_bytes(Hd, g.fedge_cap);
       dim3 fg(g.n_ftiles, N);
       {
         const void* ffn = Hd == 64 ? (const void*)fwd_mfma_layer_kernel<1>
@@ -1951,7 +1984,7 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
       else if (Hd == 128) fwd_mfma_layer_kernel<2><<<fg, 256, qbytes, s>>>(f);
       else fwd_mfma_layer_kernel<4><<<fg, 256, qbytes, s>>>(f);
     }
-    fwd_dec_bf16_kernel<<<ceil_div((long)N * M * 16, 256), 256, 0, s>>>(fa, g.h16 + (size_t)g.L * NM * Hd);
+    fwd_dec_coop_kernel<<<ceil_div((long)N * M * 16, 256), 256, 0, s>>>(fa, g.h + (size_t)g.L * NM * Hd);
   } else {
     fwd_enc_kernel<<<N * M, Hd, 0, s>>>(fa);
     const size_t lds_fwd = sizeof(float) * (size_t)(g.maxdeg + 2) * Hd;

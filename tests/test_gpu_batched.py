@@ -88,3 +88,62 @@ def test_batched_step_rejects_bad_descriptors():
     with pytest.raises(gn.GnmpcError):
         gn.step_batched([d])
     torch.cuda.synchronize()
+
+
+def test_batched_step_matches_oracle_on_serving_shapes():
+    """Four instances of the serving workload (uneven M, N up to 30, n_u up to
+    12; shared BF16 GNN Hd=128, L=2) in one batched step, each against the FP64
+    oracle: condensing of the device's own A, B, c (H - Rbar and g within
+    1e-5), the QP solution against the interior-point oracle (1e-4), and the
+    Jacobians of 8 nodes at 3 stages against the exact model by the BF16 gate."""
+    from oracle.condense import condense_local
+    from oracle.gnn import gnn_kink_margin, gnn_linearize
+    from oracle.qp import qp_ipm
+    from tests.gnn_gate import bf16_gate, delta_A
+    every = wl.batch_instances(52, seed=4)
+    probs = [every[i] for i in (23, 51, 24, 34)]   # (M, N, n_u) = (304, 30, 12), (117, 30, 12), (75, 20, 9), (212, 10, 6)
+    setups = [_setup(P) for P in probs]
+    gn.step_batched([gn.step_desc(plan, b) for plan, b in setups])
+    torch.cuda.synchronize()
+    f64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    for P, (plan, b) in zip(probs, setups):
+        A, B, c = (b[k].double().cpu().numpy() for k in ("A", "B", "c"))
+        H, g, u = (b[k].double().cpu().numpy() for k in ("H", "g", "u"))
+        prow, pcol = plan.graph_pattern()
+        cs = P.costs
+        ref = condense_local(A, B, c, prow, pcol, f64(P.x0), f64(cs.Q), f64(cs.q), f64(cs.R), f64(cs.r), wl.no_rows())
+        n = P.N * P.nu
+        Rb = np.zeros((n, n))
+        for k in range(P.N):
+            Rb[k * P.nu:(k + 1) * P.nu, k * P.nu:(k + 1) * P.nu] = f64(cs.R[k])
+        eh = np.linalg.norm((H - Rb) - (ref["H"] - Rb)) / np.linalg.norm(ref["H"] - Rb)
+        eg = np.linalg.norm(g - ref["g"]) / np.linalg.norm(ref["g"])
+        assert eh < 1e-5 and eg < 1e-5, (P.name, eh, eg)
+        uref, *_ = qp_ipm(ref["H"], ref["g"], P.lb, P.ub)
+        info = gn.qp_info(b["info"])
+        eu = np.linalg.norm(u - uref) / max(np.linalg.norm(uref), 1e-12)
+        print(P.name, (P.M, P.N, P.nu), "H", eh, "g", eg, "u", eu, "QP", info.status, info.iters)
+        assert info.status == gn.QP_SOLVED and eu < 1e-4, (P.name, info.status, eu)
+        Wr = P.gnn.rounded_bf16()
+        xh, uh = f64(P.xhat), f64(P.uhat)
+        stages = [0, P.N // 2, P.N - 1]
+        nodes = sorted({0, 1, int(P.act[0]), int(P.act[-1]), P.M // 3, P.M // 2, P.M - 2, P.M - 1})
+        _, _, Ar, Br, _, _ = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes)
+        margin = {}
+        for k in stages:
+            for i, m in zip(nodes, gnn_kink_margin(xh[k], uh[k], Wr, P.row_ptr, P.col, P.act, nodes=nodes)):
+                margin[(k, i)] = m
+        pairs = [(k, i) for k in stages for i in nodes]
+        bf16_gate(delta_A(A, prow, pcol), delta_A(Ar, prow, pcol), B, Br, prow, margin, pairs)
+
+
+def test_batched_step_rejects_a_repeated_plan():
+    """A plan's workspace serves one instance at a time: two descriptors of the
+    same plan are refused (INVALID_ARG) before anything is enqueued."""
+    P = wl.batch_instances(1, seed=6, M_range=(50, 60), N_range=(5, 6))[0]
+    plan, b = _setup(P)
+    d = gn.step_desc(plan, b)
+    with pytest.raises(gn.GnmpcError) as e:
+        gn.step_batched([d, d])
+    assert e.value.status == gn.INVALID_ARG
+    assert "two descriptors" in gn.lib().gnmpc_plan_last_error(plan._h).decode()

@@ -1,0 +1,152 @@
+"""End-to-end parity of one condensed MPC step (linearize -> condense -> QP,
+Algorithm 1's inner iteration) on the GPU, through the C-ABI, against the FP64
+oracle: the 1000-node BF16 step that bench.py times and the 100-node FP32 GNN
+step."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.condense import condense_local
+from oracle.gnn import gnn_forward, gnn_linearize
+from oracle.qp import qp_ipm
+from paper_2602_17601_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+gn = pytest.importorskip("paper_2602_17601_amd.gnmpc")
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _rbar(R, N, nu):
+    Rb = np.zeros((N * nu, N * nu))
+    for k in range(N):
+        Rb[k * nu:(k + 1) * nu, k * nu:(k + 1) * nu] = R[k]
+    return Rb
+
+
+def _gpu_step(P, gnn_dtype):
+    """The step exactly as bench.py runs it (tracking costs, the problem's rows,
+    box |u| <= 1, rows C x <= d passed as Ct u <= dt, default ADMM settings)."""
+    n, nr = P.N * P.nu, P.rows.n
+    plan = gn.Plan(P.M, P.nu, P.N, max(nr, 1), gn.F32)
+    plan.graph_set(P.row_ptr, P.col, P.gnn.L)
+    plan.model_set_gnn(P.gnn, P.act, dtype=gnn_dtype)
+    plan.rows_set(P.rows.node, P.rows.stage)
+    dev = "cuda"
+    A = torch.empty(P.N, plan.nnz, 6, 6, device=dev)
+    B = torch.empty(P.N, P.M, 6, P.nu, device=dev)
+    c = torch.empty(P.N, P.M, 6, device=dev)
+    f = torch.empty(P.N, P.M, 6, device=dev)
+    H = torch.empty(n, n, device=dev)
+    g = torch.empty(n, device=dev)
+    Ct = torch.empty(max(nr, 1), n, device=dev)
+    dt = torch.empty(max(nr, 1), device=dev)
+    Gx = torch.empty(P.N + 1, P.M, 6, device=dev)
+    u = torch.empty(n, device=dev)
+    info = torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device=dev)
+    cs = P.costs
+    plan.linearize(_t(P.xhat), _t(P.uhat), A, B, c, f)
+    plan.condense(A, B, c, _t(P.x0), _t(cs.Q), _t(cs.q), _t(cs.R), _t(cs.r),
+                  _t(P.rows.C) if nr else None, _t(P.rows.d) if nr else None, H, g,
+                  Ct if nr else None, dt if nr else None, Gx)
+    plan.solve_box_qp(H, g, _t(P.lb), _t(P.ub), Ct if nr else None, None, dt if nr else None, u, info,
+                      settings=gn.default_admm_settings())
+    torch.cuda.synchronize()
+    out = dict(A=_np(A), B=_np(B), c=_np(c), f=_np(f), H=_np(H), g=_np(g), Ct=_np(Ct)[:nr], dt=_np(dt)[:nr],
+               Gx=_np(Gx), u=_np(u), info=gn.qp_info(info))
+    return plan, out
+
+
+def _condense_on_device_blocks(P, plan, out):
+    """The oracle's per-node recursion on the device's own A, B, c (promoted to
+    FP64), with the same FP32-rounded costs and rows."""
+    prow, pcol = plan.graph_pattern()
+    cs = P.costs
+    rows = wl.StateRows(P.rows.node, P.rows.stage, _f32(P.rows.C), _f32(P.rows.d))
+    return condense_local(out["A"], out["B"], out["c"], prow, pcol, _f32(P.x0), _f32(cs.Q), _f32(cs.q),
+                          _f32(cs.R), _f32(cs.r), rows)
+
+
+def test_step_chain1000_bf16_matches_oracle():
+    """The benchmarked step: 1000-node 1-2-hop chain, GNN Hd=128 L=3 with BF16
+    weights, n_u=12, N=20, 200 obstacle rows, FP32 condensing, ADMM QP.
+      (i) condensing of the device's own A, B, c against the oracle's per-node
+          recursion: H - Rbar, g, Ct, dt, Gx within 1e-5 (this reaches the
+          one-stage propagation with 4 column slices of the 13-wide pattern);
+      (ii) the QP solution against the interior-point oracle on that H, g, Ct,
+          dt within 1e-4;
+      (iii) the device's offsets c and next states against the exact FP64 GNN
+          (BF16-rounded weights) on every node of stages 0, 9 and 19: the next
+          state increments within 2e-2, and the offsets' error within 2e-2 of
+          the increments (c is the offset of a next state; for this bias-free,
+          positively homogeneous network its exact value is zero)."""
+    P = wl.gnn1000_bf16()
+    plan, out = _gpu_step(P, gn.BF16)
+    assert all(np.all(np.isfinite(out[k])) for k in ("A", "B", "c", "H", "g", "Ct", "dt", "u"))
+    ref = _condense_on_device_blocks(P, plan, out)
+    Rb = _rbar(_f32(P.costs.R), P.N, P.nu)
+    errs = dict(H=_rel(out["H"] - Rb, ref["H"] - Rb), g=_rel(out["g"], ref["g"]), Ct=_rel(out["Ct"], ref["Ct"]),
+                dt=_rel(out["dt"], ref["dt"]), Gx=_rel(out["Gx"], ref["Gx"]))
+    print("condensing on the device's blocks:", errs)
+    assert all(e < 1e-5 for e in errs.values()), errs
+    uref, *_ = qp_ipm(ref["H"], ref["g"], P.lb, P.ub, ref["Ct"], np.full(P.rows.n, -np.inf), ref["dt"])
+    info = out["info"]
+    eu = np.linalg.norm(out["u"] - uref) / max(np.linalg.norm(uref), 1e-12)
+    print("QP:", info.status, info.iters, "rel u", eu, "active box", int(np.sum(np.abs(uref) > 1 - 1e-6)))
+    assert info.status == gn.QP_SOLVED and eu < 1e-4
+    # (iii) offsets and next states against the exact model
+    Wr = P.gnn.rounded_bf16()
+    xh, uh = _f32(P.xhat), _f32(P.uhat)
+    stages = [0, 9, 19]
+    _, _, _, _, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, stages=stages)
+    for k in stages:
+        inc_ref = fr[k] - xh[k]
+        fe = gnn_forward(xh[k], uh[k], Wr, P.row_ptr, P.col, P.act)
+        np.testing.assert_allclose(fe, fr[k], rtol=0, atol=1e-15)
+        e_inc = _rel(out["f"][k] - xh[k], inc_ref)
+        e_c = np.linalg.norm(out["c"][k] - cr[k]) / np.linalg.norm(inc_ref)
+        print("stage", k, "increment", e_inc, "offset", e_c)
+        assert e_inc < 2e-2 and e_c < 2e-2, (k, e_inc, e_c)
+
+
+def test_step_chain100_fp32_matches_oracle():
+    """100-node 1-2-hop chain, GNN Hd=64 L=2 in FP32, n_u=6, N=20, no state rows:
+      (i) condensing of the device's own A, B, c: H - Rbar, g, Gx within 1e-5;
+      (ii) end to end against the oracle's own pipeline (per-node forward-mode
+           Jacobians, per-node condensing recursion): H - Rbar and g within 1e-5;
+      (iii) the QP solution against the interior-point oracle within 1e-4."""
+    P = wl.gnn100_fp32()
+    plan, out = _gpu_step(P, gn.F32)
+    ref = _condense_on_device_blocks(P, plan, out)
+    Rb = _rbar(_f32(P.costs.R), P.N, P.nu)
+    e1 = dict(H=_rel(out["H"] - Rb, ref["H"] - Rb), g=_rel(out["g"], ref["g"]), Gx=_rel(out["Gx"], ref["Gx"]))
+    print("condensing on the device's blocks:", e1)
+    assert all(e < 1e-5 for e in e1.values()), e1
+    xh, uh = _f32(P.xhat), _f32(P.uhat)
+    prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, P.gnn, P.row_ptr, P.col, P.act)
+    cs = P.costs
+    full = condense_local(Ar, Br, cr, prow, pcol, _f32(P.x0), _f32(cs.Q), _f32(cs.q), _f32(cs.R), _f32(cs.r),
+                          wl.no_rows())
+    e2 = dict(H=_rel(out["H"] - Rb, full["H"] - Rb), g=_rel(out["g"], full["g"]))
+    print("end to end:", e2)
+    assert all(e < 1e-5 for e in e2.values()), e2
+    uref, *_ = qp_ipm(full["H"], full["g"], P.lb, P.ub)
+    eu = np.linalg.norm(out["u"] - uref) / max(np.linalg.norm(uref), 1e-12)
+    print("QP:", out["info"].status, out["info"].iters, "rel u", eu)
+    assert out["info"].status == gn.QP_SOLVED and eu < 1e-4

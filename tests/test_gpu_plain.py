@@ -136,6 +136,7 @@ def _random_blocks(rng, M, hops, L, N, nu, spread=0.6):
     (50, 1, 1, 9, 4, 5, True, torch.float64),       # two-stage recursion launches, odd N (last stage alone)
     (1, 1, 1, 4, 3, 2, True, torch.float64),        # a single node (textbook dense condensing)
     (20, 2, 1, 1, 6, 3, False, torch.float64),      # horizon one
+    (60, 2, 3, 12, 12, 9, False, torch.float32),    # 13-wide pattern: one-stage launches, up to 3 column slices
 ])
 def test_condense_random_instances_match_oracle(M, hops, L, N, nu, n_c, full_Q, dtype):
     rng = np.random.default_rng(M * 100 + N)
@@ -281,3 +282,51 @@ def test_qp_maxiter_is_soft():
                          check_every=1)
     assert info.status == gn.QP_MAXITER
     assert np.all(np.isfinite(u))
+
+
+def test_qp_fp64_pass_with_the_factor_in_global_memory():
+    """n = 240 with 200 rows and kappa(K) above 1e7: the FP64 pass takes over,
+    and its packed factor (about 245 KB) does not fit one workgroup's LDS, so it
+    lives in global memory.  Against the interior-point oracle within 1e-4."""
+    rng = np.random.default_rng(11)
+    n, nc = 240, 200
+    Qm, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    H = Qm @ np.diag(np.geomspace(1e-2, 1e8, n)) @ Qm.T
+    g = rng.normal(0, 3.0, size=n) * np.sqrt(np.geomspace(1e-2, 1e8, n))
+    lb, ub = -np.ones(n), np.ones(n)
+    Ct = rng.normal(size=(nc, n)) / np.sqrt(n)
+    uc = rng.uniform(-0.3, 0.3, size=nc)
+    lc = np.full(nc, -np.inf)
+    H, g, Ct, uc = (_cast(v, torch.float32) for v in (H, g, Ct, uc))
+    H = 0.5 * (H + H.T)
+    ref, *_ = qp_ipm(H, g, lb, ub, Ct, lc, uc)
+    plan = gn.Plan(1, n, 1, nc, gn.F32)
+    u, info = _solve_gpu(plan, H, g, lb, ub, Ct, lc, uc, torch.float32, eps_abs=1e-9, eps_rel=1e-9,
+                         max_iter=40000)
+    print("kappa", info.kappa_est, "iters", info.iters, "status", info.status, "rel", _qp_rel(u, ref))
+    assert info.used_fp64 == 1 and info.kappa_est > 1e7
+    assert info.status == gn.QP_SOLVED, (info.status, info.iters)
+    assert _qp_rel(u, ref) < 1e-4
+
+
+def test_qp_fp32_n360_factor_in_global_memory():
+    """n = 360 (the largest condensed QP of the serving workload, N = 30 and
+    n_u = 12): the FP32 packed factor (about 282 KB) lives in global memory.
+    Against the interior-point oracle within 1e-4."""
+    rng = np.random.default_rng(12)
+    n, nc = 360, 60
+    Qm, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    H = Qm @ np.diag(np.geomspace(0.1, 10.0, n)) @ Qm.T
+    g = rng.normal(0, 3.0, size=n)
+    lb, ub = -np.ones(n), np.ones(n)
+    Ct = rng.normal(size=(nc, n)) / np.sqrt(n)
+    lc = np.full(nc, -np.inf)
+    uc = rng.uniform(-0.3, 0.3, size=nc)
+    H, g, Ct, uc = (_cast(v, torch.float32) for v in (H, g, Ct, uc))
+    H = 0.5 * (H + H.T)
+    ref, *_ = qp_ipm(H, g, lb, ub, Ct, lc, uc)
+    plan = gn.Plan(1, n, 1, nc, gn.F32)
+    u, info = _solve_gpu(plan, H, g, lb, ub, Ct, lc, uc, torch.float32)
+    print("iters", info.iters, "status", info.status, "rel", _qp_rel(u, ref))
+    assert info.status == gn.QP_SOLVED and info.used_fp64 == 0
+    assert _qp_rel(u, ref) < 1e-4

@@ -138,19 +138,53 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
 
 
-def test_bf16_mask_mode_leaves_tangents_exact():
-    """In 'bf16' mode only the values (hence the ReLU decisions) see rounded
-    operands.  With identity activations there are no decisions, so the
-    Jacobian must be bitwise the exact one; with ReLU the next state moves by
-    no more than bfloat16 rounding allows."""
-    from oracle.gnn import _round
-    rp, col, act, W, x, u = _small(M=9, L=2)
-    e = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity")
-    b = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity", rounding="bf16")
-    assert np.array_equal(e[2], b[2]) and np.array_equal(e[3], b[3])
-    fe = gnn_forward(x, u, W, rp, col, act)
-    fb = gnn_forward(x, u, W, rp, col, act, rounding="bf16")
-    inc_e, inc_b = (fe - x) / W.dt, (fb - x) / W.dt
-    assert 0 < np.linalg.norm(inc_b - inc_e) / np.linalg.norm(inc_e) < 3e-2
-    assert _round(np.array([1.00390625]), "bf16")[0] == 1.0
-    assert _round(np.array([1.005859375]), "bf16")[0] == 1.0078125
+def _encoder_pre(x, u, W, act, j):
+    """Encoder pre-activation of node j (the test builds its input from the model's definition)."""
+    from oracle.gnn import node_input
+    return W.W_enc @ node_input(x, u, j, act) + W.b_enc
+
+
+@pytest.mark.parametrize("j,L", [(0, 2), (6, 2), (4, 3)])
+def test_kink_margin_finds_a_zero_encoder_preactivation_in_exactly_the_downstream_fields(j, L):
+    """Shift one encoder bias so that node j's pre-activation of feature 3 is
+    zero: the margin must vanish for exactly the nodes whose L-hop receptive
+    field contains j, and stay clear of zero elsewhere."""
+    from oracle.gnn import gnn_kink_margin
+    rp, col, act, W, x, u = _small(M=11, hops=1, Hd=12, L=L, seed=21)
+    W.b_enc = W.b_enc.copy()
+    W.b_enc[3] -= _encoder_pre(x, u, W, act, j)[3]
+    mg = gnn_kink_margin(x, u, W, rp, col, act)
+    for i in range(11):
+        if j in ball(rp, col, i, L):
+            assert mg[i] < 1e-14, (i, mg[i])
+        else:
+            assert mg[i] > 1e-6, (i, mg[i])
+
+
+def test_kink_margin_finds_a_zero_edge_preactivation_of_the_first_round():
+    """Zero the round-0 pre-activation of edge (r <- s): with L = 2 it is in
+    the field of every node within one hop downstream of r, and no other."""
+    from oracle.gnn import gnn_kink_margin
+    rp, col, act, W, x, u = _small(M=10, hops=2, Hd=8, L=2, seed=4)
+    M, r, s, f = 10, 5, 3, 2
+    h = np.stack([np.maximum(_encoder_pre(x, u, W, act, n), 0) for n in range(M)])
+    ze = W.W_edge[0] @ np.concatenate([h[r], h[r] - h[s]]) + W.b_edge[0]
+    W.b_edge = [b.copy() for b in W.b_edge]
+    W.b_edge[0][f] -= ze[f]
+    mg = gnn_kink_margin(x, u, W, rp, col, act)
+    for i in range(M):
+        if r in ball(rp, col, i, 1):
+            assert mg[i] < 1e-14, (i, mg[i])
+        else:
+            assert mg[i] > 1e-6, (i, mg[i])
+
+
+def test_kink_margin_is_scale_invariant_without_biases():
+    """With zero biases the model is positively homogeneous: scaling x and u by
+    a > 0 scales every pre-activation and every term by a, so no margin moves."""
+    from oracle.gnn import gnn_kink_margin
+    rp, col, act, W, x, u = _small(M=9, L=2, seed=7)
+    m1 = gnn_kink_margin(x, u, W, rp, col, act)
+    m2 = gnn_kink_margin(3.5 * x, 3.5 * u, W, rp, col, act)
+    np.testing.assert_allclose(m1, m2, rtol=1e-12)
+    assert np.all(m1 > 0) and np.all(np.isfinite(m1))
