@@ -8,7 +8,7 @@
 // with the OSQP stopping rule, its primal-infeasibility certificate and its
 // rho adaptation (refactorization when the residual balance is off by > 5x).
 //
-// One workgroup of 1024 lanes solves one instance.  K is factored once per
+// One workgroup of 512 lanes (8 waves) solves one instance.  K is factored once per
 // rho (right-looking Cholesky on the packed lower triangle, held in LDS when it
 // fits) and L is inverted in place, so each iteration costs two packed
 // triangular mat-vecs (W = L^{-1}: x~ = W'(W rhs)) plus one pass over Ct that
@@ -71,6 +71,17 @@ __device__ inline T wave_max(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Order this wave's memory accesses across lanes: a value one lane stores to
+// the factor storage (LDS, or global memory when the factor does not fit LDS)
+// is read by other lanes of the same wave after this point.  The hardware
+// performs a wave's memory operations in order; the wavefront-scope fence
+// keeps the compiler from moving loads or stores across the point.
+__device__ __attribute__((always_inline)) inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Shared block-wide reductions through a small LDS array.
@@ -444,7 +455,7 @@ __device__ __attribute__((always_inline)) bool diag_factor_invert(T* Dg, T* tmp)
 #pragma unroll
     for (int c = 0; c < 16; ++c) tmp[lane * 16 + c] = c <= lane ? a[c] : T(0);
   }
-  __builtin_amdgcn_wave_barrier();
+  wave_sync();
   T col[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -457,7 +468,7 @@ __device__ __attribute__((always_inline)) bool diag_factor_invert(T* Dg, T* tmp)
 #pragma unroll
     for (int r = 0; r < 16; ++r) Dg[r * 16 + lane] = col[r];
   }
-  __builtin_amdgcn_wave_barrier();
+  wave_sync();
   return ok;
 }
 
@@ -512,7 +523,7 @@ __device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, i
         T acc[4] = {T(0), T(0), T(0), T(0)};
         T* B = w.mat + bo(I, J - 1);
         bmma<false>(acc, B, Dp);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         bstore(B, acc, T(-1));
       }
     }
@@ -525,12 +536,12 @@ __device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, i
       if (t < m) {
         T* B = w.mat + bo(J + 1 + t, J);
         bmma<true>(acc, B, D);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         bstore(B, acc, T(1));
       } else {
         T* B = w.mat + bo(J, t - m);
         bmma<false>(acc, D, B);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         bstore(B, acc, T(1));
       }
     }
@@ -564,7 +575,7 @@ __device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, i
       T acc[4] = {T(0), T(0), T(0), T(0)};
       bmma_rt(acc, A, B, tr);
       bsub(C, acc);
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
       const bool ok = diag_factor_invert(w.mat + bo(J + 1, J + 1), w.part);
       if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
     } else {

@@ -212,13 +212,16 @@ def random_rows(rng, M: int, N: int, n_c: int):
     return StateRows(node, stage, C, d)
 
 
-def sphere_obstacle_rows(rng, M: int, N: int, xhat, radius: float = 0.1,
-                         clearance: float = 0.15, n_nodes: int = 10):
+def sphere_obstacle_rows(rng, M: int, N: int, xhat, act, radius: float = 0.1,
+                         clearance: float = 0.15, n_nodes: int = 10, spread: int = 8):
     """Node-position half-spaces keeping nodes outside a sphere obstacle.
 
     Rest positions hang along -z: r^i = (0, 0, -i/M).  The sphere (radius
-    ``radius``) sits beside a seeded node c in [0.4M, 0.6M) at distance
-    ``clearance`` along a seeded horizontal unit vector.  For each of the
+    ``radius``) sits beside a seeded node c at distance ``clearance`` along a
+    seeded horizontal unit vector; c is drawn within ``spread`` nodes of the
+    actuated node nearest the middle of the chain, so that the inputs reach
+    the constrained nodes within the horizon (a row no input reaches has
+    C S_k = 0 and only restates a fact about the free response).  For each of the
     ``n_nodes`` nodes nearest the centre and each stage k = 1..N, the row
     linearizes "outside the sphere" around the nominal position:
     n = unit(r^i + p_hat^i_k - centre), C = [-n^T, 0], d = n^T (r^i - centre) - radius,
@@ -226,7 +229,8 @@ def sphere_obstacle_rows(rng, M: int, N: int, xhat, radius: float = 0.1,
     """
     rest = np.zeros((M, 3))
     rest[:, 2] = -np.arange(M) / M
-    c = int(rng.integers(int(0.4 * M), int(0.6 * M)))
+    a_mid = int(np.asarray(act)[np.argmin(np.abs(np.asarray(act) - (M - 1) / 2))])
+    c = min(M - 1, max(0, a_mid + int(rng.integers(-spread, spread + 1))))
     ang = rng.uniform(0, 2 * math.pi)
     w = np.array([math.cos(ang), math.sin(ang), 0.0])
     centre = rest[c] + clearance * w
@@ -303,7 +307,7 @@ def make_problem(name: str, *, M: int, hops: int, N: int, n_act: int, model: str
     x0 = initial_state(rng, M, x0_sigma)
     xhat, uhat = nominal_trajectory(rng, x0, N, nu, walk)
     if obstacle:
-        rows = sphere_obstacle_rows(rng, M, N, xhat)
+        rows = sphere_obstacle_rows(rng, M, N, xhat, act)
     elif n_random_rows:
         rows = random_rows(rng, M, N, n_random_rows)
     else:

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from paper_2602_17601_amd import workloads as wl
+from tests.tolerance import U32, h_err
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +117,7 @@ def test_batched_step_matches_oracle_on_serving_shapes():
         Rb = np.zeros((n, n))
         for k in range(P.N):
             Rb[k * P.nu:(k + 1) * P.nu, k * P.nu:(k + 1) * P.nu] = f64(cs.R[k])
-        eh = np.linalg.norm((H - Rb) - (ref["H"] - Rb)) / np.linalg.norm(ref["H"] - Rb)
+        eh = h_err(H, ref["H"], Rb, U32)
         eg = np.linalg.norm(g - ref["g"]) / np.linalg.norm(ref["g"])
         assert eh < 1e-5 and eg < 1e-5, (P.name, eh, eg)
         uref, *_ = qp_ipm(ref["H"], ref["g"], P.lb, P.ub)

@@ -9,6 +9,7 @@ from oracle.graph import jacobian_pattern
 from oracle.msd import msd_linearize
 from oracle.qp import qp_ipm
 from paper_2602_17601_amd import workloads as wl
+from tests.tolerance import U32, U64, h_err
 
 pytestmark = pytest.mark.gpu
 
@@ -110,7 +111,7 @@ def test_condense_fp64_chain10_matches_oracle():
     plan = _plan_msd(P, gn.F64)
     prow, pcol, A, B, c = msd_linearize(P.xhat, P.uhat, P.row_ptr, P.col, P.act, P.msd)
     out, ref, Rb = _condense_both(plan, torch.float64, A, B, c, P.x0, P.costs, P.rows, prow, pcol)
-    assert _rel(out["H"] - Rb, ref["H"] - Rb) < 1e-12
+    assert h_err(out["H"], ref["H"], Rb, U64) < 1e-12
     assert _rel(out["g"], ref["g"]) < 1e-12
     assert _rel(out["Gx"], ref["Gx"]) < 1e-13
     assert np.array_equal(out["H"], out["H"].T)
@@ -150,7 +151,7 @@ def test_condense_random_instances_match_oracle(M, hops, L, N, nu, n_c, full_Q, 
     plan.rows_set(rows.node, rows.stage)
     out, ref, Rb = _condense_both(plan, dtype, A, B, c, x0, cost, rows, prow, pcol)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
-    assert _rel(out["H"] - Rb, ref["H"] - Rb) < tol
+    assert h_err(out["H"], ref["H"], Rb, U64 if dtype == torch.float64 else U32) < tol
     assert _rel(out["g"], ref["g"]) < tol
     if n_c:
         assert _rel(out["Ct"], ref["Ct"]) < tol
@@ -165,7 +166,7 @@ def test_condense_paper_scale_plain_fp32_and_bitwise_repeatable():
     prow, pcol, A, B, c = msd_linearize(P.xhat, P.uhat, P.row_ptr, P.col, P.act, P.msd)
     cost = wl.random_costs(np.random.default_rng(99), P.M, P.N, P.nu)
     out, ref, Rb = _condense_both(plan, torch.float32, A, B, c, P.x0, cost, P.rows, prow, pcol)
-    assert _rel(out["H"] - Rb, ref["H"] - Rb) < 1e-5
+    assert h_err(out["H"], ref["H"], Rb, U32) < 1e-5
     assert _rel(out["g"], ref["g"]) < 1e-5
     assert _rel(out["Ct"], ref["Ct"]) < 1e-5
     assert _rel(out["dt"], ref["dt"]) < 1e-5
@@ -287,18 +288,30 @@ def test_qp_maxiter_is_soft():
 def test_qp_fp64_pass_with_the_factor_in_global_memory():
     """n = 240 with 200 rows and kappa(K) above 1e7: the FP64 pass takes over,
     and its packed factor (about 245 KB) does not fit one workgroup's LDS, so it
-    lives in global memory.  Against the interior-point oracle within 1e-4."""
+    lives in global memory.  Against the interior-point oracle within 1e-4.
+
+    H has eigenvalues 1e-2 .. 1e8, mixed only inside 4x4 diagonal blocks (then
+    symmetrically permuted): each entry is then of the size of its block's
+    eigenvalues, so rounding H to FP32 keeps it positive definite (a dense
+    rotation would not: the FP32 rounding of entries of size 1e8 / n moves
+    the smallest eigenvalues by more than 1e-2)."""
     rng = np.random.default_rng(11)
     n, nc = 240, 200
-    Qm, _ = np.linalg.qr(rng.normal(size=(n, n)))
-    H = Qm @ np.diag(np.geomspace(1e-2, 1e8, n)) @ Qm.T
-    g = rng.normal(0, 3.0, size=n) * np.sqrt(np.geomspace(1e-2, 1e8, n))
+    lam = np.geomspace(1e-2, 1e8, n)
+    H = np.zeros((n, n))
+    for b in range(0, n, 4):
+        Qb, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+        H[b:b + 4, b:b + 4] = Qb @ np.diag(lam[b:b + 4]) @ Qb.T
+    perm = rng.permutation(n)
+    H = H[np.ix_(perm, perm)]
+    g = rng.normal(0, 3.0, size=n) * np.sqrt(lam[np.argsort(perm)])
     lb, ub = -np.ones(n), np.ones(n)
     Ct = rng.normal(size=(nc, n)) / np.sqrt(n)
     uc = rng.uniform(-0.3, 0.3, size=nc)
     lc = np.full(nc, -np.inf)
     H, g, Ct, uc = (_cast(v, torch.float32) for v in (H, g, Ct, uc))
     H = 0.5 * (H + H.T)
+    assert np.linalg.eigvalsh(H).min() > 0.9e-2      # the FP32-rounded H is still positive definite
     ref, *_ = qp_ipm(H, g, lb, ub, Ct, lc, uc)
     plan = gn.Plan(1, n, 1, nc, gn.F32)
     u, info = _solve_gpu(plan, H, g, lb, ub, Ct, lc, uc, torch.float32, eps_abs=1e-9, eps_rel=1e-9,
