@@ -243,6 +243,29 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* plan, int32_t n, const void* H, cons
                                 const void* lc, const void* uc, const gnmpc_admm_settings* settings,
                                 void* u, gnmpc_qp_info* info, void* stream);
 
+/* Allocation-free variant of gnmpc_solve_box_qp, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It takes no plan: dtype is GNMPC_F32 or
+ * GNMPC_F64 (the type of every array), and the arguments, layouts, settings,
+ * FP64 fallback and results are those of gnmpc_solve_box_qp (same kernels, so
+ * the same bits).  The solver's workspace is a fixed 4 MiB array in device
+ * memory, one per GPU, held by the library until the process ends: n may be
+ * at most 464 (any n_c the LDS of one workgroup admits).  It runs on the
+ * current device, which must own `stream`; the call enqueues a small kernel
+ * that clears the solver's flags, then the solve, and never allocates or
+ * frees memory.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (different streams, threads or processes sharing
+ * the device's memory) race and give wrong results: serialize them, e.g. on
+ * one stream.  Errors: GNMPC_INVALID_ARG (dtype, null arrays, settings),
+ * GNMPC_SHAPE (n outside 1..464 or n_c < 0), GNMPC_UNSUPPORTED (the vectors
+ * do not fit one workgroup's LDS), GNMPC_HIP_ERROR (symbol lookup or launch);
+ * all checked on the host before anything is enqueued. */
+gnmpc_status gnmpc_solve_box_qp_noalloc(int32_t dtype, int32_t n, const void* H, const void* g,
+                                        const void* lb, const void* ub, int32_t n_c, const void* Ct,
+                                        const void* lc, const void* uc,
+                                        const gnmpc_admm_settings* settings, void* u,
+                                        gnmpc_qp_info* info, void* stream);
+
 /* ---------------- batched steps ---------------- */
 
 /* The device arrays of one instance's condensed MPC step: the arguments of

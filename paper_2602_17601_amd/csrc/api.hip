@@ -420,6 +420,19 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const v
   return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
 }
 
+gnmpc_status gnmpc_solve_box_qp_noalloc(int32_t dtype, int32_t n, const void* H, const void* g, const void* lb,
+                                        const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc,
+                                        const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, void* stream) {
+  if (dtype != GNMPC_F32 && dtype != GNMPC_F64) return GNMPC_INVALID_ARG;
+  if (!H || !g || !lb || !ub || !u || !st) return GNMPC_INVALID_ARG;
+  if (n_c > 0 && !Ct) return GNMPC_INVALID_ARG;
+  if (const gnmpc_status cs = qp_noalloc_check(dtype, n, n_c); cs != GNMPC_OK) return cs;
+  if (!(st->rho > 0) || !(st->sigma > 0) || !(st->alpha > 0 && st->alpha < 2) || !(st->eps_abs >= 0) ||
+      !(st->eps_rel >= 0) || st->max_iter < 1 || st->check_every < 1 || !(st->kappa_fp64 > 0))
+    return GNMPC_INVALID_ARG;
+  return launch_qp_noalloc(dtype, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
+}
+
 gnmpc_status gnmpc_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
                        void* stream) {
   if (!p) return GNMPC_INVALID_ARG;

@@ -122,6 +122,12 @@ void prop_blocks_free(gnmpc_plan* p);
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
                        int n_c, const void* Ct, const void* lc, const void* uc,
                        const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
+// Allocation-free QP (workspace in a static device array; see qp_admm.hip).
+constexpr int kQpNoallocMaxN = 464;
+gnmpc_status qp_noalloc_check(int dtype, int n, int n_c);
+gnmpc_status launch_qp_noalloc(int dtype, int n, const void* H, const void* g, const void* lb, const void* ub,
+                               int n_c, const void* Ct, const void* lc, const void* uc,
+                               const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
 // tangent.hip
 gnmpc_status launch_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
                         hipStream_t s);

@@ -19,6 +19,8 @@
 // right behind it) redoes factorization and iterations in FP64.
 #include <math.h>
 
+#include <mutex>
+
 #include "plan.hpp"
 
 namespace gnmpc {
@@ -1212,19 +1214,29 @@ gnmpc_status launch_pass(gnmpc_plan* p, const QpArgs<Tin>& a, int mode, hipStrea
   bool in_lds = lds_bytes(a.n, a.n_c, sizeof(T), true) <= kLdsCap;
   size_t lds = lds_bytes(a.n, a.n_c, sizeof(T), in_lds);
   if (lds > kLdsCap) {
-    p->last_error = "QP too large for one workgroup's LDS";
+    if (p) p->last_error = "QP too large for one workgroup's LDS";
     return GNMPC_UNSUPPORTED;
   }
-  GNMPC_HIP_TRY(p, set_max_lds((const void*)qp_solve_kernel<T, Tin>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (set_max_lds((const void*)qp_solve_kernel<T, Tin>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess) {
+    if (p) p->last_error = "QP: could not raise the LDS limit of the solve kernel";
+    return GNMPC_HIP_ERROR;
+  }
   qp_solve_kernel<T, Tin><<<1, kQpThreads, lds, s>>>(a, mode, in_lds ? 1 : 0);
   return GNMPC_OK;
 }
 
+__global__ void qp_flag_clear_kernel(int32_t* flag) {
+  if (threadIdx.x < 2) flag[threadIdx.x] = 0;
+}
+
+// One QP solve with its workspace at `ws` (qp_workspace_bytes(n, n_c) bytes,
+// 256-byte aligned) and its two flags at `flag`; p (may be null) receives the
+// error text and the phase timer records.
 template <typename Tin>
-gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
-                 const void* Ct, const void* lc, const void* uc, const gnmpc_admm_settings* st, void* u,
-                 gnmpc_qp_info* info, hipStream_t s) {
+gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const void* H, const void* g,
+                 const void* lb, const void* ub, int n_c, const void* Ct, const void* lc, const void* uc,
+                 const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s) {
   QpArgs<Tin> a;
   a.n = n;
   a.n_c = n_c;
@@ -1237,13 +1249,12 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.uc = (const Tin*)uc;
   a.u = (Tin*)u;
   a.info = info;
-  unsigned char* ws = (unsigned char*)p->d_qp;
   const size_t nbo = bo(nblocks(n), 0);
   a.G = (const double*)ws;
   a.gmat = (double*)(ws + (sizeof(double) * (size_t)n * n + 255) / 256 * 256);  // 256-byte aligned
   a.Kp = a.gmat + nbo;
   a.Kf = reinterpret_cast<float*>(a.Kp + nbo);
-  a.flag = p->d_qp_flag;
+  a.flag = flag;
   a.rho = st->rho;
   a.sigma = st->sigma;
   a.alpha = st->alpha;
@@ -1252,7 +1263,7 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
   a.kappa_fp64 = st->kappa_fp64;
   a.max_iter = st->max_iter;
   a.check_every = st->check_every;
-  phase_begin(p, GNMPC_PH_QP, s);
+  if (p) phase_begin(p, GNMPC_PH_QP, s);
   qp_prep_kernel<Tin><<<(int)(nbo / 256), 256, 0, s>>>(a, (double*)ws);
   gnmpc_status rc;
   if (sizeof(Tin) == 8) {
@@ -1261,11 +1272,27 @@ gnmpc_status run(gnmpc_plan* p, int n, const void* H, const void* g, const void*
     rc = launch_pass<float, Tin>(p, a, 0, s);
     if (rc == GNMPC_OK) rc = launch_pass<double, Tin>(p, a, 1, s);
   }
-  phase_end(p, GNMPC_PH_QP, s);
+  if (p) phase_end(p, GNMPC_PH_QP, s);
   if (rc != GNMPC_OK) return rc;
-  GNMPC_HIP_TRY(p, hipGetLastError());
+  if (hipGetLastError() != hipSuccess) {
+    if (p) p->last_error = "QP: kernel launch failed";
+    return GNMPC_HIP_ERROR;
+  }
   return GNMPC_OK;
 }
+
+// Workspace of the allocation-free entry: a file-scope device array (one copy
+// per GPU, held until the process ends).  Host code never passes the array's
+// name to a kernel: it takes the array's device address on each GPU once, by
+// hipGetSymbolAddress, and uses that address.  Layout: 256 bytes of flags, then
+// the QP workspace.
+constexpr size_t kQpScratchBytes = (size_t)4 << 20;
+constexpr size_t kQpScratchFlagBytes = 256;
+static __device__ __align__(256) unsigned char scratch[kQpScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char* scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -1278,8 +1305,42 @@ size_t qp_workspace_bytes(int n, int n_c) {
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,
                        const void* Ct, const void* lc, const void* uc, const gnmpc_admm_settings* st, void* u,
                        gnmpc_qp_info* info, hipStream_t s) {
-  if (p->dims.dtype == GNMPC_F64) return run<double>(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
-  return run<float>(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
+  unsigned char* ws = (unsigned char*)p->d_qp;
+  if (p->dims.dtype == GNMPC_F64)
+    return run<double>(p, ws, p->d_qp_flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
+  return run<float>(p, ws, p->d_qp_flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
+}
+
+gnmpc_status qp_noalloc_check(int dtype, int n, int n_c) {
+  if (n < 1 || n > kQpNoallocMaxN || n_c < 0 || kQpScratchFlagBytes + qp_workspace_bytes(n, n_c) > kQpScratchBytes)
+    return GNMPC_SHAPE;
+  // the FP64 pass (which an FP32 solve may hand over to) needs the larger LDS
+  (void)dtype;
+  if (lds_bytes(n, n_c, sizeof(double), false) > kLdsCap) return GNMPC_UNSUPPORTED;
+  return GNMPC_OK;
+}
+
+gnmpc_status launch_qp_noalloc(int dtype, int n, const void* H, const void* g, const void* lb, const void* ub,
+                               int n_c, const void* Ct, const void* lc, const void* uc,
+                               const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GNMPC_HIP_ERROR;
+  unsigned char* base;
+  {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GNMPC_HIP_ERROR;
+      scratch_ptr[dev] = (unsigned char*)ptr;
+    }
+    base = scratch_ptr[dev];
+  }
+  int32_t* flag = reinterpret_cast<int32_t*>(base);
+  unsigned char* ws = base + kQpScratchFlagBytes;
+  // the flags must start at zero: the array keeps whatever the last call on this GPU left
+  qp_flag_clear_kernel<<<1, 64, 0, s>>>(flag);
+  if (dtype == GNMPC_F64) return run<double>(nullptr, ws, flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
+  return run<float>(nullptr, ws, flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, s);
 }
 
 }  // namespace gnmpc

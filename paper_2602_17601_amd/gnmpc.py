@@ -94,6 +94,8 @@ def lib():
             "gnmpc_vjp": ([vp] * 7, i32),
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
+            "gnmpc_solve_box_qp_noalloc": ([i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp],
+                                           i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
             "gnmpc_timers_enable": ([vp, i32], i32),
             "gnmpc_step_batched": ([vp, i32, P(AdmmSettings), vp], i32),
@@ -305,6 +307,39 @@ def _timers_read(self):
 
 Plan.timers_enable = _timers_enable
 Plan.timers_read = _timers_read
+
+
+def solve_box_qp_noalloc(H, g, lb, ub, Ct, lc, uc, u, info=None, settings=None, stream=None):
+    """gnmpc_solve_box_qp_noalloc: the box QP with no plan and no allocation
+    (workspace in the library's static per-GPU array; n <= 464).  All tensors
+    on the current device, float32 or float64 (the dtype of H)."""
+    dtype = H.dtype
+    if dtype not in (torch.float32, torch.float64):
+        raise GnmpcError(INVALID_ARG, "solve_box_qp_noalloc: float32 or float64 arrays")
+    dev = torch.cuda.current_device()
+    n = g.shape[0]
+    nc = 0 if Ct is None else Ct.shape[0]
+
+    def arg(t, shape, name, dt=dtype, allow_none=False):
+        if t is None:
+            if allow_none:
+                return None
+            raise GnmpcError(INVALID_ARG, f"{name} is required")
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device.index == dev):
+            raise GnmpcError(INVALID_ARG, f"{name} must be a tensor on cuda:{dev}")
+        if t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise GnmpcError(SHAPE, f"{name}: expected contiguous {dt} {tuple(shape)}, got {t.dtype} "
+                                    f"{tuple(t.shape)} contiguous={t.is_contiguous()}")
+        return C.c_void_p(t.data_ptr())
+
+    st = settings or default_admm_settings()
+    args = [arg(H, (n, n), "H"), arg(g, (n,), "g"), arg(lb, (n,), "lb"), arg(ub, (n,), "ub"), nc,
+            arg(Ct, (nc, n), "Ct", allow_none=nc == 0), arg(lc, (nc,), "lc", allow_none=True),
+            arg(uc, (nc,), "uc", allow_none=True), C.byref(st), arg(u, (n,), "u"),
+            arg(info, (QP_INFO_BYTES,), "info", dt=torch.uint8, allow_none=True)]
+    s = lib().gnmpc_solve_box_qp_noalloc(F64 if dtype == torch.float64 else F32, n, *args, _stream(stream))
+    if s != OK:
+        raise GnmpcError(s, "solve_box_qp_noalloc: " + status_string(s))
 
 
 def step_desc(plan, b):

@@ -106,3 +106,24 @@ def test_null_plan_calls_are_rejected():
     s = gn.AdmmSettings()
     assert L.gnmpc_solve_box_qp(None, 1, None, None, None, None, 0, None, None, None, C.byref(s), None, None,
                                 None) == gn.INVALID_ARG
+
+
+def test_noalloc_qp_validates_before_touching_the_gpu():
+    """gnmpc_solve_box_qp_noalloc checks dtype, arrays, sizes and settings on
+    the host (no GPU is needed to be told no)."""
+    L = gn.lib()
+    s = gn.AdmmSettings()
+    L.gnmpc_admm_default_settings(C.byref(s))
+    fake = C.c_void_p(256)   # never dereferenced: every call below fails validation first
+    f = L.gnmpc_solve_box_qp_noalloc
+    assert f(gn.BF16, 8, fake, fake, fake, fake, 0, None, None, None, C.byref(s), fake, None, None) == gn.INVALID_ARG
+    assert f(gn.F32, 8, None, fake, fake, fake, 0, None, None, None, C.byref(s), fake, None, None) == gn.INVALID_ARG
+    assert f(gn.F32, 8, fake, fake, fake, fake, 3, None, None, None, C.byref(s), fake, None, None) == gn.INVALID_ARG
+    assert f(gn.F32, 465, fake, fake, fake, fake, 0, None, None, None, C.byref(s), fake, None, None) == gn.SHAPE
+    assert f(gn.F64, 0, fake, fake, fake, fake, 0, None, None, None, C.byref(s), fake, None, None) == gn.SHAPE
+    assert f(gn.F32, 64, fake, fake, fake, fake, 100000, fake, None, None, C.byref(s), fake, None,
+             None) == gn.UNSUPPORTED
+    bad = gn.AdmmSettings()
+    L.gnmpc_admm_default_settings(C.byref(bad))
+    bad.alpha = 2.5
+    assert f(gn.F32, 8, fake, fake, fake, fake, 0, None, None, None, C.byref(bad), fake, None, None) == gn.INVALID_ARG
