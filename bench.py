@@ -80,25 +80,74 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(P, Pm):
-    """The FP64 oracle on the host, one thread, on a bounded sample of the
-    step: the GNN linearization on 1000 node-stages (extrapolated to all
-    N*M), then one full condensing on the GNN Jacobian pattern and one QP
-    solve.  The condensing takes the analytic mass-spring-damper Jacobians of
-    the same chain (oracle) placed into the wider GNN pattern, so the blocks
-    have the dynamics' magnitudes and the QP is the plain model's real one."""
+def _host_cpu():
+    """CPU model name and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_lin_sample(job):
+    """Worker of the multi-core oracle timing: the FP64 GNN linearization of the
+    1000-node workload on the given (stage, node) sample, one BLAS thread."""
+    stages, nodes = job
     from threadpoolctl import threadpool_limits
-    from oracle.condense import condense_local
     from oracle.gnn import gnn_linearize
-    from oracle.graph import jacobian_pattern
-    from oracle.msd import msd_linearize
-    from oracle.qp import qp_ipm
+    from paper_2602_17601_amd import workloads as wl
+    P = wl.gnn1000_bf16()
     Wr = P.gnn.rounded_bf16()
-    stages, nodes = [3, 7, 11, 15, 19], list(range(300, 500))
     with threadpool_limits(1):
         t0 = time.perf_counter()
         gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes)
-        t_lin = (time.perf_counter() - t0) / (len(stages) * len(nodes)) * P.N * P.M
+        return time.perf_counter() - t0
+
+
+def _oracle_plain_step(P):
+    """One plain-form step of the FP64 oracle: analytic linearization,
+    per-node condensing recursion and the interior-point QP (seconds)."""
+    from oracle.condense import condense_local
+    from oracle.msd import msd_linearize
+    from oracle.qp import qp_ipm
+    t0 = time.perf_counter()
+    prow, pcol, A, B, c = msd_linearize(P.xhat, P.uhat, P.row_ptr, P.col, P.act, P.msd)
+    l = condense_local(A, B, c, prow, pcol, P.x0, P.costs.Q, P.costs.q, P.costs.R, P.costs.r, P.rows)
+    if P.rows.n:
+        qp_ipm(l["H"], l["g"], P.lb, P.ub, l["Ct"], np.full(P.rows.n, -np.inf), l["dt"])
+    else:
+        qp_ipm(l["H"], l["g"], P.lb, P.ub)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(P, Pm):
+    """The FP64 oracle on the host cores, on a bounded sample of the step.
+
+    GNN form: the per-node linearization timed on a sample of node-stages
+    (1000 on one thread; 1000 per core on all cores, split over one worker
+    process per core) and extrapolated to all N*M node-stages, plus one full
+    condensing on the 13-wide GNN pattern and one QP solve, which the oracle
+    runs on one thread.  The condensing takes the analytic mass-spring-damper
+    Jacobians of the same chain placed into the wider GNN pattern, so the
+    blocks have the dynamics' magnitudes.  Plain form: whole oracle steps
+    (linearize, condense, QP) of the 10-, 100- and 1000-node workloads."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle.condense import condense_local
+    from oracle.graph import jacobian_pattern
+    from oracle.msd import msd_linearize
+    from oracle.qp import qp_ipm
+    from paper_2602_17601_amd import workloads as wl
+    cpu, cores = _host_cpu()
+    stages = [3, 7, 11, 15, 19]
+    sample1 = (stages, list(range(300, 500)))
+    with threadpool_limits(1):
+        t_lin1 = _oracle_lin_sample(sample1) / 1000 * P.N * P.M
         prow, pcol = jacobian_pattern(P.row_ptr, P.col, P.M, P.gnn.L)
         mrow, mcol, Am, Bm, cm = msd_linearize(Pm.xhat, Pm.uhat, Pm.row_ptr, Pm.col, Pm.act, Pm.msd)
         A = np.zeros((P.N, len(pcol), 6, 6))
@@ -112,19 +161,83 @@ def cpu_baseline(P, Pm):
         t0 = time.perf_counter()
         qp_ipm(l["H"], l["g"], Pm.lb, Pm.ub, l["Ct"], np.full(Pm.rows.n, -np.inf), l["dt"])
         t_qp = time.perf_counter() - t0
-    step = t_lin + t_cond + t_qp
-    return {"value": 1.0 / step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle, 1 thread: GNN linearization timed on {len(stages) * len(nodes)} node-stages "
-                       f"({t_lin / (P.N * P.M) * 1e3:.1f} ms each, extrapolated to {P.N * P.M}), one full "
-                       f"condensing on the {len(pcol)}-block GNN pattern ({t_cond:.2f} s) and one QP "
-                       f"({t_qp:.2f} s, mass-spring-damper Jacobians)")}
+        plain = {name: 1.0 / _oracle_plain_step(prob) for name, prob in
+                 (("msd10_fp64", wl.msd10_fp64()), ("msd100", wl.gnn100_fp32("msd")), ("msd1000", Pm))}
+    # all cores: one worker process per core, 200 nodes x 5 stages each
+    jobs = [(stages, [(300 + 200 * w + t) % P.M for t in range(200)]) for w in range(cores)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_lin_sample, jobs)
+    t_lin_n = (time.perf_counter() - t0) / (1000 * cores) * P.N * P.M
+    step1 = t_lin1 + t_cond + t_qp
+    stepn = t_lin_n + t_cond + t_qp
+    return {"value": 1.0 / stepn, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu, "value_1_thread": 1.0 / step1, "plain_form_steps_per_s": plain,
+            "sample": (f"FP64 oracle (numpy) on {cpu}, {cores} cores: GNN linearization timed on 1000 "
+                       f"node-stages per core in {cores} worker processes, including their start-up "
+                       f"({t_lin_n / (P.N * P.M) * 1e3:.2f} ms per node-stage; 1 thread: "
+                       f"{t_lin1 / (P.N * P.M) * 1e3:.1f} ms), extrapolated to {P.N * P.M}; one full "
+                       f"condensing on the {len(pcol)}-block GNN pattern ({t_cond:.2f} s, 1 thread) and "
+                       f"one QP ({t_qp:.2f} s, 1 thread); plain form: whole oracle steps on 1 thread")}
+
+
+# Published MI355X peaks used by the per-phase rooflines.
+FP32_MATRIX_PEAK_TFLOPS = 157.3   # dense FP32 (matrix cores)
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # FP32 vector (packed); the library builds without packed FP32, i.e. half
+CU_COUNT = 256
+
+
+def phase_rooflines(P, nnz, phase_ms, jac_flops):
+    """Per-phase attainable-roofline fractions of the GNN step: algorithmic
+    FLOPs and HBM bytes of each phase, t_roof = max(bytes / HBM peak,
+    FLOPs / peak of the binding unit), against the measured phase time."""
+    M, N, nu, Hd, L = P.M, P.N, P.nu, P.gnn.Hd, P.gnn.L
+    E = int(P.col.shape[0])
+    f4 = 4
+    A_bytes, B_bytes, c_bytes = N * nnz * 36 * f4, N * M * 6 * nu * f4, N * M * 6 * f4
+    # forward: encoder and decoder per node, per round [W_a; W_b] h and W_n [h; agg] per node (8 Hd^2,
+    # the edge MLP in factored form) plus the per-edge combine, ReLU and sum (3 Hd)
+    fwd_flops = N * (M * (2 * 9 * Hd + 2 * Hd * 6) + L * (M * 8 * Hd * Hd + E * 3 * Hd))
+    n = N * nu
+    prop_flops = 72 * nnz * nu * N * (N - 1) / 2 + 72 * nnz * N
+    gram_flops = sum(6 * M * (k * nu) * (k * nu + 1) + 2 * 6 * M * k * nu for k in range(1, N + 1))
+    rows_flops = 2 * 6 * P.rows.n * n
+    qp_flops = 2 * (n ** 3) / 3 + 10 * (2 * n * n + 4 * n * P.rows.n)
+    cu_peak = FP32_MATRIX_PEAK_TFLOPS / CU_COUNT
+    ph = [
+        # phase, flops, bytes, binding unit, peak TFLOP/s
+        ("gnn_forward", fwd_flops, P.xhat.size * f4 + 2 * N * M * 6 * f4, "mfma_bf16", BF16_DENSE_PEAK_TFLOPS),
+        ("gnn_stage_images", 0, 0, "none (implementation traffic: the Jacobian kernel's stage copies)", None),
+        ("gnn_jacobian", jac_flops, A_bytes + B_bytes, "mfma_bf16", BF16_DENSE_PEAK_TFLOPS),
+        ("gnn_assembly", 2 * N * (nnz * 36 + M * 6 * nu), A_bytes + B_bytes + c_bytes, "hbm", None),
+        ("condense_propagate", prop_flops, A_bytes + B_bytes + c_bytes, "fp32_vector", FP32_VECTOR_PEAK_TFLOPS),
+        ("condense_gram", gram_flops, n * n * f4, "fp32_matrix", FP32_MATRIX_PEAK_TFLOPS),
+        ("condense_rows", rows_flops, P.rows.n * 6 * n * f4 + P.rows.n * n * f4, "hbm", None),
+        ("qp", qp_flops, n * n * f4 + P.rows.n * n * f4, "fp32_matrix_one_cu", cu_peak),
+    ]
+    out = {}
+    tot_roof = tot_meas = 0.0
+    for name, fl, by, unit, peak in ph:
+        t_mem = by / (HBM_PEAK_GBS * 1e9)
+        t_cmp = fl / (peak * 1e12) if peak else 0.0
+        t_roof = max(t_mem, t_cmp)
+        bound = unit if t_roof == 0 else ("hbm" if t_mem >= t_cmp else unit)
+        t_meas = phase_ms.get(name, 0.0) * 1e-3
+        out[name] = {"flops": fl, "hbm_bytes": by, "bound": bound, "t_roof_us": t_roof * 1e6,
+                     "t_meas_us": t_meas * 1e6, "frac": t_roof / t_meas if t_meas > 0 else None}
+        tot_roof += t_roof
+        tot_meas += t_meas
+    out["step"] = {"t_roof_us": tot_roof * 1e6, "t_meas_us": tot_meas * 1e6,
+                   "frac": tot_roof / tot_meas if tot_meas > 0 else None}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single instance: K independent instances of uneven size "
@@ -160,6 +273,8 @@ def main():
     dev = "cuda"
     P = wl.gnn1000_bf16()
     Pm = wl.gnn1000_bf16(model="msd")
+    # the host baseline runs before the GPU is touched (its worker processes start clean)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(P, Pm)
     n = P.N * P.nu
 
     def t(a):
@@ -274,7 +389,9 @@ def main():
         "config": {"workload": ("1000-node 1-2-hop chain, GNN Hd=128 L=3 (BF16 MLPs, FP32 accumulate), "
                                 "n_u=12 at 4 nodes, N=20, 200 node-position rows, FP32 condensing, ADMM box QP"),
                    "M": P.M, "N": P.N, "nu": P.nu, "nnz_blocks": int(plan_g.nnz), "state_rows": P.rows.n},
-        "timing": "eager launches" if args.eager else "HIP graph replay of the whole step",
+        "timing": ("eager launches" if args.eager else "HIP graph replay of the whole step") +
+                  " on inputs resident in HBM (x0, nominal trajectory, costs, rows uploaded once before timing; "
+                  "u stays on the device)",
         "median_ms_per_step": st_g["median_ms"],
         "p95_ms_per_step": st_g["p95_ms"],
         "eager_steps_per_s": st_g["eager_steps_per_s"],
@@ -287,7 +404,8 @@ def main():
         "qp_iters_gnn": qpi.iters,
         "qp_status_gnn": qpi.status,
         "roofline": roofline,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(P, Pm),
+        "phase_roofline_gnn": phase_rooflines(P, int(plan_g.nnz), phase_avg(ph_g), flops),
+        "cpu_baseline": cpu,
         "tangent": tangent_rates(gn, plan_g, bg, args.steps),
     }
     print(json.dumps(out), flush=True)

@@ -216,6 +216,12 @@ sprop_block_kernel(int k, int M, int nu, int nbn, int rstride, int umax, int ema
 // kernel (so the values are the same bit for bit), writes the rows of its own nodes, then
 // forms S_{k+2} (and Gx_{k+2}) of its nodes from the staged U1 rows.  This halves the
 // chain of dependent launches of the recursion.
+// LDS a two-stage workgroup may use.  gfx950 allows 160 KB per workgroup, but
+// past 64 KB only one 4-wave workgroup fits a CU and the stage pair runs slower
+// than two one-stage launches (measured on the 13-wide GNN pattern, ~106 KB:
+// 0.56 ms against 0.23 ms for the recursion).
+constexpr size_t kProp2LdsCap = 64 * 1024;
+
 struct Prop2Layout {
   int rs, es1, u1, r1, g1, es2, u2, stride;
 };
@@ -932,7 +938,7 @@ gnmpc_status prop_blocks_build(gnmpc_plan* p) {
 // entries (global index, position of the column in U2) and U2 = the union of U1's
 // pattern columns.  Layout per block (int32): e0, ne, nn, |U1|, |U2|, U1 entry count, 0, 0,
 // then the arrays at the offsets of Prop2Layout.  Not used (pb2_stride = 0) when the
-// staged rows do not fit 64 KB of LDS.
+// staged rows do not fit kProp2LdsCap bytes of LDS.
 gnmpc_status prop_blocks2_build(gnmpc_plan* p) {
   if (p->d_pb2_rec) {
     (void)hipFree(p->d_pb2_rec);
@@ -970,7 +976,7 @@ gnmpc_status prop_blocks2_build(gnmpc_plan* p) {
   }
   const Prop2Layout L = prop2_layout(nb, p->pb_emax, u1max, e1max, u2max);
   const size_t lds = prop2_lds_bytes(L, (size_t)p->elem, p->pb_emax, u1max, e1max, u2max);
-  if (lds > 64 * 1024) return GNMPC_OK;
+  if (lds > kProp2LdsCap) return GNMPC_OK;
   std::vector<int32_t> rec((size_t)nblk * L.stride, 0);
   for (int b = 0; b < nblk; ++b) {
     int32_t* r = rec.data() + (size_t)b * L.stride;

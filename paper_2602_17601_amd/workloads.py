@@ -329,11 +329,11 @@ def msd10_fp64() -> Problem:
                         x0_sigma=0.1, qdiag=(1, 1, 1, 1, 1, 1), dtype="f64")
 
 
-def gnn100_fp32() -> Problem:
+def gnn100_fp32(model: str = "gnn") -> Problem:
     """GNN-linearized condensing in FP32: 100-node 1-2-hop chain, Hd=64, L=2,
-    forces at nodes 50 and 100, N=20."""
-    return make_problem("gnn100_fp32", M=100, hops=2, N=20, n_act=2, model="gnn", seed=2,
-                        weight_seed=1, Hd=64, L=2, x0_sigma=0.02, walk=0.002)
+    forces at nodes 50 and 100, N=20.  ``model='msd'`` gives the plain form."""
+    return make_problem("gnn100_fp32" if model == "gnn" else "msd100_fp32", M=100, hops=2, N=20, n_act=2,
+                        model=model, seed=2, weight_seed=1, Hd=64, L=2, x0_sigma=0.02, walk=0.002)
 
 
 def gnn1000_bf16(model: str = "gnn") -> Problem:
