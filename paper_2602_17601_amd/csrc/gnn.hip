@@ -845,19 +845,22 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
     const int vb1 = mt[6 + 2 * l], vc1 = mt[7 + 2 * l];
     const int nbase = so + vc0 * SREC;
     const size_t woff = (size_t)(l - 1) * Hd * Hd;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        w1[m][kb] = ldwr(rW1, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
-        w2[m][kb] = ldwr(rW2, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
-      }
     // ---- phase A: edge GEMMs per sender, aggregates of every receiver in registers.
     // Round l-1's nodes lead round l in the same order, so sender p is node p of round l.
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    // The node weights of this round are read two fragments per sender slot, and the
+    // next round's edge weights one pair per node slot of phase B: every workgroup
+    // reads the same weights from L2, and spreading the requests over the round keeps
+    // them from queueing behind each other (issued at once, they stalled the round's
+    // first sender by several thousand cycles).
 #pragma unroll
     for (int p = 0; p < MAXV; ++p) {
+      if (p < 2 * KB) {
+        const int m = p / KB, kb = p % KB;
+        w1[m][kb] = ldwr(rW1, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
+        w2[m][kb] = ldwr(rW2, 2 * woB + 32 * m * Hd + 64 * kb, (uint32_t)(2 * woff));
+      }
       if (p < vc0) {
         const uint32_t* rec = ST + so + p * SREC;
         const uint4* rec4 = reinterpret_cast<const uint4*>(rec);
@@ -912,18 +915,16 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       }
     }
     __syncthreads();
-    if (l < a.L) {
-      const size_t wn = (size_t)l * Hd * Hd;
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        wa[kb] = ldwr(rWa, 2 * woA + 64 * kb, (uint32_t)(2 * wn));
-        wb[kb] = ldwr(rWb, 2 * woA + 64 * kb, (uint32_t)(2 * wn));
-      }
-    }
+    const size_t wn = (size_t)l * Hd * Hd;  // next round's weights
+
     // ---- phase B: node GEMMs, two node groups; results stay in registers until every wave is done reading
     const unsigned char* AGg = AG + ((size_t)ng * kCols + col) * CB;  // node 2 j + ng at + 2 j * kCols * CB
 #pragma unroll
     for (int j = 0; j < MAXV / 2; ++j) {
+      if (j < KB && l < a.L) {
+        wa[j] = ldwr(rWa, 2 * woA + 64 * j, (uint32_t)(2 * wn));
+        wb[j] = ldwr(rWb, 2 * woA + 64 * j, (uint32_t)(2 * wn));
+      }
       const int q = 2 * j + ng;
       if (q < vc1) {
         floatx4_t c[2];
