@@ -759,6 +759,16 @@ __device__ inline bf16x8_t ldwr(__amdgpu_buffer_rsrc_t r, uint32_t voff_bytes, u
   return __builtin_bit_cast(bf16x8_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff_bytes, soff_bytes, 0));
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits for
+// every outstanding global load and store of the wave (its release fence covers
+// global memory), so each barrier would wait for weight fragments still in flight.
+// The kernel below exchanges data between waves through LDS only.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int Hd>
 __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   constexpr int NW = Hd / 16;   // waves
@@ -811,7 +821,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   }
   for (int t = threadIdx.x; t < 3 * Hd; t += NT) DT[t] = a.decT[(t % Hd) * 6 + 3 + t / Hd];
   for (int t = threadIdx.x; t < 9 * Hd / 4; t += NT) reinterpret_cast<float4*>(ET)[t] = reinterpret_cast<const float4*>(a.encT)[t];
-  __syncthreads();
+  lds_barrier();
   // round 0: encoder tangents of the seeds (mask x weight, exact in bf16), 8 features per item
   {
     const int vc = mt[7];
@@ -836,7 +846,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       *reinterpret_cast<uint4*>(R1 + ((size_t)q * kCols + c) * CB + swzc<CB>(16 * fc, c)) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   floatx4_t acc[MAXV];
   int so = 0;          // stage offset of the current round
@@ -884,14 +894,13 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
 #pragma unroll
         for (int q4 = 0; q4 < MAXV; q4 += 4) {
           if ((rcv >> q4) & 15u) {
+            // every receiver of the group without a test: a non-receiver's mask word is zero
 #pragma unroll
             for (int q = q4; q < q4 + 4; ++q) {
-              if (__builtin_expect((rcv >> q) & 1u, 1)) {
-                // 1.0f where the edge's ReLU is on for this lane's feature, else 0
-                const float mf = __uint_as_float((uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], mpos, 1) & 0x3F800000u);
+              // 1.0f where the edge's ReLU is on for this lane's feature, else 0
+              const float mf = __uint_as_float((uint32_t)__builtin_amdgcn_sbfe((int)tbl[q], mpos, 1) & 0x3F800000u);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[q][i] = __builtin_fmaf(-mf, ay[i], acc[q][i]);
-              }
+              for (int i = 0; i < 4; ++i) acc[q][i] = __builtin_fmaf(-mf, ay[i], acc[q][i]);
             }
           }
         }
@@ -914,7 +923,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     const size_t wn = (size_t)l * Hd * Hd;  // next round's weights
 
     // ---- phase B: node GEMMs, two node groups; results stay in registers until every wave is done reading
@@ -955,7 +964,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
                                                 (uint32_t)__builtin_amdgcn_sbfe(bits, 16 * m + 4 * grp + i, 1));
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (l < a.L) {
       unsigned char* R1g = R1 + ((size_t)ng * kCols + col) * CB;
       const int sw0 = swzc<CB>(2 * (wg * 32 + 4 * grp), col), sw1 = swzc<CB>(2 * (wg * 32 + 16 + 4 * grp), col);
@@ -972,7 +981,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     so = nbase + (vc1 * HW + 3) / 4 * 4;
   }
@@ -1010,7 +1019,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   const int4* orec = reinterpret_cast<const int4*>(ST) + (so >> 2);
   for (int t = threadIdx.x; t < oc * 18; t += NT) {
     const int o = t / 18, rem = t % 18, r = rem / 6, dd = rem % 6;
