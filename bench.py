@@ -102,7 +102,7 @@ def _oracle_lin_sample(job):
     from oracle.gnn import gnn_linearize
     from paper_2602_17601_amd import workloads as wl
     P = wl.gnn1000_bf16()
-    Wr = P.gnn.rounded_bf16()
+    Wr = P.gnn.rounded_bf16(biases="f32")
     with threadpool_limits(1):
         t0 = time.perf_counter()
         gnn_linearize(P.xhat, P.uhat, Wr, P.row_ptr, P.col, P.act, stages=stages, nodes=nodes)
@@ -439,6 +439,18 @@ def tangent_rates(gn, plan, b, reps):
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms": ms, "bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
                      "hbm_frac": nbytes / (ms * 1e-3) / 8e12}
+    # reverse mode through the GNN's layers (forward pass recomputed, then the layers backwards)
+    if getattr(plan, "model", None) == "gnn":
+        for _ in range(3):
+            plan.gnn_vjp(b["xhat"], b["uhat"], out, gx, gu)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.gnn_vjp(b["xhat"], b["uhat"], out, gx, gu)
+        e1.record()
+        torch.cuda.synchronize()
+        res["gnn_vjp_reverse_mode"] = {"ms": e0.elapsed_time(e1) / reps,
+                                       "note": "forward pass recomputed at the point, then L rounds backwards"}
     return res
 
 

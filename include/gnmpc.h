@@ -198,6 +198,26 @@ gnmpc_status gnmpc_rows_set(gnmpc_plan* plan, int32_t n_c, const int32_t* node, 
 gnmpc_status gnmpc_linearize(gnmpc_plan* plan, const void* xhat, const void* uhat,
                              void* A, void* B, void* c, void* fnext, void* stream);
 
+/* The GNN one-step model of Sec. V-A (eq. forward_dynamics; semi-implicit
+ * Euler) at the N stages, without its Jacobians: fnext[k] = f(xhat[k], uhat[k]).
+ * xhat [N+1][M][6] (stage N is not read), uhat [N][nu], fnext [N][M][6]: FP32
+ * device arrays.  GNMPC_NOT_READY unless the graph and a GNN model are set.
+ * Uses the plan's forward-pass workspace (as gnmpc_linearize does). */
+gnmpc_status gnmpc_gnn_forward(gnmpc_plan* plan, const void* xhat, const void* uhat, void* fnext,
+                               void* stream);
+
+/* Reverse mode through the GNN's layers: the gradient of sum_k g[k] . f(x_k, u_k)
+ * at (xhat[k], uhat[k]), i.e. gx[k] = (d f / d x_k)' g[k] and gu[k] = (d f / d u_k)' g[k]
+ * (the transposed linearization of Sec. V-A, with ReLU's subgradient 0 at 0),
+ * without forming the Jacobian blocks.  The forward pass is recomputed at the
+ * given point for its ReLU masks, then the cotangents run back layer by layer.
+ * FP32 device arrays: xhat [N+1][M][6], uhat [N][nu], g [N][M][6]; outputs gx
+ * [N][M][6], gu [N][nu] (every entry written; outputs may not alias inputs).
+ * GNMPC_NOT_READY unless the graph and a GNN model are set; GNMPC_INVALID_ARG
+ * for a NULL array.  Uses the plan's forward-pass workspace. */
+gnmpc_status gnmpc_gnn_vjp(gnmpc_plan* plan, const void* xhat, const void* uhat, const void* g, void* gx,
+                           void* gu, void* stream);
+
 /* Tangent maps of the linearized one-step model x_{k+1} = f(x_k, u_k) of Sec. V-A,
  * from the blocks gnmpc_linearize produced (A [N][nnz][6][6], B [N][M][6][nu], in
  * the plan's pattern and dtype).  Device arrays of the plan dtype, all N stages:

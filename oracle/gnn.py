@@ -18,6 +18,10 @@ derivative mask is z > 0).  The offset is c = f(xhat,uhat) - sum_j A^{ij} xhat^j
 ``activation='identity'`` replaces every ReLU by the identity; it exists only
 so the tests can compare against a closed-form affine model.
 
+``gnn_vjp`` is reverse mode through the same network: the gradient of g . f,
+pinned in the tests against the forward-mode Jacobian above (a separate
+algorithm) and against central differences.
+
 ``gnn_kink_margin`` reports, per node, how close the model is to a ReLU kink
 anywhere in the node's receptive field: the smallest ratio |z| / scale(z) over
 every pre-activation z that f^i depends on, scale(z) being the sum of the
@@ -87,6 +91,55 @@ def gnn_forward(x, u, W, row_ptr, col, act, activation="relu", margins=False):
     pn = x[:, :3] + W.dt * vn
     f = np.concatenate([pn, vn], axis=1)
     return (f, out) if margins else f
+
+
+def gnn_vjp(x, u, W, row_ptr, col, act, g, activation="relu"):
+    """Reverse mode of one step: the gradient of g . f(x, u) (Sec. V-A's model).
+
+    x [M][6], u [nu], g [M][6] -> (gx [M][6], gu [nu]).  The forward pass keeps
+    each layer's derivative masks; the cotangents then run back through the
+    decoder and integrator, the L message-passing rounds in reverse order and
+    the encoder, each written out from the layer's definition.
+    """
+    M, nu, Hd = x.shape[0], u.shape[0], W.Hd
+    inp = np.stack([node_input(x, u, i, act) for i in range(M)])
+    h, m_enc = _act(inp @ W.W_enc.T + W.b_enc, activation)
+    recv, send = _edges(row_ptr, col)
+    m_edge, m_node = [], []
+    for l in range(W.L):
+        e_in = np.concatenate([h[recv], h[recv] - h[send]], axis=1)
+        m, de = _act(e_in @ W.W_edge[l].T + W.b_edge[l], activation)
+        agg = np.zeros_like(h)
+        np.add.at(agg, recv, m)
+        h, dn = _act(np.concatenate([h, agg], axis=1) @ W.W_node[l].T + W.b_node[l], activation)
+        m_edge.append(de)
+        m_node.append(dn)
+    # integrator: p+ = p + dt v+, v+ = v + dt o[3:6]
+    vb = g[:, 3:] + W.dt * g[:, :3]               # cotangent of v+
+    gx = np.concatenate([g[:, :3], vb], axis=1)   # direct dependence on p and v
+    ob = np.zeros((M, 6))
+    ob[:, 3:6] = W.dt * vb                        # cotangent of o
+    hb = ob @ W.W_dec                             # of h^L
+    for l in reversed(range(W.L)):
+        nb = (m_node[l] * hb) @ W.W_node[l]       # of [h; agg] at the node update
+        hb_new, ab = nb[:, :Hd].copy(), nb[:, Hd:]
+        eb = (m_edge[l] * ab[recv]) @ W.W_edge[l]  # of [h_i; h_i - h_j] per edge (every edge feeds agg_i)
+        np.add.at(hb_new, recv, eb[:, :Hd] + eb[:, Hd:])
+        np.add.at(hb_new, send, -eb[:, Hd:])
+        hb = hb_new
+    ib = (m_enc * hb) @ W.W_enc                   # of the node inputs [x^i; P^i u]
+    gx = gx + ib[:, :6]
+    gu = np.zeros(nu)
+    for a, node in enumerate(act):
+        gu[3 * a:3 * a + 3] += ib[int(node), 6:9]
+    return gx, gu
+
+
+def gnn_vjp_stages(xhat, uhat, W, row_ptr, col, act, g, activation="relu"):
+    """gnn_vjp at every stage k < N: (gx [N][M][6], gu [N][nu])."""
+    N = uhat.shape[0]
+    out = [gnn_vjp(xhat[k], uhat[k], W, row_ptr, col, act, g[k], activation) for k in range(N)]
+    return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
 
 
 def gnn_kink_margin(x, u, W, row_ptr, col, act, nodes=None):

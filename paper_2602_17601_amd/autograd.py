@@ -1,8 +1,11 @@
 """The plan's one-step model x_{k+1} = f(x_k, u_k) (Sec. V-A) as a differentiable
-torch op over all N stages.  The forward pass is gnmpc_linearize, which also forms
-the block Jacobians A_k, B_k at (x_k, u_k) with the forward-mode kernel; the
-backward pass applies gnmpc_vjp to those saved blocks, and ``dynamics_jvp`` applies
-gnmpc_jvp.  Argument marshalling only: every product runs in the library."""
+torch op over all N stages.  For a GNN model the forward pass is gnmpc_gnn_forward
+and the backward pass gnmpc_gnn_vjp, reverse mode through the network's layers
+(the forward pass is recomputed at the saved point for its ReLU masks; no
+Jacobian blocks are formed).  For the mass-spring-damper model the forward pass is
+gnmpc_linearize, whose analytic blocks A_k, B_k are saved and multiplied by
+gnmpc_vjp.  ``dynamics_jvp`` applies gnmpc_jvp to the linearization's blocks.
+Argument marshalling only: every product runs in the library."""
 from __future__ import annotations
 
 import torch
@@ -28,19 +31,33 @@ class Dynamics(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, plan, x, u):
-        A, B, f = _blocks(plan, x, u)
         ctx.plan = plan
+        xd, ud = x.detach().contiguous(), u.detach().contiguous()
+        if getattr(plan, "model", None) == "gnn":
+            f = torch.empty(plan.N, plan.M, 6, device=x.device, dtype=x.dtype)
+            plan.gnn_forward(xd, ud, f)
+            ctx.save_for_backward(xd, ud)
+            ctx.reverse = True
+            return f
+        A, B, f = _blocks(plan, x, u)
         ctx.save_for_backward(A, B)
+        ctx.reverse = False
         return f
 
     @staticmethod
     def backward(ctx, grad):
-        A, B = ctx.saved_tensors
         plan = ctx.plan
         N, M, nu = plan.N, plan.M, plan.nu
         gx = torch.zeros(N + 1, M, 6, device=grad.device, dtype=grad.dtype)
         gu = torch.empty(N, nu, device=grad.device, dtype=grad.dtype)
-        plan.vjp(A, B, grad.contiguous(), gx[:N], gu)
+        if ctx.reverse:
+            xd, ud = ctx.saved_tensors
+            gxs = torch.empty(N, M, 6, device=grad.device, dtype=grad.dtype)
+            plan.gnn_vjp(xd, ud, grad.contiguous(), gxs, gu)
+            gx[:N] = gxs
+        else:
+            A, B = ctx.saved_tensors
+            plan.vjp(A, B, grad.contiguous(), gx[:N], gu)
         return None, gx, gu
 
 

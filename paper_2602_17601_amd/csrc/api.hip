@@ -391,6 +391,23 @@ gnmpc_status gnmpc_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, 
   return launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
 }
 
+gnmpc_status gnmpc_gnn_forward(gnmpc_plan* p, const void* xhat, const void* uhat, void* fnext, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!xhat || !uhat || !fnext) return fail(p, GNMPC_INVALID_ARG, "gnn_forward: null array");
+  if (!p->graph_ready || p->model != 2) return fail(p, GNMPC_NOT_READY, "gnn_forward: graph and GNN model must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_gnn_forward_only(p, xhat, uhat, fnext, (hipStream_t)stream);
+}
+
+gnmpc_status gnmpc_gnn_vjp(gnmpc_plan* p, const void* xhat, const void* uhat, const void* g, void* gx, void* gu,
+                           void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!xhat || !uhat || !g || !gx || !gu) return fail(p, GNMPC_INVALID_ARG, "gnn_vjp: null array");
+  if (!p->graph_ready || p->model != 2) return fail(p, GNMPC_NOT_READY, "gnn_vjp: graph and GNN model must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_gnn_vjp(p, xhat, uhat, g, gx, gu, (hipStream_t)stream);
+}
+
 gnmpc_status gnmpc_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
                             const void* Q, int32_t Q_full, const void* q, const void* R, const void* r,
                             const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt, void* Gx,

@@ -38,7 +38,7 @@ struct GnnState {
   float *Wn1T = nullptr, *Wn2T = nullptr, *bn = nullptr;    // [L][Hd][Hd], [L][Hd]
   float *decT = nullptr, *bdec = nullptr;                   // [Hd][6], [6]
   // forward-pass workspace
-  float* h = nullptr;              // [L+1][N][M][Hd]
+  float* h = nullptr;              // [max(L+1, 3)][N][M][Hd]
   uint32_t *mask_enc = nullptr;    // [N][M][Hd/32]
   uint32_t *mask_node = nullptr;   // [L][N][M][Hd/32]
   uint32_t *mask_edge = nullptr;   // [L][N][E][Hd/32]
@@ -72,6 +72,10 @@ struct GnnState {
   int32_t *fecnt = nullptr;       // [n_ftiles][NC] in-edges of each target column
   int32_t *fepre = nullptr;       // [n_ftiles][NC] edges of the columns before it (exclusive prefix)
   int32_t *fesrc = nullptr, *feid = nullptr;  // per edge: source column, CSR edge id
+  // reverse mode (gnmpc_gnn_vjp): FP32 weights row-major (out, in) so lane q reads
+  // column q of W (the transposed products), and each node's out-edges
+  float *WabR = nullptr, *WbR = nullptr, *Wn1R = nullptr, *Wn2R = nullptr;  // [L][Hd][Hd]; WabR = W_a + W_b
+  int32_t *out_ptr = nullptr, *out_recv = nullptr, *out_edge = nullptr;     // [M+1], [E], [E]
   std::vector<void*> allocs;
 };
 
@@ -1778,8 +1782,36 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   if ((s = dupload(p, g.ptr, vec)) != GNMPC_OK) return s;
   UP(encT, encT) UP(benc, benc) UP(WaT, WaT) UP(WbT, WbT) UP(be, be) UP(Wn1T, Wn1T) UP(Wn2T, Wn2T) UP(bn, bn)
   UP(decT, decT) UP(bdec, bdec)
+  {
+    // reverse mode: W_a + W_b, W_b, W_n1, W_n2 row-major (out f, in q); the transposes above hold [q][f]
+    std::vector<float> WabR((size_t)L * Hd * Hd), WbR(WabR.size()), Wn1R(WabR.size()), Wn2R(WabR.size());
+    for (int l = 0; l < L; ++l)
+      for (int f = 0; f < Hd; ++f)
+        for (int q = 0; q < Hd; ++q) {
+          const size_t t = ((size_t)l * Hd + q) * Hd + f, r = ((size_t)l * Hd + f) * Hd + q;
+          WabR[r] = WaT[t] + WbT[t];
+          WbR[r] = WbT[t];
+          Wn1R[r] = Wn1T[t];
+          Wn2R[r] = Wn2T[t];
+        }
+    UP(WabR, WabR) UP(WbR, WbR) UP(Wn1R, Wn1R) UP(Wn2R, Wn2R)
+    // out-edges of every node j: the receivers i of edges j -> i and the CSR index of each edge
+    std::vector<int32_t> optr(p->M + 1, 0), orecv(std::max(p->E, 1)), oedge(std::max(p->E, 1));
+    for (int e = 0; e < p->E; ++e) ++optr[p->h_col[e] + 1];
+    for (int j = 0; j < p->M; ++j) optr[j + 1] += optr[j];
+    std::vector<int32_t> fill(optr.begin(), optr.end() - 1);
+    for (int i = 0; i < p->M; ++i)
+      for (int e = p->h_row_ptr[i]; e < p->h_row_ptr[i + 1]; ++e) {
+        const int q = fill[p->h_col[e]]++;
+        orecv[q] = i;
+        oedge[q] = e;
+      }
+    UP(out_ptr, optr) UP(out_recv, orecv) UP(out_edge, oedge)
+  }
   const size_t NM = (size_t)g.N * g.M;
-  if ((s = dalloc(p, g.h, (size_t)(L + 1) * NM * Hd)) != GNMPC_OK) return s;
+  // hidden states of the L + 1 layers; reverse mode reuses this buffer for three
+  // cotangent arrays of the same size, so it holds at least three
+  if ((s = dalloc(p, g.h, (size_t)std::max(L + 1, 3) * NM * Hd)) != GNMPC_OK) return s;
   if ((s = dalloc(p, g.mask_enc, NM * (Hd / 32))) != GNMPC_OK) return s;
   if ((s = dalloc(p, g.mask_node, (size_t)L * NM * (Hd / 32))) != GNMPC_OK) return s;
   if ((s = dalloc(p, g.mask_edge, (size_t)L * g.N * std::max(g.E, 1) * (Hd / 32))) != GNMPC_OK) return s;
@@ -1921,11 +1953,13 @@ gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w,
   return GNMPC_OK;
 }
 
-gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
-                                  void* fnext, hipStream_t s) {
+// The GNN forward pass at the N stages: hidden states, ReLU masks (and, on the
+// matrix-core path, the per-feature active in-edge counts) in the plan's
+// workspace, next states in g.fnext.
+static gnmpc_status launch_gnn_forward(gnmpc_plan* p, const void* xhat, const void* uhat, FwdArgs& fa,
+                                       hipStream_t s) {
   GnnState& g = *p->gnn;
   const int Hd = g.Hd, N = g.N, M = g.M;
-  FwdArgs fa;
   fa.N = N;
   fa.M = M;
   fa.E = g.E;
@@ -2002,6 +2036,18 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     fwd_dec_kernel<<<ceil_div((long)N * M, 256), 256, 0, s>>>(fa);
   }
   phase_end(p, GNMPC_PH_GNN_FORWARD, s);
+  return GNMPC_OK;
+}
+
+gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
+                                  void* fnext, hipStream_t s) {
+  GnnState& g = *p->gnn;
+  const int Hd = g.Hd, N = g.N, M = g.M;
+  FwdArgs fa;
+  {
+    const gnmpc_status fs = launch_gnn_forward(p, xhat, uhat, fa, s);
+    if (fs != GNMPC_OK) return fs;
+  }
   const long nB = (long)N * M * NBX * p->dims.nu;
   fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
   JvpArgs ja;
@@ -2149,6 +2195,184 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
                                                                (const float*)A, (const float*)B, g.fnext,
                                                                (float*)c, (float*)fnext);
   phase_end(p, GNMPC_PH_GNN_ASSEMBLY, s);
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode through the layers (the gradient of g . f at the N stages,
+// Sec. V-A's model f read backwards).  The forward pass is recomputed first, at
+// the given point, for its ReLU masks; the backward pass then needs no
+// activations, only the masks, and runs layer by layer over every (stage, node)
+// with one workgroup of Hd lanes each (lane q owns feature q of the node's
+// cotangent).  With W_a, W_b the two halves of the edge MLP's first layer
+// (z_ij = W_a h_i + W_b (h_i - h_j) + b_e, m_ij = relu(z_ij)), agg_i = sum_j m_ij,
+// and z_i = W_n1 h_i + W_n2 agg_i + b_n, h'_i = relu(z_i), a round backwards is
+//   zb_i  = mask_i . hb'_i,   hb_i = W_n1' zb_i,   ab_i = W_n2' zb_i        (node)
+//   hb_i += (W_a + W_b)' (cnt_i . ab_i)                 (the receiver side of its in-edges)
+//   hb_j -= W_b' sum_{i: j -> i} D_ij . ab_i            (the sender side of its out-edges)
+// where D_ij is edge (j -> i)'s ReLU mask and cnt_i = sum_j D_ij per feature.
+// Cotangent buffers reuse the forward's hidden-state workspace (the masks carry
+// everything the backward pass needs).
+namespace {
+
+struct VjpArgs {
+  int N, M, E, Hd, L, nu;
+  float dt;
+  const float *g, *decT, *encT;
+  const float *WabR, *WbR, *Wn1R, *Wn2R;          // this round's (for the round kernels)
+  const uint32_t *mask_enc, *mask_node, *mask_edge;  // this round's node and edge masks (round kernels)
+  const int32_t *row_ptr, *out_ptr, *out_recv, *out_edge, *act_of_node;
+  float *hb, *hbt, *ab;  // [N][M][Hd] each
+  float *gx, *gu;
+};
+
+__device__ inline float mask_on(const uint32_t* words, int f) { return (words[f >> 5] >> (f & 31)) & 1u ? 1.f : 0.f; }
+
+// o = W_dec h^L + b_dec, v+ = v + dt o[3:6], p+ = p + dt v+:
+//   vb = g_v + dt g_p,  gx = [g_p; vb] (direct terms),  hb^L = W_dec[3:6]' (dt vb)
+__global__ void vjp_dec_kernel(VjpArgs a) {
+  const int s = blockIdx.x, q = threadIdx.x;
+  const float* gs = a.g + (size_t)s * NBX;
+  float vb[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) vb[r] = gs[3 + r] + a.dt * gs[r];
+  float h = 0.f;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) h += a.decT[q * 6 + 3 + r] * (a.dt * vb[r]);
+  a.hb[(size_t)s * a.Hd + q] = h;
+  if (q < NBX) a.gx[(size_t)s * NBX + q] = q < 3 ? gs[q] : vb[q - 3];
+}
+
+// node update and the receiver side of the in-edges of one round
+__global__ void vjp_node_kernel(VjpArgs a) {
+  extern __shared__ float vs[];  // [Hd] zb, then [Hd] cnt . ab
+  const int s = blockIdx.x, q = threadIdx.x, Hd = a.Hd;
+  const int k = s / a.M, i = s - k * a.M;
+  float* zb = vs;
+  float* yb = vs + Hd;
+  zb[q] = mask_on(a.mask_node + (size_t)s * (Hd / 32), q) * a.hb[(size_t)s * Hd + q];
+  __syncthreads();
+  float hn = 0.f, abq = 0.f;
+  for (int f = 0; f < Hd; ++f) {
+    const float z = zb[f];
+    hn += a.Wn1R[(size_t)f * Hd + q] * z;
+    abq += a.Wn2R[(size_t)f * Hd + q] * z;
+  }
+  float cnt = 0.f;
+  const uint32_t* me = a.mask_edge + (size_t)k * a.E * (Hd / 32);
+  for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) cnt += mask_on(me + (size_t)e * (Hd / 32), q);
+  yb[q] = cnt * abq;
+  __syncthreads();
+  for (int f = 0; f < Hd; ++f) hn += a.WabR[(size_t)f * Hd + q] * yb[f];
+  a.hbt[(size_t)s * Hd + q] = hn;
+  a.ab[(size_t)s * Hd + q] = abq;
+}
+
+// the sender side of the out-edges of one round: hb_j = hbt_j - W_b' sum_i D_ij . ab_i
+__global__ void vjp_edge_kernel(VjpArgs a) {
+  extern __shared__ float vs[];  // [Hd]
+  const int s = blockIdx.x, q = threadIdx.x, Hd = a.Hd;
+  const int k = s / a.M, j = s - k * a.M;
+  const uint32_t* me = a.mask_edge + (size_t)k * a.E * (Hd / 32);
+  float z = 0.f;
+  for (int t = a.out_ptr[j]; t < a.out_ptr[j + 1]; ++t)
+    z += mask_on(me + (size_t)a.out_edge[t] * (Hd / 32), q) * a.ab[((size_t)k * a.M + a.out_recv[t]) * Hd + q];
+  vs[q] = z;
+  __syncthreads();
+  float h = a.hbt[(size_t)s * Hd + q];
+  for (int f = 0; f < Hd; ++f) h -= a.WbR[(size_t)f * Hd + q] * vs[f];
+  a.hb[(size_t)s * Hd + q] = h;
+}
+
+// encoder h0 = relu(W_enc [x; P u] + b): [xb; ub] = W_enc' (mask . hb^0); gx += xb, gu at the actuator
+__global__ void vjp_enc_kernel(VjpArgs a) {
+  extern __shared__ float vs[];  // [9][Hd / 64] wave partial sums
+  const int s = blockIdx.x, q = threadIdx.x, Hd = a.Hd;
+  const int k = s / a.M, i = s - k * a.M;
+  const int nwv = Hd / 64, lane = q & 63, wv = q >> 6;
+  const float zb = mask_on(a.mask_enc + (size_t)s * (Hd / 32), q) * a.hb[(size_t)s * Hd + q];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    float v = a.encT[d * Hd + q] * zb;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) vs[d * nwv + wv] = v;
+  }
+  __syncthreads();
+  if (q < 9) {
+    float v = 0.f;
+    for (int w = 0; w < nwv; ++w) v += vs[q * nwv + w];
+    if (q < NBX) {
+      a.gx[(size_t)s * NBX + q] += v;
+    } else {
+      const int act = a.act_of_node[i];
+      if (act >= 0) a.gu[(size_t)k * a.nu + 3 * act + (q - NBX)] = v;
+    }
+  }
+}
+
+__global__ void copy_f32_kernel(const float* __restrict__ src, float* __restrict__ dst, long n) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+}  // namespace
+
+gnmpc_status launch_gnn_forward_only(gnmpc_plan* p, const void* xhat, const void* uhat, void* fnext, hipStream_t s) {
+  GnnState& g = *p->gnn;
+  FwdArgs fa;
+  const gnmpc_status fs = launch_gnn_forward(p, xhat, uhat, fa, s);
+  if (fs != GNMPC_OK) return fs;
+  const long n = (long)g.N * g.M * NBX;
+  copy_f32_kernel<<<ceil_div(n, 256), 256, 0, s>>>(g.fnext, (float*)fnext, n);
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
+}
+
+gnmpc_status launch_gnn_vjp(gnmpc_plan* p, const void* xhat, const void* uhat, const void* gin, void* gx, void* gu,
+                            hipStream_t s) {
+  GnnState& g = *p->gnn;
+  const int Hd = g.Hd, N = g.N, M = g.M, L = g.L;
+  FwdArgs fa;
+  const gnmpc_status fs = launch_gnn_forward(p, xhat, uhat, fa, s);
+  if (fs != GNMPC_OK) return fs;
+  const size_t NM = (size_t)N * M;
+  VjpArgs va;
+  va.N = N;
+  va.M = M;
+  va.E = g.E;
+  va.Hd = Hd;
+  va.L = L;
+  va.nu = p->dims.nu;
+  va.dt = g.dt;
+  va.g = (const float*)gin;
+  va.decT = g.decT;
+  va.encT = g.encT;
+  va.row_ptr = p->d_row_ptr;
+  va.out_ptr = g.out_ptr;
+  va.out_recv = g.out_recv;
+  va.out_edge = g.out_edge;
+  va.act_of_node = p->d_act_of_node;
+  va.mask_enc = g.mask_enc;
+  va.hb = g.h;  // the hidden states are no longer needed (the buffer holds at least three arrays)
+  va.hbt = g.h + NM * Hd;
+  va.ab = g.h + 2 * NM * Hd;
+  va.gx = (float*)gx;
+  va.gu = (float*)gu;
+  vjp_dec_kernel<<<(unsigned)NM, Hd, 0, s>>>(va);
+  for (int l = L - 1; l >= 0; --l) {
+    const size_t wo = (size_t)l * Hd * Hd;
+    va.WabR = g.WabR + wo;
+    va.WbR = g.WbR + wo;
+    va.Wn1R = g.Wn1R + wo;
+    va.Wn2R = g.Wn2R + wo;
+    va.mask_node = g.mask_node + (size_t)l * NM * (Hd / 32);
+    va.mask_edge = g.mask_edge + (size_t)l * N * g.E * (Hd / 32);
+    vjp_node_kernel<<<(unsigned)NM, Hd, 2 * Hd * sizeof(float), s>>>(va);
+    vjp_edge_kernel<<<(unsigned)NM, Hd, Hd * sizeof(float), s>>>(va);
+  }
+  vjp_enc_kernel<<<(unsigned)NM, Hd, 9 * (Hd / 64) * sizeof(float), s>>>(va);
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
 }

@@ -94,6 +94,8 @@ def lib():
             "gnmpc_vjp": ([vp] * 7, i32),
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
+            "gnmpc_gnn_forward": ([vp, vp, vp, vp, vp], i32),
+            "gnmpc_gnn_vjp": ([vp, vp, vp, vp, vp, vp, vp], i32),
             "gnmpc_solve_box_qp_noalloc": ([i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp],
                                            i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
@@ -227,6 +229,7 @@ class Plan:
         p = MsdParams(prm.k, prm.c, prm.m, prm.dt, prm.k3, prm.gravity, prm.anchor, 0)
         a = _i32(act)
         self._check(lib().gnmpc_model_set_msd(self._h, C.byref(p), _hp(a), len(a)), "model_set_msd")
+        self.model = "msd"
 
     def model_set_gnn(self, W, act, dtype=F32):
         flat = [W.W_enc, W.b_enc]
@@ -238,6 +241,7 @@ class Plan:
         a = _i32(act)
         self._check(lib().gnmpc_model_set_gnn(self._h, C.byref(d), _hp(w), w.size, _hp(a), len(a)),
                     "model_set_gnn")
+        self.model = "gnn"
 
     def rows_set(self, node, stage):
         n, st = _i32(node), _i32(stage)
@@ -251,6 +255,21 @@ class Plan:
                 self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
                 self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True)]
         self._check(lib().gnmpc_linearize(self._h, *args, _stream(stream)), "linearize")
+
+    def gnn_forward(self, xhat, uhat, fnext, stream=None):
+        """fnext[k] = f(xhat[k], uhat[k]) with the plan's GNN (gnmpc_gnn_forward)."""
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(xhat, (N + 1, M, 6), "xhat"), self._dev(uhat, (N, nu), "uhat"),
+                self._dev(fnext, (N, M, 6), "fnext")]
+        self._check(lib().gnmpc_gnn_forward(self._h, *args, _stream(stream)), "gnn_forward")
+
+    def gnn_vjp(self, xhat, uhat, g, gx, gu, stream=None):
+        """gx[k] = (df/dx_k)' g[k], gu[k] = (df/du_k)' g[k] by reverse mode through the
+        GNN's layers (gnmpc_gnn_vjp)."""
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(xhat, (N + 1, M, 6), "xhat"), self._dev(uhat, (N, nu), "uhat"),
+                self._dev(g, (N, M, 6), "g"), self._dev(gx, (N, M, 6), "gx"), self._dev(gu, (N, nu), "gu")]
+        self._check(lib().gnmpc_gnn_vjp(self._h, *args, _stream(stream)), "gnn_vjp")
 
     def jvp(self, A, B, dx, du, out, stream=None):
         """out[k] = A_k dx[k] + B_k du[k] (gnmpc_jvp)."""

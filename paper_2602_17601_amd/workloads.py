@@ -89,13 +89,16 @@ class GNNWeights:
     b_dec: np.ndarray
     dt: float = 0.01
 
-    def rounded_bf16(self) -> "GNNWeights":
-        """Copy with every weight and bias rounded to bfloat16 (RNE), as float64."""
+    def rounded_bf16(self, biases: str = "bf16") -> "GNNWeights":
+        """Copy with every weight rounded to bfloat16 (RNE), as float64; biases
+        rounded to bfloat16 too (``biases='bf16'``) or to float32 (``'f32'``, how
+        the library's BF16 mode holds them: added to FP32 sums)."""
         r = bf16_round
-        return GNNWeights(self.Hd, self.L, r(self.W_enc), r(self.b_enc),
-                          [r(w) for w in self.W_edge], [r(b) for b in self.b_edge],
-                          [r(w) for w in self.W_node], [r(b) for b in self.b_node],
-                          r(self.W_dec), r(self.b_dec), self.dt)
+        rb = r if biases == "bf16" else (lambda b: np.asarray(b, np.float32).astype(np.float64))
+        return GNNWeights(self.Hd, self.L, r(self.W_enc), rb(self.b_enc),
+                          [r(w) for w in self.W_edge], [rb(b) for b in self.b_edge],
+                          [r(w) for w in self.W_node], [rb(b) for b in self.b_node],
+                          r(self.W_dec), rb(self.b_dec), self.dt)
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:

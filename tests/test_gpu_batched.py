@@ -125,7 +125,7 @@ def test_batched_step_matches_oracle_on_serving_shapes():
         eu = np.linalg.norm(u - uref) / max(np.linalg.norm(uref), 1e-12)
         print(P.name, (P.M, P.N, P.nu), "H", eh, "g", eg, "u", eu, "QP", info.status, info.iters)
         assert info.status == gn.QP_SOLVED and eu < 1e-4, (P.name, info.status, eu)
-        Wr = P.gnn.rounded_bf16()
+        Wr = P.gnn.rounded_bf16(biases="f32")
         xh, uh = f64(P.xhat), f64(P.uhat)
         stages = [0, P.N // 2, P.N - 1]
         nodes = sorted({0, 1, int(P.act[0]), int(P.act[-1]), P.M // 3, P.M // 2, P.M - 2, P.M - 1})

@@ -112,7 +112,7 @@ def test_step_chain1000_bf16_matches_oracle():
     print("QP:", info.status, info.iters, "rel u", eu, "active box", int(np.sum(np.abs(uref) > 1 - 1e-6)))
     assert info.status == gn.QP_SOLVED and eu < 1e-4
     # (iii) offsets and next states against the exact model
-    Wr = P.gnn.rounded_bf16()
+    Wr = P.gnn.rounded_bf16(biases="f32")
     xh, uh = _f32(P.xhat), _f32(P.uhat)
     stages = [0, 9, 19]
     _, _, _, _, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, stages=stages)

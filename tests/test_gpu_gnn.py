@@ -108,7 +108,7 @@ def test_gnn_bf16_paper_scale_against_exact_oracle():
     P = wl.gnn1000_bf16()
     plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.BF16)
     assert np.all(np.isfinite(A)) and np.all(np.isfinite(B)) and np.all(np.isfinite(c))
-    Wr = P.gnn.rounded_bf16()
+    Wr = P.gnn.rounded_bf16(biases="f32")
     nodes = [0, 1, 2, 249, 250, 251, 499, 500, 617, 749, 750, 998, 999]
     pairs = [(k, i) for k in range(P.N) for i in nodes]
     prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act, nodes=nodes)
@@ -136,7 +136,7 @@ def test_gnn_bf16_small_graphs_against_exact_oracle(M, hops, L, Hd, n_act, N):
                         L=L, x0_sigma=0.3, walk=0.05)
     plan, xh, uh, A, B, c, f = _gpu_linearize(P, gn.BF16)
     assert np.all(np.isfinite(A)) and np.all(np.isfinite(B)) and np.all(np.isfinite(c))
-    Wr = P.gnn.rounded_bf16()
+    Wr = P.gnn.rounded_bf16(biases="f32")
     prow, pcol, Ar, Br, cr, fr = gnn_linearize(xh, uh, Wr, P.row_ptr, P.col, P.act)
     pairs = [(k, i) for k in range(P.N) for i in range(P.M)]
     bf16_gate(delta_A(A, prow, pcol), delta_A(Ar, prow, pcol), B, Br, prow, _margins(P, Wr, xh, uh, pairs), pairs)

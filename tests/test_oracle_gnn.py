@@ -188,3 +188,49 @@ def test_kink_margin_is_scale_invariant_without_biases():
     m2 = gnn_kink_margin(3.5 * x, 3.5 * u, W, rp, col, act)
     np.testing.assert_allclose(m1, m2, rtol=1e-12)
     assert np.all(m1 > 0) and np.all(np.isfinite(m1))
+
+
+# ----------------------------------------------------------------------------- reverse mode
+
+@pytest.mark.parametrize("M,hops,Hd,L,bias", [(7, 2, 12, 2, 0.0), (9, 1, 8, 3, 0.3), (6, 2, 10, 1, 0.5)])
+def test_reverse_mode_is_the_transpose_of_the_forward_mode_jacobian(M, hops, Hd, L, bias):
+    """gnn_vjp (reverse mode, whole graph) against the dense transpose of the
+    per-node forward-mode Jacobian (a separate algorithm): gx = A' g, gu = B' g."""
+    from oracle.gnn import gnn_vjp
+    rp, col, act, W, x, u = _small(M, hops, Hd, L, seed=M + L, bias_scale=bias)
+    prow, pcol, A, B, c, f = gnn_linearize(x[None], u[None], W, rp, col, act)
+    g = np.random.default_rng(3).normal(size=(M, 6))
+    gx, gu = gnn_vjp(x, u, W, rp, col, act, g)
+    D = _dense_jac(prow, pcol, A[0], M)
+    np.testing.assert_allclose(gx.reshape(-1), D.T @ g.reshape(-1), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(gu, B[0].reshape(6 * M, -1).T @ g.reshape(-1), rtol=0, atol=1e-12)
+
+
+def test_reverse_mode_matches_central_differences_of_g_dot_f():
+    """d/dt g . f(x + t dx, u + t du) at t = 0 equals gx . dx + gu . du."""
+    from oracle.gnn import gnn_vjp
+    rp, col, act, W, x, u = _small(8, 2, 12, 2, seed=21, bias_scale=0.2)
+    rng = np.random.default_rng(4)
+    g = rng.normal(size=x.shape)
+    gx, gu = gnn_vjp(x, u, W, rp, col, act, g)
+    for _ in range(3):
+        dx, du = rng.normal(size=x.shape), rng.normal(size=u.shape)
+        h = 1e-6
+        fp = gnn_forward(x + h * dx, u + h * du, W, rp, col, act)
+        fm = gnn_forward(x - h * dx, u - h * du, W, rp, col, act)
+        fd = np.sum(g * (fp - fm)) / (2 * h)
+        assert abs(fd - (np.sum(gx * dx) + gu @ du)) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_reverse_mode_of_the_affine_model_is_the_weight_product_transposed():
+    """With identity activations the model is affine, so g . f is linear in g and
+    the reverse mode must give exactly the transposed forward-mode products."""
+    from oracle.gnn import gnn_vjp
+    rp, col, act, W, x, u = _small(7, 2, 6, 2, seed=8)
+    prow, pcol, A, B, c, f = gnn_linearize(x[None], u[None], W, rp, col, act, activation="identity")
+    D = _dense_jac(prow, pcol, A[0], 7)
+    for s in range(2):
+        g = np.random.default_rng(10 + s).normal(size=(7, 6))
+        gx, gu = gnn_vjp(x, u, W, rp, col, act, g, activation="identity")
+        np.testing.assert_allclose(gx.reshape(-1), D.T @ g.reshape(-1), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(gu, B[0].reshape(42, -1).T @ g.reshape(-1), rtol=0, atol=1e-12)
