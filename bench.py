@@ -407,6 +407,7 @@ def main():
         "phase_roofline_gnn": phase_rooflines(P, int(plan_g.nnz), phase_avg(ph_g), flops),
         "cpu_baseline": cpu,
         "tangent": tangent_rates(gn, plan_g, bg, args.steps),
+        "simulator": simulator_rate(torch, gn, wl),
     }
     print(json.dumps(out), flush=True)
 
@@ -452,6 +453,34 @@ def tangent_rates(gn, plan, b, reps):
         res["gnn_vjp_reverse_mode"] = {"ms": e0.elapsed_time(e1) / reps,
                                        "note": "forward pass recomputed at the point, then L rounds backwards"}
     return res
+
+
+def simulator_rate(torch, gn, wl, reps=3):
+    """Trajectories of the nonlinear spring-damper chain for the surrogate's data set
+    (4096 trajectories x 100 steps x 1000 nodes, FP32): time per call with HIP events
+    on the stream it runs on, and the HBM rate of its algorithmic traffic (x0 and u
+    read once, every state written once)."""
+    B, T, M = 4096, 100, 1000
+    S = wl.simulator_batch(B, T, M)
+    plan = gn.Plan(M, S.nu, 1, 1, gn.F32)
+    plan.graph_set(S.row_ptr, S.col, 1)
+    plan.model_set_msd(S.msd, S.act)
+    x0 = torch.tensor(S.x0, dtype=torch.float32, device="cuda")
+    u = torch.tensor(S.u, dtype=torch.float32, device="cuda")
+    X = torch.empty(B, T + 1, M, 6, dtype=torch.float32, device="cuda")
+    plan.msd_simulate(x0, u, X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.msd_simulate(x0, u, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 4 * (x0.numel() + u.numel() + X.numel())
+    del X
+    return {"workload": f"{B} trajectories x {T} steps, {M}-node 1-2-hop chain, cubic springs k3=50, gravity",
+            "ms": ms, "node_steps_per_s": B * T * M / (ms * 1e-3), "bytes": nbytes,
+            "GB_per_s": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
 
 def bench_batch(args, torch, gn, wl):

@@ -198,6 +198,19 @@ gnmpc_status gnmpc_rows_set(gnmpc_plan* plan, int32_t n_c, const int32_t* node, 
 gnmpc_status gnmpc_linearize(gnmpc_plan* plan, const void* xhat, const void* uhat,
                              void* A, void* B, void* c, void* fnext, void* stream);
 
+/* Trajectories of the plan's (nonlinear) mass-spring-damper model: for each of B
+ * independent trajectories, X[b][0] = x0[b] and X[b][t+1] = f(X[b][t], u[b][t])
+ * for t < T, f being the semi-implicit Euler step of Sec. V-A eq.
+ * forward_dynamics with the node accelerations of gnmpc_msd_params (the data a
+ * learned GNN surrogate is trained on).  Device arrays of the plan dtype:
+ * x0 [B][M][6], u [B][T][nu], X [B][T+1][M][6] (caller-owned; X may not alias
+ * the inputs).  GNMPC_NOT_READY unless the graph and a mass-spring-damper model
+ * are set; GNMPC_SHAPE for negative B or T; GNMPC_UNSUPPORTED when two states
+ * of the graph do not fit one workgroup's LDS (M up to 3413 in FP32, 1706 in
+ * FP64). */
+gnmpc_status gnmpc_msd_simulate(gnmpc_plan* plan, int32_t B, int32_t T, const void* x0, const void* u,
+                                void* X, void* stream);
+
 /* The GNN one-step model of Sec. V-A (eq. forward_dynamics; semi-implicit
  * Euler) at the N stages, without its Jacobians: fnext[k] = f(xhat[k], uhat[k]).
  * xhat [N+1][M][6] (stage N is not read), uhat [N][nu], fnext [N][M][6]: FP32

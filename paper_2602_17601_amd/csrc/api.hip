@@ -391,6 +391,19 @@ gnmpc_status gnmpc_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, 
   return launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
 }
 
+gnmpc_status gnmpc_msd_simulate(gnmpc_plan* p, int32_t B, int32_t T, const void* x0, const void* u, void* X,
+                                void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (B < 0 || T < 0) return fail(p, GNMPC_SHAPE, "msd_simulate: B and T must be >= 0");
+  if (!p->graph_ready || p->model != 1)
+    return fail(p, GNMPC_NOT_READY, "msd_simulate: graph and mass-spring-damper model must be set");
+  if (B == 0) return GNMPC_OK;
+  if (!x0 || !X || (T > 0 && p->dims.nu > 0 && !u)) return fail(p, GNMPC_INVALID_ARG, "msd_simulate: null array");
+  if (!msd_sim_fits(p)) return fail(p, GNMPC_UNSUPPORTED, "msd_simulate: two states of the graph exceed LDS");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_msd_simulate(p, B, T, x0, u, X, (hipStream_t)stream);
+}
+
 gnmpc_status gnmpc_gnn_forward(gnmpc_plan* p, const void* xhat, const void* uhat, void* fnext, void* stream) {
   if (!p) return GNMPC_INVALID_ARG;
   if (!xhat || !uhat || !fnext) return fail(p, GNMPC_INVALID_ARG, "gnn_forward: null array");

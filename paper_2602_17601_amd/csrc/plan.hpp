@@ -136,6 +136,9 @@ gnmpc_status launch_vjp(gnmpc_plan* p, const void* A, const void* B, const void*
 // gnn.hip
 gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w);
 void gnn_free(gnmpc_plan* p);
+// msd_sim.hip
+bool msd_sim_fits(const gnmpc_plan* p);
+gnmpc_status launch_msd_simulate(gnmpc_plan* p, int B, int T, const void* x0, const void* u, void* X, hipStream_t s);
 gnmpc_status launch_gnn_forward_only(gnmpc_plan* p, const void* xhat, const void* uhat, void* fnext, hipStream_t s);
 gnmpc_status launch_gnn_vjp(gnmpc_plan* p, const void* xhat, const void* uhat, const void* g, void* gx, void* gu,
                             hipStream_t s);

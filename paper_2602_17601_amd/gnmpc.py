@@ -95,6 +95,7 @@ def lib():
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
             "gnmpc_gnn_forward": ([vp, vp, vp, vp, vp], i32),
+            "gnmpc_msd_simulate": ([vp, i32, i32, vp, vp, vp, vp], i32),
             "gnmpc_gnn_vjp": ([vp, vp, vp, vp, vp, vp, vp], i32),
             "gnmpc_solve_box_qp_noalloc": ([i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp],
                                            i32),
@@ -255,6 +256,14 @@ class Plan:
                 self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
                 self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True)]
         self._check(lib().gnmpc_linearize(self._h, *args, _stream(stream)), "linearize")
+
+    def msd_simulate(self, x0, u, X, stream=None):
+        """X[b][0] = x0[b], X[b][t+1] = f(X[b][t], u[b][t]) with the plan's spring-damper
+        model (gnmpc_msd_simulate); x0 [B][M][6], u [B][T][nu], X [B][T+1][M][6]."""
+        B, T = X.shape[0], X.shape[1] - 1
+        args = [self._dev(x0, (B, self.M, 6), "x0"), self._dev(u, (B, T, self.nu), "u"),
+                self._dev(X, (B, T + 1, self.M, 6), "X")]
+        self._check(lib().gnmpc_msd_simulate(self._h, B, T, *args, _stream(stream)), "msd_simulate")
 
     def gnn_forward(self, xhat, uhat, fnext, stream=None):
         """fnext[k] = f(xhat[k], uhat[k]) with the plan's GNN (gnmpc_gnn_forward)."""

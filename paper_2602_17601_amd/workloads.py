@@ -364,3 +364,42 @@ def batch_instances(count: int, seed: int = 4, M_range=(50, 1000), N_range=(10, 
                                 seed=seed * 100003 + i, weight_seed=seed, Hd=128, L=2, x0_sigma=0.02,
                                 walk=0.002, gnn_dtype="bf16"))
     return out
+
+
+@dataclass
+class SimBatch:
+    """Inputs of a batch of simulator trajectories on one chain."""
+    name: str
+    M: int
+    hops: int
+    act: np.ndarray
+    row_ptr: np.ndarray
+    col: np.ndarray
+    msd: MSDParams
+    x0: np.ndarray      # [B][M][6]
+    u: np.ndarray       # [B][T][nu]
+
+    @property
+    def nu(self):
+        return 3 * len(self.act)
+
+
+def simulator_batch(B: int, T: int, M: int = 1000, hops: int = 2, n_act: int = 4, seed: int = 5,
+                    x0_sigma: float = 0.02, step: float = 0.1) -> SimBatch:
+    """Trajectory inputs for the learned-surrogate data set: the nonlinear chain
+    (cubic springs k3 = 50, gravity 9.81, node 0 anchored), x0 ~ N(0, x0_sigma^2)
+    per entry, and inputs as random walks u_0 ~ U(-1, 1), u_{t+1} = clip(u_t +
+    step N(0, 1), -1, 1), all from ``default_rng(seed)`` (x0 first, then u)."""
+    rng = np.random.default_rng(seed)
+    act = actuated_nodes(M, n_act)
+    row_ptr, col = chain_csr(M, hops)
+    nu = 3 * n_act
+    x0 = rng.normal(0.0, x0_sigma, size=(B, M, NBX))
+    u = np.empty((B, T, nu))
+    cur = rng.uniform(-1.0, 1.0, size=(B, nu))
+    for t in range(T):
+        u[:, t] = cur
+        cur = np.clip(cur + step * rng.normal(size=(B, nu)), -1.0, 1.0)
+    return SimBatch(f"sim{seed}_{B}x{T}x{M}", M, hops, act, row_ptr, col,
+                    MSDParams(k3=50.0, gravity=9.81), x0, u)
+
