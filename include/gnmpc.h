@@ -127,6 +127,25 @@ typedef struct {
   double prim_res, dual_res, kappa_est, obj;
 } gnmpc_qp_info;
 
+/* Finiteness report of gnmpc_linearize, written on the device (status values). */
+typedef enum {
+  GNMPC_LIN_FINITE = 0,            /* every input and output entry is finite               */
+  GNMPC_LIN_NONFINITE_INPUT = 1,   /* xhat (stages 0..N-1) or uhat holds a NaN or infinity */
+  GNMPC_LIN_NONFINITE_OUTPUT = 2   /* inputs finite, but A, B, c or fnext is not (e.g. an   */
+                                   /* overflow in the model)                               */
+} gnmpc_lin_status;
+
+/* Device-side report of gnmpc_linearize.  Arrays are numbered 0 xhat, 1 uhat,
+ * 2 A, 3 B, 4 c, 5 fnext; the "first" entry is the lowest element index of the
+ * lowest-numbered array that holds a non-finite value. */
+typedef struct {
+  int32_t status;       /* gnmpc_lin_status                                          */
+  int32_t first_array;  /* array of the first non-finite entry, -1 if none             */
+  int32_t first_stage;  /* its stage k, -1 if none                                     */
+  int32_t first_node;   /* its node (the row node i of an A block), -1 for uhat or none */
+  int64_t nonfinite[6]; /* number of non-finite entries of each array                  */
+} gnmpc_lin_info;
+
 const char* gnmpc_version(void);
 const char* gnmpc_status_string(int32_t status);
 
@@ -194,9 +213,23 @@ gnmpc_status gnmpc_rows_set(gnmpc_plan* plan, int32_t n_c, const int32_t* node, 
  *   B    [N][M][6][nu]   B^i_k = d f^i / d u
  *   c    [N][M][6]       c^i_k = f^i - sum_j A^{ij}_k xhat^j_k - B^i_k uhat_k
  *   fnext[N][M][6]       f(xhat_k, uhat_k), may be NULL
- * ReLU uses the subgradient 0 at 0. */
+ * ReLU uses the subgradient 0 at 0.  info (device, may be NULL): when given, two
+ * further launches after the linearization count the non-finite entries of the
+ * inputs and outputs and write a gnmpc_lin_info (a fixed-order reduction: no
+ * clearing needed, and repeated calls give the same report). */
 gnmpc_status gnmpc_linearize(gnmpc_plan* plan, const void* xhat, const void* uhat,
-                             void* A, void* B, void* c, void* fnext, void* stream);
+                             void* A, void* B, void* c, void* fnext, gnmpc_lin_info* info, void* stream);
+
+/* Roll the linearized dynamics forward (Sec. III-B, the dynamics constraint of
+ * the OCP; Algorithm 1 shifts its trajectory with it): x[0] = x0 and
+ * x[k+1] = A_k x[k] + B_k u[k] + c_k for k < N, i.e. the stacked states
+ * Gamma_u u + Gamma_x of the condensed form.  Device arrays of the plan dtype:
+ * A, B, c as produced by gnmpc_linearize, x0 [M][6], u [N][nu], x [N+1][M][6]
+ * (every entry written; x may not alias the inputs).  One launch per stage on
+ * `stream`.  GNMPC_NOT_READY before gnmpc_graph_set; GNMPC_INVALID_ARG for a
+ * NULL array. */
+gnmpc_status gnmpc_rollout_linear(gnmpc_plan* plan, const void* A, const void* B, const void* c,
+                                  const void* x0, const void* u, void* x, void* stream);
 
 /* Trajectories of the plan's (nonlinear) mass-spring-damper model: for each of B
  * independent trajectories, X[b][0] = x0[b] and X[b][t+1] = f(X[b][t], u[b][t])

@@ -164,6 +164,7 @@ gnmpc_status gnmpc_plan_create(gnmpc_plan** plan, const gnmpc_dims* dims, int32_
   p->qp_bytes = qp_workspace_bytes(N * nu, dims->n_c_max);
   alloc(&p->d_qp, p->qp_bytes);
   alloc((void**)&p->d_qp_flag, 64);
+  alloc(&p->d_check, lin_check_bytes());
   if (st == GNMPC_OK && hipMemset(p->d_qp_flag, 0, 64) != hipSuccess) st = GNMPC_HIP_ERROR;
   if (st != GNMPC_OK) {
     gnmpc_plan_destroy(p);
@@ -240,6 +241,7 @@ void gnmpc_plan_destroy(gnmpc_plan* p) {
   if (p->d_Gx) (void)hipFree(p->d_Gx);
   if (p->d_part) (void)hipFree(p->d_part);
   if (p->d_qp) (void)hipFree(p->d_qp);
+  if (p->d_check) (void)hipFree(p->d_check);
   dfree(p->d_qp_flag);
   delete p;
 }
@@ -381,14 +383,25 @@ gnmpc_status gnmpc_rows_set(gnmpc_plan* p, int32_t n_c, const int32_t* node, con
 }
 
 gnmpc_status gnmpc_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
-                             void* fnext, void* stream) {
+                             void* fnext, gnmpc_lin_info* info, void* stream) {
   if (!p) return GNMPC_INVALID_ARG;
   if (!xhat || !uhat || !A || !B || !c) return fail(p, GNMPC_INVALID_ARG, "linearize: null array");
   if (!p->graph_ready || p->model == 0) return fail(p, GNMPC_NOT_READY, "linearize: graph and model must be set");
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
-  if (p->model == 1) return launch_msd_linearize(p, xhat, uhat, A, B, c, fnext, s);
-  return launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
+  const gnmpc_status st = p->model == 1 ? launch_msd_linearize(p, xhat, uhat, A, B, c, fnext, s)
+                                        : launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
+  if (st != GNMPC_OK || !info) return st;
+  return launch_lin_check(p, xhat, uhat, A, B, c, fnext, info, s);
+}
+
+gnmpc_status gnmpc_rollout_linear(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                                  const void* u, void* x, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!A || !B || !c || !x0 || !u || !x) return fail(p, GNMPC_INVALID_ARG, "rollout_linear: null array");
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "rollout_linear: graph must be set");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_rollout(p, A, B, c, x0, u, x, (hipStream_t)stream);
 }
 
 gnmpc_status gnmpc_msd_simulate(gnmpc_plan* p, int32_t B, int32_t T, const void* x0, const void* u, void* X,
@@ -535,7 +548,7 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
     gnmpc_plan* p = d.plan;
     void* si = (void*)bs.s[i % kBatchStreams];
     const int32_t n = p->dims.N * p->dims.nu;
-    gnmpc_status s = gnmpc_linearize(p, d.xhat, d.uhat, d.A, d.B, d.c, nullptr, si);
+    gnmpc_status s = gnmpc_linearize(p, d.xhat, d.uhat, d.A, d.B, d.c, nullptr, nullptr, si);
     if (s == GNMPC_OK)
       s = gnmpc_condense(p, d.A, d.B, d.c, d.x0, d.Q, d.Q_full, d.q, d.R, d.r, d.rowC, d.rowd, d.H, d.g, d.Ct,
                          d.dt, nullptr, si);

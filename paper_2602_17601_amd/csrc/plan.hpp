@@ -58,6 +58,9 @@ struct gnmpc_plan {
   size_t qp_bytes = 0;
   int32_t* d_qp_flag = nullptr;
 
+  // per-block partial counts of the finiteness check of gnmpc_linearize
+  void* d_check = nullptr;
+
   // per-phase timers
   bool timers_on = false;
   std::vector<hipEvent_t> ev_start[GNMPC_PH_COUNT], ev_stop[GNMPC_PH_COUNT];
@@ -133,6 +136,12 @@ gnmpc_status launch_jvp(gnmpc_plan* p, const void* A, const void* B, const void*
                         hipStream_t s);
 gnmpc_status launch_vjp(gnmpc_plan* p, const void* A, const void* B, const void* g, void* gx, void* gu,
                         hipStream_t s);
+gnmpc_status launch_rollout(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                            const void* u, void* x, hipStream_t s);
+// check.hip
+size_t lin_check_bytes();
+gnmpc_status launch_lin_check(gnmpc_plan* p, const void* xhat, const void* uhat, const void* A, const void* B,
+                              const void* c, const void* fnext, gnmpc_lin_info* info, hipStream_t s);
 // gnn.hip
 gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w);
 void gnn_free(gnmpc_plan* p);

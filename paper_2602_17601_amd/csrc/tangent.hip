@@ -3,7 +3,10 @@
 // of x_{k+1} = f(x_k, u_k), the JVP is t_k = A_k dx_k + B_k du_k and the VJP is
 // (A_k' g_k, B_k' g_k).  Every output element is one thread's fixed-order sum, so
 // results do not depend on scheduling; the VJP's state part walks the pattern by
-// column (the entries of column node j in increasing order).
+// column (the entries of column node j in increasing order).  The linear rollout
+// x_{k+1} = A_k x_k + B_k u_k + c_k (Sec. III-B, the dynamics constraint of the
+// OCP; the shift of Algorithm 1 needs it) is the JVP's row sum plus the offset,
+// one launch per stage since stage k+1 reads stage k.
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -76,6 +79,48 @@ __global__ void __launch_bounds__(kVjpThreads) vjp_u_kernel(int N, int M, int nu
   if (threadIdx.x == 0) gu[(size_t)k * nu + d] = red[0];
 }
 
+// x[k+1][i][r] = sum_e A[k][e][r][:] x[k][pcol[e]] + B[k][i][r][:] u[k] + c[k][i][r], the same
+// fixed order as the oracle's block rollout; the stage-0 launch reads x0 and also
+// writes x[0] = x0 (its readers read x0, so no thread waits for another)
+template <typename T>
+__global__ void rollout_stage_kernel(int k, int M, int nu, long nnz, const int32_t* __restrict__ prow,
+                                     const int32_t* __restrict__ pcol, const T* __restrict__ A,
+                                     const T* __restrict__ B, const T* __restrict__ c, const T* __restrict__ xk,
+                                     const T* __restrict__ u, T* __restrict__ x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * NBX) return;
+  const int r = t % NBX, i = t / NBX;
+  const size_t sM = (size_t)M * NBX;
+  const T* Ak = A + (size_t)k * nnz * 36;
+  T v = T(0);
+  for (int e = prow[i]; e < prow[i + 1]; ++e) {
+    const T* a = Ak + (size_t)e * 36 + r * 6;
+    const T* xj = xk + (size_t)pcol[e] * NBX;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v += a[q] * xj[q];
+  }
+  const T* b = B + (((size_t)k * M + i) * NBX + r) * nu;
+  const T* uk = u + (size_t)k * nu;
+  for (int d = 0; d < nu; ++d) v += b[d] * uk[d];
+  v += c[(size_t)k * sM + t];
+  if (k == 0) x[t] = xk[t];
+  x[(size_t)(k + 1) * sM + t] = v;
+}
+
+template <typename T>
+gnmpc_status run_rollout(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                         const void* u, void* x, hipStream_t s) {
+  const int N = p->dims.N, M = p->M, nu = p->dims.nu;
+  const int n = M * NBX;
+  for (int k = 0; k < N; ++k) {
+    const T* xk = k == 0 ? (const T*)x0 : (const T*)x + (size_t)k * n;
+    rollout_stage_kernel<T><<<ceil_div(n, 256), 256, 0, s>>>(k, M, nu, p->nnz, p->d_prow, p->d_pcol, (const T*)A,
+                                                            (const T*)B, (const T*)c, xk, (const T*)u, (T*)x);
+    GNMPC_HIP_TRY(p, hipGetLastError());
+  }
+  return GNMPC_OK;
+}
+
 template <typename T>
 gnmpc_status run_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
                      hipStream_t s) {
@@ -111,6 +156,12 @@ gnmpc_status launch_vjp(gnmpc_plan* p, const void* A, const void* B, const void*
                         hipStream_t s) {
   if (p->dims.dtype == GNMPC_F64) return run_vjp<double>(p, A, B, g, gx, gu, s);
   return run_vjp<float>(p, A, B, g, gx, gu, s);
+}
+
+gnmpc_status launch_rollout(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                            const void* u, void* x, hipStream_t s) {
+  if (p->dims.dtype == GNMPC_F64) return run_rollout<double>(p, A, B, c, x0, u, x, s);
+  return run_rollout<float>(p, A, B, c, x0, u, x, s);
 }
 
 }  // namespace gnmpc

@@ -18,6 +18,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgnmpc.s
 OK, INVALID_ARG, BAD_GRAPH, SHAPE, UNSUPPORTED, HIP_ERROR, BAD_CONSTRAINT, NOT_READY, NO_DEVICE = range(9)
 F64, F32, BF16 = 0, 1, 2
 QP_SOLVED, QP_MAXITER, QP_PRIMAL_INFEASIBLE, QP_NONFINITE, QP_NOT_PD = range(5)
+LIN_FINITE, LIN_NONFINITE_INPUT, LIN_NONFINITE_OUTPUT = range(3)
+LIN_ARRAYS = ("xhat", "uhat", "A", "B", "c", "fnext")
 PHASES = ("gnn_forward", "gnn_jacobian", "gnn_assembly", "msd_linearize", "condense_propagate",
           "condense_gram", "condense_rows", "qp", "gnn_stage_images")
 
@@ -57,6 +59,14 @@ class QpInfo(C.Structure):
 QP_INFO_BYTES = C.sizeof(QpInfo)
 
 
+class LinInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("first_array", C.c_int32), ("first_stage", C.c_int32),
+                ("first_node", C.c_int32), ("nonfinite", C.c_int64 * 6)]
+
+
+LIN_INFO_BYTES = C.sizeof(LinInfo)
+
+
 class StepDesc(C.Structure):
     _fields_ = [("plan", C.c_void_p)] + [(f, C.c_void_p) for f in (
         "xhat", "uhat", "x0", "Q", "q", "R", "r", "rowC", "rowd", "lb", "ub", "lc", "uc")] + [
@@ -89,7 +99,8 @@ def lib():
             "gnmpc_model_set_msd": ([vp, P(MsdParams), vp, i32], i32),
             "gnmpc_model_set_gnn": ([vp, P(GnnDesc), vp, i64, vp, i32], i32),
             "gnmpc_rows_set": ([vp, i32, vp, vp], i32),
-            "gnmpc_linearize": ([vp] + [vp] * 7, i32),
+            "gnmpc_linearize": ([vp] + [vp] * 8, i32),
+            "gnmpc_rollout_linear": ([vp] * 8, i32),
             "gnmpc_jvp": ([vp] * 7, i32),
             "gnmpc_vjp": ([vp] * 7, i32),
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
@@ -250,12 +261,23 @@ class Plan:
         self.n_c = len(n)
 
     # ---- hot path
-    def linearize(self, xhat, uhat, A, B, c, fnext=None, stream=None):
+    def linearize(self, xhat, uhat, A, B, c, fnext=None, info=None, stream=None):
+        """A, B, c (and fnext) at the N points (gnmpc_linearize); info, a uint8 tensor of
+        LIN_INFO_BYTES on the device, receives the finiteness report (decode with lin_info)."""
         M, N, nu = self.M, self.N, self.nu
         args = [self._dev(xhat, (N + 1, M, 6), "xhat"), self._dev(uhat, (N, nu), "uhat"),
                 self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
-                self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True)]
+                self._dev(c, (N, M, 6), "c"), self._dev(fnext, (N, M, 6), "fnext", allow_none=True),
+                self._dev(info, (LIN_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)]
         self._check(lib().gnmpc_linearize(self._h, *args, _stream(stream)), "linearize")
+
+    def rollout_linear(self, A, B, c, x0, u, x, stream=None):
+        """x[0] = x0, x[k+1] = A_k x[k] + B_k u[k] + c_k (gnmpc_rollout_linear)."""
+        M, N, nu = self.M, self.N, self.nu
+        args = [self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(c, (N, M, 6), "c"), self._dev(x0, (M, 6), "x0"), self._dev(u, (N, nu), "u"),
+                self._dev(x, (N + 1, M, 6), "x")]
+        self._check(lib().gnmpc_rollout_linear(self._h, *args, _stream(stream)), "rollout_linear")
 
     def msd_simulate(self, x0, u, X, stream=None):
         """X[b][0] = x0[b], X[b][t+1] = f(X[b][t], u[b][t]) with the plan's spring-damper
@@ -413,3 +435,8 @@ def qp_info(t):
     """Decode a device info buffer (uint8 tensor of QP_INFO_BYTES) after a sync."""
     b = bytes(t.cpu().numpy().tobytes())
     return QpInfo.from_buffer_copy(b)
+
+
+def lin_info(t):
+    """Decode a linearization report (uint8 tensor of LIN_INFO_BYTES) after a sync."""
+    return LinInfo.from_buffer_copy(bytes(t.cpu().numpy().tobytes()))

@@ -101,11 +101,18 @@ def test_plan_create_without_a_gpu_reports_no_device():
 def test_null_plan_calls_are_rejected():
     L = gn.lib()
     assert L.gnmpc_graph_set(None, None, None, 0, 0, 1) == gn.INVALID_ARG
-    assert L.gnmpc_linearize(None, None, None, None, None, None, None, None) == gn.INVALID_ARG
+    assert L.gnmpc_linearize(None, None, None, None, None, None, None, None, None) == gn.INVALID_ARG
+    assert L.gnmpc_rollout_linear(None, None, None, None, None, None, None, None) == gn.INVALID_ARG
     assert L.gnmpc_rows_set(None, 0, None, None) == gn.INVALID_ARG
     s = gn.AdmmSettings()
     assert L.gnmpc_solve_box_qp(None, 1, None, None, None, None, 0, None, None, None, C.byref(s), None, None,
                                 None) == gn.INVALID_ARG
+
+
+def test_linearization_report_layout_matches_the_header():
+    """gnmpc_lin_info: four int32 then six int64 counts (48 bytes, no padding)."""
+    assert gn.LIN_INFO_BYTES == 4 * 4 + 6 * 8
+    assert gn.LinInfo.nonfinite.offset == 16
 
 
 def test_noalloc_qp_validates_before_touching_the_gpu():
