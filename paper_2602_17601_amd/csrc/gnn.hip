@@ -1133,11 +1133,18 @@ struct FwdMfmaArgs {
 constexpr int kFwdCT = 2;
 __host__ __device__ constexpr int fwd_groups(int Hd) { return Hd <= 128 ? kFwdCT : 1; }
 // Dynamic LDS of fwd_mfma_layer_kernel: three bf16 planes of the layer input and
-// of the aggregates, the FP32 W_b h of every column, then the staged mask groups.
+// of the aggregates, the FP32 W_b h of every column (16-byte chunks XOR-swizzled
+// by column, so the 16 columns of a wave read 16 distinct bank groups), the
+// staged mask groups, then the tile's lists (sender column of each edge; first
+// edge, edge count and node of each column).
 __host__ __device__ constexpr size_t fwd_planes_bytes(int Hd) { return (size_t)16 * fwd_groups(Hd) * Hd * 2; }
+__host__ __device__ constexpr size_t fwd_mask_bytes(int Hd, int fedge_cap) {
+  return ((size_t)(fedge_cap + 16 * fwd_groups(Hd)) * (Hd / 4) + 15) / 16 * 16;
+}
 size_t fwd_lds_bytes(int Hd, int fedge_cap) {
   const int NC = 16 * fwd_groups(Hd);
-  return 6 * fwd_planes_bytes(Hd) + (size_t)NC * Hd * 4 + (size_t)(fedge_cap + NC) * (Hd / 4);
+  return 6 * fwd_planes_bytes(Hd) + (size_t)NC * Hd * 4 + fwd_mask_bytes(Hd, fedge_cap) +
+         (size_t)(fedge_cap + 3 * NC) * 4;
 }
 
 template <int MT>
@@ -1150,12 +1157,45 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   unsigned char* Ag = Hs + 3 * PL;                         // [3][NC][CB] aggregates: hi, mid, lo
   float* Ybs = reinterpret_cast<float*>(Ag + 3 * PL);      // [NC][Hd] W_b h per column
   unsigned char* qmask = reinterpret_cast<unsigned char*>(Ybs + NC * Hd);  // [edges + NC][NQ] 4-bit groups
+  int32_t* esrc = reinterpret_cast<int32_t*>(qmask + fwd_mask_bytes(Hd, a.fedge_cap));  // [edges]
+  int32_t* epre = esrc + a.fedge_cap;                                                 // [NC]
+  int32_t* ecnt = epre + NC;                                                          // [NC]
+  int32_t* cnode = ecnt + NC;                                                         // [NC]
+  auto ysw = [](int c, int f0) { return c * Hd + ((((f0 >> 2) ^ c) & (NQ - 1)) << 2); };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* fm = a.fmeta + (size_t)tile * 4;
   const int nt = fm[0], eb = fm[1], ec = fm[2];
   const int32_t* cols = a.fcols + (size_t)tile * NC;
+  // Weight fragments (lane: row 16 m + col of the wave's rows, 8 inputs from
+  // 32 kb + 8 grp).  For Hd <= 128 the edge GEMMs' fragments of every k-block are
+  // requested first, so they arrive while the columns are gathered, and the node
+  // update's before the edge terms; Hd = 256 has no registers for that and loads
+  // them per k-block.
+  constexpr bool HOIST = MT <= 2;
+  constexpr int KH = HOIST ? KB : 1;
+  auto load_w = [&](bf16x8_t (&dst)[MT], const uint16_t* W, int kb) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int row = wave * RW + 16 * m + col;
+      dst[m] = *reinterpret_cast<const bf16x8_t*>(W + (size_t)row * Hd + kb * 32 + grp * 8);
+    }
+  };
+  bf16x8_t wa[KH][MT], wb[KH][MT];
+  if constexpr (HOIST) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      load_w(wa[kb], a.Wa, kb);
+      load_w(wb[kb], a.Wb, kb);
+    }
+  }
+  for (int t = threadIdx.x; t < ec; t += 256) esrc[t] = a.fesrc[eb + t];
+  for (int t = threadIdx.x; t < NC; t += 256) {
+    epre[t] = a.fepre[(size_t)tile * NC + t];
+    ecnt[t] = t < nt ? a.fecnt[(size_t)tile * NC + t] : 0;
+    cnode[t] = cols[t];
+  }
   // ---- gather the input columns, 8 features (one 16-byte chunk per plane) per item
   for (int t = threadIdx.x; t < NC * (Hd / 8); t += 256) {
     const int c = t / (Hd / 8), ch = t % (Hd / 8);
@@ -1189,12 +1229,10 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       }
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      bf16x8_t wa[MT], wb[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int row = wave * RW + 16 * m + col;
-        wa[m] = *reinterpret_cast<const bf16x8_t*>(a.Wa + (size_t)row * Hd + kb * 32 + grp * 8);
-        wb[m] = *reinterpret_cast<const bf16x8_t*>(a.Wb + (size_t)row * Hd + kb * 32 + grp * 8);
+      const int ki = HOIST ? kb : 0;
+      if constexpr (!HOIST) {
+        load_w(wa[0], a.Wa, kb);
+        load_w(wb[0], a.Wb, kb);
       }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -1207,8 +1245,8 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
         for (int pl = 2; pl >= 0; --pl)
 #pragma unroll
           for (int m = 0; m < MT; ++m) {
-            ay[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[m], bfr[pl], ay[ct][m], 0, 0, 0);
-            ap[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[m], bfr[pl], ap[ct][m], 0, 0, 0);
+            ay[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[ki][m], bfr[pl], ay[ct][m], 0, 0, 0);
+            ap[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ki][m], bfr[pl], ap[ct][m], 0, 0, 0);
           }
       }
     }
@@ -1217,18 +1255,26 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int f0 = wave * RW + 16 * m + 4 * grp;
-        *reinterpret_cast<floatx4_t*>(Ybs + (16 * ct + col) * Hd + f0) = ay[ct][m];
+        *reinterpret_cast<floatx4_t*>(Ybs + ysw(16 * ct + col, f0)) = ay[ct][m];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ap[ct][m][i] += ay[ct][m][i] + a.be[f0 + i];
       }
+  }
+  bf16x8_t w1[KH][MT], w2[KH][MT];
+  if constexpr (HOIST) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      load_w(w1[kb], a.Wn1, kb);
+      load_w(w2[kb], a.Wn2, kb);
+    }
   }
   __syncthreads();
   // ---- edge terms of the target columns: agg = sum_j relu(P_i - Yb_j)
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = 16 * ct + col;
-    const int e0 = a.fepre[(size_t)tile * NC + c];
-    const int ne = c < nt ? a.fecnt[(size_t)tile * NC + c] : 0;
+    const int e0 = epre[c];
+    const int ne = ecnt[c];
     float agg[MT][4];
     uint32_t ncnt[MT];  // 4 byte counters: in-edges whose ReLU is on, per feature
 #pragma unroll
@@ -1238,11 +1284,11 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       for (int i = 0; i < 4; ++i) agg[m][i] = 0.f;
     }
     for (int t = 0; t < ne; ++t) {
-      const int sc = a.fesrc[eb + e0 + t];
+      const int sc = esrc[e0 + t];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int f0 = wave * RW + 16 * m + 4 * grp;
-        const floatx4_t yb = *reinterpret_cast<const floatx4_t*>(Ybs + sc * Hd + f0);
+        const floatx4_t yb = *reinterpret_cast<const floatx4_t*>(Ybs + ysw(sc, f0));
         uint32_t nib = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1256,7 +1302,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       }
     }
     if (c < nt) {
-      const int node = cols[c];
+      const int node = cnode[c];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int f0 = wave * RW + 16 * m + 4 * grp;
@@ -1285,12 +1331,10 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       for (int m = 0; m < MT; ++m) acc[ct][m] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      bf16x8_t w1[MT], w2[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int row = wave * RW + 16 * m + col;
-        w1[m] = *reinterpret_cast<const bf16x8_t*>(a.Wn1 + (size_t)row * Hd + kb * 32 + grp * 8);
-        w2[m] = *reinterpret_cast<const bf16x8_t*>(a.Wn2 + (size_t)row * Hd + kb * 32 + grp * 8);
+      const int ki = HOIST ? kb : 0;
+      if constexpr (!HOIST) {
+        load_w(w1[0], a.Wn1, kb);
+        load_w(w2[0], a.Wn2, kb);
       }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -1306,8 +1350,8 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
         for (int pl = 2; pl >= 0; --pl)
 #pragma unroll
           for (int m = 0; m < MT; ++m) {
-            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], bh[pl], acc[ct][m], 0, 0, 0);
-            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[m], bg[pl], acc[ct][m], 0, 0, 0);
+            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[ki][m], bh[pl], acc[ct][m], 0, 0, 0);
+            acc[ct][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[ki][m], bg[pl], acc[ct][m], 0, 0, 0);
           }
       }
     }
@@ -1315,7 +1359,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
     for (int ct = 0; ct < CT; ++ct) {
       const int c = 16 * ct + col;
       if (c < nt) {
-        const int node = cols[c];
+        const int node = cnode[c];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           const int f0 = wave * RW + 16 * m + 4 * grp;
@@ -1343,7 +1387,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) word |= (uint32_t)(qmask[(size_t)srow * NQ + wd * 8 + q] & 0xF) << (4 * q);
     if (r < ec) a.mask_edge[((size_t)k * a.E + a.feid[eb + r]) * HW + wd] = word;
-    else a.mask_node[((size_t)k * a.M + cols[r - ec]) * HW + wd] = word;
+    else a.mask_node[((size_t)k * a.M + cnode[r - ec]) * HW + wd] = word;
   }
 }
 
