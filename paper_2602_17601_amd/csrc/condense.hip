@@ -486,7 +486,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   const float* qk = q + (size_t)k * sh.M * NBX;
   const bool diag = ta == tb;
   float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT, rows (kRB / 4) (threadIdx.x / kT) .. + kRB / 4 - 1 of each block
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int qa = 32 * (wave >> 1), qb = 32 * (wave & 1);
   const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
   cfloatx4 acc[2][2];

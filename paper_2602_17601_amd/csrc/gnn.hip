@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(256) jvp_mfma_kernel(MfmaArgs a) {
   unsigned char* R1 = smem_raw;                                            // [cap1][16] bf16 columns
   unsigned char* R2 = smem_raw + (size_t)a.cap1 * kCols * CB1;            // [cap2][16] fp32 columns
   int32_t* SP = reinterpret_cast<int32_t*>(R2 + (size_t)a.cap2 * kCols * CB2);  // staged program + masks
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int col = lane & 15, grp = lane >> 4;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* mt = a.meta + (size_t)tile * a.meta_stride;
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(Hd * 4) jvp_mfma2_kernel(Mfma2Args a) {
   uint32_t* ST = reinterpret_cast<uint32_t*>(AG + (size_t)a.cap2 * kCols * CB);  // stage words
   float* DT = reinterpret_cast<float*>(ST + a.stage_words);                    // decoder rows 3..5, [3][Hd]
   float* ET = DT + 3 * Hd;                                                     // encoder weights [9][Hd]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int col = lane & 15, grp = lane >> 4;
   // phase A: wave w owns output features [16 w, 16 w + 16) of every node.  The
   // tangents are the A operand, so lane (n, g) holds feature fA = 16 w + n of
@@ -1162,7 +1162,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   int32_t* ecnt = epre + NC;                                                          // [NC]
   int32_t* cnode = ecnt + NC;                                                         // [NC]
   auto ysw = [](int c, int f0) { return c * Hd + ((((f0 >> 2) ^ c) & (NQ - 1)) << 2); };
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int col = lane & 15, grp = lane >> 4;
   const int tile = blockIdx.x, k = blockIdx.y;
   const int32_t* fm = a.fmeta + (size_t)tile * 4;

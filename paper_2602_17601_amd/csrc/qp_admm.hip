@@ -28,6 +28,9 @@ namespace {
 
 constexpr int kQpThreads = 512;
 constexpr int kWaves = kQpThreads / 64;
+// This lane's wave in the workgroup, as a wave-uniform (scalar) value, so loops
+// and tests over waves compile to scalar branches instead of exec-mask updates.
+__device__ inline int wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 template <typename Tin>
 struct QpArgs {
@@ -90,7 +93,7 @@ __device__ __attribute__((always_inline)) inline void wave_sync() {
 template <typename T>
 __device__ __attribute__((always_inline)) T block_max(T v, T* red) {
   v = wave_max(v);
-  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int w = wave_index(), l = threadIdx.x & 63;
   __syncthreads();
   if (l == 0) red[w] = v;
   __syncthreads();
@@ -101,7 +104,7 @@ __device__ __attribute__((always_inline)) T block_max(T v, T* red) {
 template <typename T>
 __device__ __attribute__((always_inline)) T block_sum(T v, T* red) {
   v = wave_sum(v);
-  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int w = wave_index(), l = threadIdx.x & 63;
   __syncthreads();
   if (l == 0) red[w] = v;
   __syncthreads();
@@ -132,7 +135,7 @@ __device__ void block_argmax_abs(const T* v, int n, T* red, T& vmax, int& imax) 
       bi = oi;
     }
   }
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = wave_index(), l = threadIdx.x & 63;
   __syncthreads();
   if (l == 0) {
     red[w] = bv;
@@ -288,7 +291,7 @@ __device__ inline void ld4(const double* p, double (&o)[4]) {
 // out = W v over the first n rows.
 template <typename T>
 __device__ void tri_mv(const Work<T>& w, int n, const T* v, T* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int nb = nblocks(n), r = lane >> 2, c4 = (lane & 3) * 4;
   for (int job = wave; job < (nb + 1) / 2; job += kWaves) {
     for (int half = 0; half < 2; ++half) {
@@ -312,7 +315,7 @@ __device__ void tri_mv(const Work<T>& w, int n, const T* v, T* out) {
 // out = W' v over the first n rows.
 template <typename T>
 __device__ void tri_mv_t(const Work<T>& w, int n, const T* v, T* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int nb = nblocks(n), r = lane >> 2, c4 = (lane & 3) * 4;
   for (int job = wave; job < (nb + 1) / 2; job += kWaves) {
     for (int half = 0; half < 2; ++half) {
@@ -499,8 +502,9 @@ __device__ inline void bsub(T* C, const T acc[4]) {
 //   b. panel L_IJ = K_IJ D' (I > J); W row J: W_JK <- D W_JK (K < J);
 //   c. trailing K_IK -= L_IJ L_KJ' (J < K <= I) and W_IK -= L_IJ W_JK (I > J,
 //      K < J).  Wave 0 takes the update of block (J+1, J+1) first and then
-//      factors and inverts it (lookahead) while the other waves do the rest,
-//      two block products at a time.
+//      factors and inverts it (lookahead) while the other waves do the rest:
+//      strips of up to four target blocks of one block row I, which share the
+//      operand L_IJ, so a wave keeps four independent product chains in flight.
 // At the end block (I, K) holds W_IK.  False if K is not positive definite.
 template <typename T>
 __device__ inline void bmma_rt(T acc[4], const T* A, const T* B, bool trans) {
@@ -508,9 +512,56 @@ __device__ inline void bmma_rt(T acc[4], const T* A, const T* B, bool trans) {
   else bmma<false>(acc, A, B);
 }
 
+// C_q -= A op(B_q) for the cnt (1..4, wave-uniform) blocks of a strip: C_q are
+// consecutive blocks of one block row (stride 256 elements), B_q given one by one.
+// Each block's product is the same as bmma's; FP32 interleaves the four MFMA chains.
+template <bool TRANS>
+__device__ inline void strip_sub(const float* A, const float* const (&B)[4], float* C, int cnt) {
+  const int l = threadIdx.x & 63, r = l & 15, kq = l >> 4;
+  const float4 a4 = *reinterpret_cast<const float4*>(A + r * 16 + 4 * kq);
+  const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+  float b[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < cnt) {
+      const float* Bq = B[q];
+      if (TRANS) {
+        const float4 b4 = *reinterpret_cast<const float4*>(Bq + r * 16 + 4 * kq);
+        b[q][0] = b4.x; b[q][1] = b4.y; b[q][2] = b4.z; b[q][3] = b4.w;
+      } else {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) b[q][st] = Bq[(4 * kq + st) * 16 + r];
+      }
+    }
+  }
+  qfloatx4 c[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = qfloatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < cnt) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][st], av[st], c[q], 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < cnt) {
+      const float acc[4] = {c[q][0], c[q][1], c[q][2], c[q][3]};
+      bsub(C + q * 256, acc);
+    }
+  }
+}
+template <bool TRANS>
+__device__ inline void strip_sub(const double* A, const double* const (&B)[4], double* C, int cnt) {
+  for (int q = 0; q < cnt; ++q) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bmma<TRANS>(acc, A, B[q]);
+    bsub(C + q * 256, acc);
+  }
+}
+
 template <typename T>
 __device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, int nb) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   if (wave == 0) {
     const bool ok = diag_factor_invert(w.mat, w.part);
     if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
@@ -549,51 +600,38 @@ __device__ __attribute__((always_inline)) bool factor_invert(const Work<T>& w, i
     }
     __syncthreads();
     if (m == 0) break;
-    // ---- c: task 0 is the pair (J+1, J+1); tasks 1.. are the other trailing pairs, then the W updates
-    const int npairs = m * (m + 1) / 2, ntask = npairs + m * J;
-    auto decode = [&](int t, const T*& A, const T*& B, T*& C, bool& trans) {
-      if (t < npairs) {
-        int ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-        while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-        while (ii * (ii + 1) / 2 > t) --ii;
-        const int kk = t - ii * (ii + 1) / 2;
-        A = w.mat + bo(J + 1 + ii, J);
-        B = w.mat + bo(J + 1 + kk, J);
-        C = w.mat + bo(J + 1 + ii, J + 1 + kk);
-        trans = true;
-      } else {
-        const int u = t - npairs, I = J + 1 + u / J, K = u % J;
-        A = w.mat + bo(I, J);
-        B = w.mat + bo(J, K);
-        C = w.mat + bo(I, K);
-        trans = false;
-      }
-    };
+    // ---- c: wave 0 updates (J+1, J+1) and factors it; the other waves take the
+    // strips of each block row I > J in turn: trailing blocks K = J+1..I (block
+    // (J+1, J+1) excluded), then W blocks K = 0..J-1, four at a time
     if (wave == 0) {
-      const T *A, *B;
-      T* C;
-      bool tr;
-      decode(0, A, B, C, tr);
       T acc[4] = {T(0), T(0), T(0), T(0)};
-      bmma_rt(acc, A, B, tr);
-      bsub(C, acc);
+      const T* LJ1 = w.mat + bo(J + 1, J);
+      bmma<true>(acc, LJ1, LJ1);
+      bsub(w.mat + bo(J + 1, J + 1), acc);
       wave_sync();
       const bool ok = diag_factor_invert(w.mat + bo(J + 1, J + 1), w.part);
       if (lane == 0) w.scal[0] = ok ? T(1) : T(-1);
     } else {
       constexpr int S = kWaves - 1;
-      for (int t = wave; t < ntask; t += 2 * S) {
-        const bool two = t + S < ntask;
-        const T *A0, *B0, *A1 = nullptr, *B1 = nullptr;
-        T *C0, *C1 = nullptr;
-        bool tr0, tr1 = false;
-        decode(t, A0, B0, C0, tr0);
-        if (two) decode(t + S, A1, B1, C1, tr1);
-        T acc0[4] = {T(0), T(0), T(0), T(0)}, acc1[4] = {T(0), T(0), T(0), T(0)};
-        bmma_rt(acc0, A0, B0, tr0);
-        if (two) bmma_rt(acc1, A1, B1, tr1);
-        bsub(C0, acc0);
-        if (two) bsub(C1, acc1);
+      int t = 0;
+      for (int I = J + 1; I < nb; ++I) {
+        const T* A = w.mat + bo(I, J);
+        for (int K = (I == J + 1 ? J + 2 : J + 1); K <= I; K += 4, ++t) {
+          if (t % S != wave - 1) continue;
+          const int cnt = min(4, I + 1 - K);
+          const T* B[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) B[q] = w.mat + bo(q < cnt ? K + q : K, J);
+          strip_sub<true>(A, B, w.mat + bo(I, K), cnt);
+        }
+        for (int K = 0; K < J; K += 4, ++t) {
+          if (t % S != wave - 1) continue;
+          const int cnt = min(4, J - K);
+          const T* B[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) B[q] = w.mat + bo(J, q < cnt ? K + q : K);
+          strip_sub<false>(A, B, w.mat + bo(I, K), cnt);
+        }
       }
     }
     __syncthreads();
@@ -637,7 +675,7 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
 // (lanes: 16 columns x 4 row quarters), so the sum order is fixed.
 template <typename T>
 __device__ T knorm1(const Work<T>& w, int n) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int nb = nblocks(n), cc = lane & 15, rq = lane >> 4;
   T nrm = T(0);
   for (int B = wave; B < nb; B += kWaves) {
@@ -712,7 +750,7 @@ constexpr int kMJ = 16;  // columns per lane
 constexpr int kMQ = kMJ / 4;  // 4-column chunks per lane
 
 __device__ inline int rp_row(int g, int h) {
-  return 4 * ((threadIdx.x >> 6) + kWaves * (g + kMG * h)) + ((threadIdx.x & 63) >> 4);
+  return 4 * (wave_index() + kWaves * (g + kMG * h)) + ((threadIdx.x & 63) >> 4);
 }
 __device__ inline int rp_col4(int j) { return 4 * (threadIdx.x & 15) + 64 * j; }
 
@@ -762,7 +800,7 @@ __device__ inline void rp_axpy(float (&acc)[kMJ], const float (&R)[kMG][kMJ], in
   for (int j = 0; j < kMJ; ++j) acc[j] += R[g][j] * wv;
 }
 __device__ inline void rp_flush(float (&acc)[kMJ], float* part, int n) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
 #pragma unroll
   for (int j = 0; j < kMJ; ++j) {
     float v = acc[j];
@@ -781,8 +819,11 @@ __device__ inline void rp_flush(float (&acc)[kMJ], float* part, int n) {
   }
 }
 
-template <typename T, typename Tin>
-__global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int mode, int mat_in_lds) {
+// MAT_LDS: the block storage of K / L / W lives in LDS (else in the plan's global
+// workspace).  A compile-time choice, so the LDS instance addresses it with LDS
+// instructions rather than generic ones.
+template <typename T, typename Tin, bool MAT_LDS>
+__global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int mode) {
   // mode 0: primary pass in T (may hand over to FP64); 1: FP64 pass, runs only
   // if the primary pass raised the flag; 2: the only pass.
   if (mode == 1 && *(volatile int32_t*)a.flag == 0) {
@@ -807,7 +848,8 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   w.red = take(64);
   w.scal = take(8);
   const size_t mat_elems = bo(nblocks(n), 0);
-  w.mat = mat_in_lds ? take(mat_elems) : reinterpret_cast<T*>(a.gmat);
+  if constexpr (MAT_LDS) w.mat = take(mat_elems);
+  else w.mat = reinterpret_cast<T*>(a.gmat);
 
   // ---- load problem vectors
   for (int i = threadIdx.x; i < m; i += kQpThreads) {
@@ -933,7 +975,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
       }
     }
     if (!done_rows) {
-      const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      const int wid = wave_index(), lane = threadIdx.x & 63;
       T* pw = w.part + (size_t)wid * n;
       for (int c = lane; c < n; c += 64) pw[c] = T(0);
       for (int r = wid; r < nc; r += kWaves) {
@@ -1007,7 +1049,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
       }
     }
     if (!done_res) {
-      const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      const int wid = wave_index(), lane = threadIdx.x & 63;
       T* pw = w.part + (size_t)wid * n;
       for (int c = lane; c < n; c += 64) pw[c] = T(0);
       for (int r = wid; r < nc; r += kWaves) {
@@ -1094,7 +1136,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
         }
       }
       if (!done_inf) {
-        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wid = wave_index(), lane = threadIdx.x & 63;
         T* pw = w.part + (size_t)wid * n;
         for (int c = lane; c < n; c += 64) pw[c] = T(0);
         for (int r = wid; r < nc; r += kWaves) {
@@ -1137,7 +1179,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
         }
         ++refactors;
         // the cached Ct'(rho z - y) must use the new rho
-        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wid = wave_index(), lane = threadIdx.x & 63;
         T* pw = w.part + (size_t)wid * n;
         for (int c = lane; c < n; c += 64) pw[c] = T(0);
         for (int r = wid; r < nc; r += kWaves) {
@@ -1217,12 +1259,13 @@ gnmpc_status launch_pass(gnmpc_plan* p, const QpArgs<Tin>& a, int mode, hipStrea
     if (p) p->last_error = "QP too large for one workgroup's LDS";
     return GNMPC_UNSUPPORTED;
   }
-  if (set_max_lds((const void*)qp_solve_kernel<T, Tin>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess) {
+  const void* fn = in_lds ? (const void*)qp_solve_kernel<T, Tin, true> : (const void*)qp_solve_kernel<T, Tin, false>;
+  if (set_max_lds(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     if (p) p->last_error = "QP: could not raise the LDS limit of the solve kernel";
     return GNMPC_HIP_ERROR;
   }
-  qp_solve_kernel<T, Tin><<<1, kQpThreads, lds, s>>>(a, mode, in_lds ? 1 : 0);
+  if (in_lds) qp_solve_kernel<T, Tin, true><<<1, kQpThreads, lds, s>>>(a, mode);
+  else qp_solve_kernel<T, Tin, false><<<1, kQpThreads, lds, s>>>(a, mode);
   return GNMPC_OK;
 }
 
