@@ -408,6 +408,7 @@ def main():
         "cpu_baseline": cpu,
         "tangent": tangent_rates(gn, plan_g, bg, args.steps),
         "simulator": simulator_rate(torch, gn, wl),
+        "closed_loop": closed_loop_rate(torch, gn, wl),
     }
     print(json.dumps(out), flush=True)
 
@@ -481,6 +482,56 @@ def simulator_rate(torch, gn, wl, reps=3):
     return {"workload": f"{B} trajectories x {T} steps, {M}-node 1-2-hop chain, cubic springs k3=50, gravity",
             "ms": ms, "node_steps_per_s": B * T * M / (ms * 1e-3), "bytes": nbytes,
             "GB_per_s": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+
+
+def closed_loop_rate(torch, gn, wl, iters=50):
+    """Algorithm 1 in closed loop on the 1000-node workload: each iteration is one
+    gnmpc_rti_step of the GNN-form controller (linearize, condense, QP, rollout of
+    the optimum, shift; obstacle rows included) and one step of the spring-damper
+    simulator as the plant, all on one stream with nothing copied to the host."""
+    P = wl.gnn1000_bf16()
+    Pm = wl.gnn1000_bf16(model="msd")
+    N, M, nu, n = P.N, P.M, P.nu, P.N * P.nu
+
+    def t(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+    plan = gn.Plan(M, nu, N, P.rows.n, gn.F32)
+    plan.graph_set(P.row_ptr, P.col, P.gnn.L)
+    plan.model_set_gnn(P.gnn, P.act, dtype=gn.BF16)
+    plan.rows_set(P.rows.node, P.rows.stage)
+    plant = gn.Plan(M, nu, 1, 1, gn.F32)
+    plant.graph_set(Pm.row_ptr, Pm.col, 1)
+    plant.model_set_msd(Pm.msd, Pm.act)
+    e = lambda *sh: torch.empty(*sh, device="cuda")
+    b = dict(xhat=t(np.repeat(P.x0[None], N + 1, axis=0)), uhat=torch.zeros(N, nu, device="cuda"), x0=t(P.x0),
+             Q=t(P.costs.Q), q=t(P.costs.q), R=t(P.costs.R), r=t(P.costs.r), rowC=t(P.rows.C), rowd=t(P.rows.d),
+             lb=t(P.lb), ub=t(P.ub), A=e(N, plan.nnz, 6, 6), B=e(N, M, 6, nu), c=e(N, M, 6), H=e(n, n), g=e(n),
+             Ct=e(P.rows.n, n), dt=e(P.rows.n), u=e(n), uc=None,
+             info=torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device="cuda"))
+    b["uc"] = b["dt"]
+    xpred, X = e(N + 1, M, 6), e(1, 2, M, 6)
+    settings = gn.default_admm_settings()
+
+    def iteration():
+        gn.rti_step(plan, b, xpred, settings=settings)
+        plant.msd_simulate(b["x0"].view(1, M, 6), b["u"][:nu].view(1, 1, nu), X)
+        b["x0"].copy_(X[0, 1])
+
+    for _ in range(5):
+        iteration()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        iteration()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    return {"workload": "GNN-form RTI controller (1000-node chain, Hd=128, L=3, N=20, 200 rows) on the "
+                        "spring-damper plant", "iterations": iters, "ms_per_iteration": ms,
+            "iterations_per_s": 1e3 / ms, "qp_status_last": gn.qp_info(b["info"]).status,
+            "qp_iters_last": gn.qp_info(b["info"]).iters}
 
 
 def bench_batch(args, torch, gn, wl):

@@ -366,6 +366,22 @@ typedef struct {
 gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count,
                                 const gnmpc_admm_settings* settings, void* stream);
 
+/* One iteration of Algorithm 1 (GNN-MPC, an SQP real-time iteration) for one
+ * instance, on `stream`: linearize the plan's model around (d->xhat, d->uhat),
+ * condense with the initial state d->x0 (the measured state), solve the box QP
+ * into d->u, roll the linearized dynamics forward from x0 with u into
+ * xpred [N+1][M][6] (the optimal predicted states x*), and write the shifted
+ * trajectory of the next iteration ("update lin. trajectory"):
+ *   xhat_next[k] = x*[k+1] (k < N), xhat_next[N] = x*[N];
+ *   uhat_next[k] = u*[k+1] (k < N-1), uhat_next[N-1] = u*[N-1].
+ * The input to apply is u*[0], the first nu entries of d->u.  xhat_next and
+ * uhat_next may be d->xhat and d->uhat (they are written last); xpred may
+ * alias neither xhat array.  Arrays as in gnmpc_step_desc, device, plan
+ * dtype; the QP status goes to d->info.  Errors as the single calls; the first
+ * failing call's status is returned and nothing after it is enqueued. */
+gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
+                            const gnmpc_admm_settings* settings, void* stream);
+
 /* ---------------- per-phase GPU timers ---------------- */
 
 /* Phases timed by gnmpc_timers_*: hipEvents are recorded on the caller's stream

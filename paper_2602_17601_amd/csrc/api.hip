@@ -564,4 +564,22 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
   return first;
 }
 
+gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
+                            const gnmpc_admm_settings* st, void* stream) {
+  if (!d || !d->plan || !st) return GNMPC_INVALID_ARG;
+  gnmpc_plan* p = d->plan;
+  if (!xpred || !xhat_next || !uhat_next) return fail(p, GNMPC_INVALID_ARG, "rti_step: null array");
+  if (xpred == xhat_next || xpred == d->xhat || xpred == d->x0)
+    return fail(p, GNMPC_INVALID_ARG, "rti_step: xpred aliases an input or xhat_next");
+  const int32_t n = p->dims.N * p->dims.nu;
+  gnmpc_status s = gnmpc_linearize(p, d->xhat, d->uhat, d->A, d->B, d->c, nullptr, nullptr, stream);
+  if (s == GNMPC_OK)
+    s = gnmpc_condense(p, d->A, d->B, d->c, d->x0, d->Q, d->Q_full, d->q, d->R, d->r, d->rowC, d->rowd, d->H,
+                       d->g, d->Ct, d->dt, nullptr, stream);
+  if (s == GNMPC_OK) s = gnmpc_solve_box_qp(p, n, d->H, d->g, d->lb, d->ub, p->n_c, d->Ct, d->lc, d->uc, st, d->u, d->info, stream);
+  if (s == GNMPC_OK) s = gnmpc_rollout_linear(p, d->A, d->B, d->c, d->x0, d->u, xpred, stream);
+  if (s == GNMPC_OK) s = launch_rti_shift(p, xpred, d->u, xhat_next, uhat_next, (hipStream_t)stream);
+  return s;
+}
+
 }  // extern "C"

@@ -138,6 +138,8 @@ gnmpc_status launch_vjp(gnmpc_plan* p, const void* A, const void* B, const void*
                         hipStream_t s);
 gnmpc_status launch_rollout(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
                             const void* u, void* x, hipStream_t s);
+gnmpc_status launch_rti_shift(gnmpc_plan* p, const void* xpred, const void* u, void* xhat, void* uhat,
+                              hipStream_t s);
 // check.hip
 size_t lin_check_bytes();
 gnmpc_status launch_lin_check(gnmpc_plan* p, const void* xhat, const void* uhat, const void* A, const void* B,

@@ -121,6 +121,34 @@ gnmpc_status run_rollout(gnmpc_plan* p, const void* A, const void* B, const void
   return GNMPC_OK;
 }
 
+// The shift of Algorithm 1 ("update lin. trajectory"): the next linearization
+// trajectory is the optimal one advanced by one stage, xhat'[k] = x*[k+1] and
+// uhat'[k] = u*[k+1]; the stages that have no successor repeat the last one
+// (xhat'[N] = x*[N], uhat'[N-1] = u*[N-1]).  One thread per output element; the
+// outputs may be the current linearization trajectory (it is not read here).
+template <typename T>
+__global__ void rti_shift_kernel(int N, int M, int nu, const T* __restrict__ xpred, const T* __restrict__ u,
+                                 T* __restrict__ xhat, T* __restrict__ uhat) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long sM = (long)M * NBX, nx = (long)(N + 1) * sM;
+  if (t < nx) {
+    const long k = t / sM;
+    xhat[t] = xpred[(k < N ? k + 1 : N) * sM + (t - k * sM)];
+  } else if (t < nx + (long)N * nu) {
+    const long q = t - nx, k = q / nu;
+    uhat[q] = u[(k < N - 1 ? k + 1 : N - 1) * nu + (q - k * nu)];
+  }
+}
+
+template <typename T>
+gnmpc_status run_shift(gnmpc_plan* p, const void* xpred, const void* u, void* xhat, void* uhat, hipStream_t s) {
+  const int N = p->dims.N, M = p->M, nu = p->dims.nu;
+  const long n = (long)(N + 1) * M * NBX + (long)N * nu;
+  rti_shift_kernel<T><<<ceil_div(n, 256), 256, 0, s>>>(N, M, nu, (const T*)xpred, (const T*)u, (T*)xhat, (T*)uhat);
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
+}
+
 template <typename T>
 gnmpc_status run_jvp(gnmpc_plan* p, const void* A, const void* B, const void* dx, const void* du, void* out,
                      hipStream_t s) {
@@ -162,6 +190,12 @@ gnmpc_status launch_rollout(gnmpc_plan* p, const void* A, const void* B, const v
                             const void* u, void* x, hipStream_t s) {
   if (p->dims.dtype == GNMPC_F64) return run_rollout<double>(p, A, B, c, x0, u, x, s);
   return run_rollout<float>(p, A, B, c, x0, u, x, s);
+}
+
+gnmpc_status launch_rti_shift(gnmpc_plan* p, const void* xpred, const void* u, void* xhat, void* uhat,
+                              hipStream_t s) {
+  if (p->dims.dtype == GNMPC_F64) return run_shift<double>(p, xpred, u, xhat, uhat, s);
+  return run_shift<float>(p, xpred, u, xhat, uhat, s);
 }
 
 }  // namespace gnmpc

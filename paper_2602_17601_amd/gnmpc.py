@@ -113,6 +113,7 @@ def lib():
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
             "gnmpc_timers_enable": ([vp, i32], i32),
             "gnmpc_step_batched": ([vp, i32, P(AdmmSettings), vp], i32),
+            "gnmpc_rti_step": ([P(StepDesc), vp, vp, vp, P(AdmmSettings), vp], i32),
             "gnmpc_timers_read": ([vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
@@ -418,6 +419,20 @@ def step_desc(plan, b):
     d.u = dv(b["u"], (n,), "u")
     d.info = dv(b.get("info"), (QP_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)
     return d
+
+
+def rti_step(plan, b, xpred, xhat_next=None, uhat_next=None, settings=None, stream=None):
+    """gnmpc_rti_step: one iteration of Algorithm 1 on the buffers `b` (as for
+    step_desc); x* goes to xpred [N+1][M][6] and the shifted linearization
+    trajectory to xhat_next / uhat_next (default: b["xhat"], b["uhat"] in place)."""
+    d = step_desc(plan, b)
+    xn = b["xhat"] if xhat_next is None else xhat_next
+    un = b["uhat"] if uhat_next is None else uhat_next
+    M, N, nu = plan.M, plan.N, plan.nu
+    args = [plan._dev(xpred, (N + 1, M, 6), "xpred"), plan._dev(xn, (N + 1, M, 6), "xhat_next"),
+            plan._dev(un, (N, nu), "uhat_next")]
+    st = settings or default_admm_settings()
+    plan._check(lib().gnmpc_rti_step(C.byref(d), *args, C.byref(st), _stream(stream)), "rti_step")
 
 
 def step_batched(descs, settings=None, stream=None):
