@@ -16,6 +16,8 @@ Modules (each function cites the passage it follows):
   kkt       -- uncondensed equality-constrained KKT solve of the OCP (Sec. III-B eq. 2)
   tangent   -- products with the linearized model's blocks (forward and reverse mode)
   mpc       -- one iteration of the GNN-MPC loop with its shift (Algorithm 1)
+  inet      -- the paper's own model, an interaction network with a global input
+               (Sec. V-A eq. forward_dynamics), and its forward-mode linearization
 
 Everything is float64.  Cost convention: stage cost 1/2 x'Qx + q'x + 1/2 u'Ru + r'u
 and QP objective 1/2 u'Hu + g'u, under which the paper's formulas for H and g

@@ -101,6 +101,59 @@ class GNNWeights:
                           r(self.W_dec), rb(self.b_dec), self.dt)
 
 
+@dataclass
+class InetWeights:
+    """The interaction network of Sec. V-A (eq. forward_dynamics), float64,
+    (out, in) row-major: psi maps the relative state e^{ij} = x^i - x^j (6) to a
+    message (d_m); phi maps [x^i (6); sum_j psi(e^{ij}) (d_m); u (n_u, the global
+    input)] to the velocity increment (3).  Each is a list of linear layers with a
+    ReLU after every layer but the last.  v+ = v + phi, p+ = p + dt v+."""
+    psi_W: list
+    psi_b: list
+    phi_W: list
+    phi_b: list
+    nu: int
+    dt: float = 0.01
+
+    @property
+    def d_m(self):
+        return int(self.psi_W[-1].shape[0])
+
+    def flat(self):
+        """Weights packed as the library takes them: psi (W, b) per layer, then phi."""
+        parts = []
+        for W, b in list(zip(self.psi_W, self.psi_b)) + list(zip(self.phi_W, self.phi_b)):
+            parts += [np.asarray(W, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)]
+        return np.concatenate(parts)
+
+
+def inet_weights(seed: int, nu: int = 6, psi_hidden: int = 4, psi_width: int = 50, d_m: int = 50,
+                 phi_hidden: int = 8, phi_width: int = 250, dt: float = 0.01, bias_lo: float = -0.1,
+                 bias_hi: float = 0.1) -> InetWeights:
+    """Xavier-uniform weights (gain 1) for psi then phi, layer by layer; biases
+    uniform in [bias_lo, bias_hi) drawn after all weights (a range above zero
+    makes every ReLU active for inputs near zero)."""
+    rng = np.random.default_rng(seed)
+    psi_dims = [6] + [psi_width] * psi_hidden + [d_m]
+    phi_dims = [6 + d_m + nu] + [phi_width] * phi_hidden + [3]
+    psi_W = [xavier(rng, psi_dims[l + 1], psi_dims[l]) for l in range(len(psi_dims) - 1)]
+    phi_W = [xavier(rng, phi_dims[l + 1], phi_dims[l]) for l in range(len(phi_dims) - 1)]
+    psi_b = [rng.uniform(bias_lo, bias_hi, psi_dims[l + 1]) for l in range(len(psi_dims) - 1)]
+    phi_b = [rng.uniform(bias_lo, bias_hi, phi_dims[l + 1]) for l in range(len(phi_dims) - 1)]
+    return InetWeights(psi_W, psi_b, phi_W, phi_b, nu, dt)
+
+
+def nearest_csr(M: int, d: int):
+    """Incoming-edge CSR where node i's senders are the d other nodes nearest to it
+    in index (ties toward the lower index), rows ascending."""
+    row_ptr, col = [0], []
+    for i in range(M):
+        others = sorted((j for j in range(M) if j != i), key=lambda j: (abs(j - i), j))[:d]
+        col += sorted(others)
+        row_ptr.append(len(col))
+    return np.asarray(row_ptr, np.int32), np.asarray(col, np.int32)
+
+
 def bf16_round(a: np.ndarray) -> np.ndarray:
     """Round float64 values to the nearest bfloat16 (ties to even), returned as float64."""
     f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
@@ -271,15 +324,16 @@ class Problem:
     rows: StateRows
     lb: np.ndarray
     ub: np.ndarray
-    model: str                      # "msd" or "gnn"
+    model: str                      # "msd", "gnn" or "inet"
     msd: MSDParams = field(default_factory=MSDParams)
     gnn: GNNWeights | None = None
     dtype: str = "f32"              # arithmetic of condensing: "f64" | "f32"
     gnn_dtype: str = "f32"          # arithmetic of the GNN MLPs: "f32" | "bf16"
+    inet: InetWeights | None = None
 
     @property
     def nu(self):
-        return 3 * len(self.act)
+        return self.inet.nu if self.model == "inet" else 3 * len(self.act)
 
     @property
     def L(self):
@@ -347,6 +401,22 @@ def gnn1000_bf16(model: str = "gnn") -> Problem:
                         M=1000, hops=2, N=20, n_act=4, model=model, seed=3, Hd=128, L=3,
                         x0_sigma=0.02, walk=0.002, obstacle=True,
                         gnn_dtype="bf16" if model == "gnn" else "f32")
+
+
+def trunk_inet(M: int = 4, d: int = 2, N: int = 20, nu: int = 6, seed: int = 7, x0_sigma: float = 0.02,
+               walk: float = 0.002, umax: float = 1.0, **inet_kw) -> Problem:
+    """The paper's own model on its robot's shape (Sec. VI-C): M = 4 nodes with d = 2
+    neighbours each, the interaction network with psi 4 x 50 and phi 8 x 250 hidden
+    units and a global input of n_u = 6 (six motors), N = 20 at 100 Hz; seeded
+    random weights (no trained ones exist here), tracking costs, |u| <= umax."""
+    row_ptr, col = nearest_csr(M, d)
+    W = inet_weights(seed, nu=nu, **inet_kw)
+    rng = np.random.default_rng(seed + 1)
+    x0 = initial_state(rng, M, x0_sigma)
+    xhat, uhat = nominal_trajectory(rng, x0, N, nu, walk)
+    costs = tracking_costs(M, N, nu, (1, 1, 1, .01, .01, .01), 0.1)
+    return Problem(f"trunk_inet{M}", M, 0, N, np.zeros(0, np.int32), row_ptr, col, x0, xhat, uhat, costs, no_rows(),
+                   -umax * np.ones(N * nu), umax * np.ones(N * nu), "inet", MSDParams(dt=W.dt), None, "f32", "f32", W)
 
 
 def batch_instances(count: int, seed: int = 4, M_range=(50, 1000), N_range=(10, 30)) -> list[Problem]:
