@@ -408,7 +408,10 @@ def main():
         "cpu_baseline": cpu,
         "tangent": tangent_rates(gn, plan_g, bg, args.steps),
         "simulator": simulator_rate(torch, gn, wl),
-        "closed_loop": closed_loop_rate(torch, gn, wl),
+        "closed_loop": {"workload": "1000-node chain, N=20, 200 obstacle rows, spring-damper plant",
+                        "plain": closed_loop_rate(torch, gn, wl, "msd"),
+                        "gnn": closed_loop_rate(torch, gn, wl, "gnn")},
+        "paper_model": paper_model_rate(torch, gn, wl),
     }
     print(json.dumps(out), flush=True)
 
@@ -484,12 +487,16 @@ def simulator_rate(torch, gn, wl, reps=3):
             "GB_per_s": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
 
-def closed_loop_rate(torch, gn, wl, iters=50):
+def closed_loop_rate(torch, gn, wl, model="msd", iters=50):
     """Algorithm 1 in closed loop on the 1000-node workload: each iteration is one
-    gnmpc_rti_step of the GNN-form controller (linearize, condense, QP, rollout of
-    the optimum, shift; obstacle rows included) and one step of the spring-damper
-    simulator as the plant, all on one stream with nothing copied to the host."""
-    P = wl.gnn1000_bf16()
+    gnmpc_rti_step of the controller (linearize, condense, QP, rollout of the
+    optimum, shift; 200 obstacle rows) and one step of the spring-damper simulator
+    as the plant, all on one stream with nothing copied to the host.  The
+    controller's model is the plant's own spring-damper model (analytic
+    Jacobians, model="msd") or the GNN (model="gnn": seeded random weights, which
+    do not describe the plant, so the loop drifts and its QPs get harder; timing
+    of the path only)."""
+    P = wl.gnn1000_bf16(model=model)
     Pm = wl.gnn1000_bf16(model="msd")
     N, M, nu, n = P.N, P.M, P.nu, P.N * P.nu
 
@@ -497,8 +504,12 @@ def closed_loop_rate(torch, gn, wl, iters=50):
         return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
 
     plan = gn.Plan(M, nu, N, P.rows.n, gn.F32)
-    plan.graph_set(P.row_ptr, P.col, P.gnn.L)
-    plan.model_set_gnn(P.gnn, P.act, dtype=gn.BF16)
+    if model == "gnn":
+        plan.graph_set(P.row_ptr, P.col, P.gnn.L)
+        plan.model_set_gnn(P.gnn, P.act, dtype=gn.BF16)
+    else:
+        plan.graph_set(P.row_ptr, P.col, 1)
+        plan.model_set_msd(P.msd, P.act)
     plan.rows_set(P.rows.node, P.rows.stage)
     plant = gn.Plan(M, nu, 1, 1, gn.F32)
     plant.graph_set(Pm.row_ptr, Pm.col, 1)
@@ -528,10 +539,50 @@ def closed_loop_rate(torch, gn, wl, iters=50):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
-    return {"workload": "GNN-form RTI controller (1000-node chain, Hd=128, L=3, N=20, 200 rows) on the "
-                        "spring-damper plant", "iterations": iters, "ms_per_iteration": ms,
-            "iterations_per_s": 1e3 / ms, "qp_status_last": gn.qp_info(b["info"]).status,
-            "qp_iters_last": gn.qp_info(b["info"]).iters}
+    info = gn.qp_info(b["info"])
+    return {"controller": "spring-damper model (analytic Jacobians)" if model == "msd" else
+            "GNN Hd=128 L=3 BF16, random weights", "iterations": iters, "ms_per_iteration": ms,
+            "iterations_per_s": 1e3 / ms, "qp_status_last": info.status, "qp_iters_last": info.iters,
+            "qp_used_fp64_last": info.used_fp64}
+
+
+def paper_model_rate(torch, gn, wl, iters=50):
+    """The paper's own model on its robot's shape (interaction network, 4 nodes with
+    2 neighbours, psi 4 x 50, phi 8 x 250, n_u = 6, N = 20, FP32): time of the
+    linearization alone and of one GNN-MPC iteration (gnmpc_rti_step), HIP events on
+    the stream both run on."""
+    P = wl.trunk_inet()
+    N, M, nu, n = P.N, P.M, P.nu, P.N * P.nu
+    plan = gn.Plan(M, nu, N, 0, gn.F32)
+    plan.graph_set(P.row_ptr, P.col, 1)
+    plan.model_set_inet(P.inet)
+
+    def t(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+    e = lambda *sh: torch.empty(*sh, device="cuda")
+    b = dict(xhat=t(P.xhat), uhat=t(P.uhat), x0=t(P.x0), Q=t(P.costs.Q), q=t(P.costs.q), R=t(P.costs.R),
+             r=t(P.costs.r), lb=t(P.lb), ub=t(P.ub), A=e(N, plan.nnz, 6, 6), B=e(N, M, 6, nu), c=e(N, M, 6),
+             H=e(n, n), g=e(n), u=e(n), info=torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device="cuda"))
+    xpred, xn, un = e(N + 1, M, 6), e(N + 1, M, 6), e(N, nu)
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / iters
+
+    lin_ms = timed(lambda: plan.linearize(b["xhat"], b["uhat"], b["A"], b["B"], b["c"]))
+    rti_ms = timed(lambda: gn.rti_step(plan, b, xpred, xn, un))
+    return {"workload": "interaction network (psi 4x50, phi 8x250), 4 nodes x 2 neighbours, n_u=6, N=20, FP32",
+            "linearize_ms": lin_ms, "rti_step_ms": rti_ms, "rti_steps_per_s": 1e3 / rti_ms,
+            "qp_iters": gn.qp_info(b["info"]).iters}
 
 
 def bench_batch(args, torch, gn, wl):

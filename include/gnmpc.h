@@ -106,6 +106,20 @@ typedef struct {
   double dt;
 } gnmpc_gnn_desc;
 
+/* The paper's own model (Sec. V-A eq. forward_dynamics): an interaction network
+ * with a global input u shared by every node.  With e^{ij} = x^i - x^j,
+ *   v^i+ = v^i + phi([x^i; sum_{j in N_i} psi(e^{ij}); u]),  p^i+ = p^i + dt v^i+,
+ * psi: 6 -> psi_hidden layers of psi_width -> d_m, phi: 6 + d_m + nu ->
+ * phi_hidden layers of phi_width -> 3, a ReLU after every layer but the last.
+ * Weights are passed packed, float64, (out, in) row-major, layer by layer:
+ * psi's (W, b) pairs, then phi's.  The paper's robot: psi 4 x 50, phi 8 x 250,
+ * nu = 6.  Widths and d_m up to 256, at most 15 hidden layers each, nu <= 64. */
+typedef struct {
+  int32_t psi_hidden, psi_width, d_m;
+  int32_t phi_hidden, phi_width, nu;
+  double dt;
+} gnmpc_inet_desc;
+
 /* ADMM settings (operator splitting in the form of Stellato et al., OSQP). */
 typedef struct {
   double rho;        /* penalty of the inequality rows (> 0)                     */
@@ -197,6 +211,16 @@ gnmpc_status gnmpc_model_set_msd(gnmpc_plan* plan, const gnmpc_msd_params* prm,
 gnmpc_status gnmpc_model_set_gnn(gnmpc_plan* plan, const gnmpc_gnn_desc* desc,
                                  const double* weights, int64_t n_weights,
                                  const int32_t* act, int32_t n_act);
+
+/* Choose the interaction-network model (gnmpc_inet_desc); weights host float64
+ * packed as described there, n_weights their count.  The graph must have been
+ * set with L = 1 and desc->nu must equal the plan's nu.  Linearization then
+ * fills every pattern block (the node and its in-neighbours) and B^i for the
+ * whole global input; condensing, the QP, the rollout and gnmpc_rti_step are
+ * unchanged.  GNMPC_SHAPE for a wrong weight count or nu, GNMPC_UNSUPPORTED
+ * when one workgroup's activations exceed LDS. */
+gnmpc_status gnmpc_model_set_inet(gnmpc_plan* plan, const gnmpc_inet_desc* desc, const double* weights,
+                                  int64_t n_weights);
 
 /* Structure of the single-node state rows C x^{node}_{stage} <= d (Sec. IV-B:
  * half-spaces X^i_k; condensed as in the stacked-constraint formula of

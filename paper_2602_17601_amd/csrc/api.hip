@@ -225,6 +225,7 @@ void gnmpc_plan_destroy(gnmpc_plan* p) {
   (void)hipSetDevice(p->device);
   destroy_timers(p);
   gnn_free(p);
+  inet_free(p);
   dfree(p->d_row_ptr);
   dfree(p->d_col);
   dfree(p->d_prow);
@@ -365,6 +366,24 @@ gnmpc_status gnmpc_model_set_gnn(gnmpc_plan* p, const gnmpc_gnn_desc* desc, cons
   return GNMPC_OK;
 }
 
+gnmpc_status gnmpc_model_set_inet(gnmpc_plan* p, const gnmpc_inet_desc* desc, const double* weights,
+                                  int64_t n_weights) {
+  if (!p || !desc || !weights) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "model_set_inet: set the graph first");
+  if (p->L != 1) return fail(p, GNMPC_SHAPE, "model_set_inet: the graph must be set with L = 1");
+  if (desc->nu != p->dims.nu) return fail(p, GNMPC_SHAPE, "model_set_inet: nu differs from the plan's nu");
+  for (int64_t t = 0; t < n_weights; ++t)
+    if (!std::isfinite(weights[t])) return fail(p, GNMPC_INVALID_ARG, "model_set_inet: non-finite weight");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  const gnmpc_status s = inet_set(p, desc, weights, n_weights);
+  if (s == GNMPC_INVALID_ARG) return fail(p, s, "model_set_inet: sizes out of range");
+  if (s == GNMPC_SHAPE) return fail(p, s, "model_set_inet: wrong number of weights");
+  if (s == GNMPC_UNSUPPORTED) return fail(p, s, "model_set_inet: activations exceed one workgroup's LDS");
+  if (s != GNMPC_OK) return s;
+  p->model = 3;
+  return GNMPC_OK;
+}
+
 gnmpc_status gnmpc_rows_set(gnmpc_plan* p, int32_t n_c, const int32_t* node, const int32_t* stage) {
   if (!p) return GNMPC_INVALID_ARG;
   if (n_c < 0 || (n_c > 0 && (!node || !stage))) return fail(p, GNMPC_INVALID_ARG, "rows_set: bad arrays");
@@ -389,8 +408,9 @@ gnmpc_status gnmpc_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, 
   if (!p->graph_ready || p->model == 0) return fail(p, GNMPC_NOT_READY, "linearize: graph and model must be set");
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
-  const gnmpc_status st = p->model == 1 ? launch_msd_linearize(p, xhat, uhat, A, B, c, fnext, s)
-                                        : launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
+  const gnmpc_status st = p->model == 1   ? launch_msd_linearize(p, xhat, uhat, A, B, c, fnext, s)
+                          : p->model == 3 ? launch_inet_linearize(p, xhat, uhat, A, B, c, fnext, s)
+                                          : launch_gnn_linearize(p, xhat, uhat, A, B, c, fnext, s);
   if (st != GNMPC_OK || !info) return st;
   return launch_lin_check(p, xhat, uhat, A, B, c, fnext, info, s);
 }

@@ -12,6 +12,9 @@ namespace gnmpc {
 
 constexpr int NBX = 6;          // states per node
 constexpr int kMaxWidth = 64;   // max blocks in one Jacobian pattern row
+constexpr int kInetMaxLayers = 16;   // linear layers of each interaction-network MLP
+constexpr int kInetMaxWidth = 256;   // widest hidden layer / message
+constexpr int kInetMaxNu = 64;       // global inputs of the interaction network
 
 #define GNMPC_HIP_TRY(plan, expr)                                                   \
   do {                                                                              \

@@ -6,7 +6,8 @@
 
 #include "common.hpp"
 
-struct GnnState;  // defined in gnn.hip
+struct GnnState;   // defined in gnn.hip
+struct InetState;  // defined in inet.hip
 
 struct gnmpc_plan {
   int device = 0;
@@ -35,12 +36,13 @@ struct gnmpc_plan {
   int32_t* d_pb2_rec = nullptr;
 
   // model
-  int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN
+  int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN, 3 interaction network
   gnmpc_msd_params msd{};
   int n_act = 0;
   std::vector<int32_t> h_act;
   int32_t* d_act_of_node = nullptr;  // [M]: actuator index of the node or -1
   GnnState* gnn = nullptr;
+  InetState* inet = nullptr;
 
   // single-node state rows
   int n_c = 0;
@@ -147,6 +149,11 @@ gnmpc_status launch_lin_check(gnmpc_plan* p, const void* xhat, const void* uhat,
 // gnn.hip
 gnmpc_status gnn_set(gnmpc_plan* p, const gnmpc_gnn_desc* desc, const double* w, int64_t n_w);
 void gnn_free(gnmpc_plan* p);
+// inet.hip
+gnmpc_status inet_set(gnmpc_plan* p, const gnmpc_inet_desc* d, const double* w, int64_t n_w);
+void inet_free(gnmpc_plan* p);
+gnmpc_status launch_inet_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
+                                   void* fnext, hipStream_t s);
 // msd_sim.hip
 bool msd_sim_fits(const gnmpc_plan* p);
 gnmpc_status launch_msd_simulate(gnmpc_plan* p, int B, int T, const void* x0, const void* u, void* X, hipStream_t s);

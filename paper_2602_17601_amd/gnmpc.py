@@ -45,6 +45,11 @@ class GnnDesc(C.Structure):
                 ("dt", C.c_double)]
 
 
+class InetDesc(C.Structure):
+    _fields_ = [("psi_hidden", C.c_int32), ("psi_width", C.c_int32), ("d_m", C.c_int32),
+                ("phi_hidden", C.c_int32), ("phi_width", C.c_int32), ("nu", C.c_int32), ("dt", C.c_double)]
+
+
 class AdmmSettings(C.Structure):
     _fields_ = [("rho", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("eps_abs", C.c_double),
                 ("eps_rel", C.c_double), ("kappa_fp64", C.c_double), ("max_iter", C.c_int32),
@@ -98,6 +103,7 @@ def lib():
             "gnmpc_graph_pattern": ([vp, vp, vp], i32),
             "gnmpc_model_set_msd": ([vp, P(MsdParams), vp, i32], i32),
             "gnmpc_model_set_gnn": ([vp, P(GnnDesc), vp, i64, vp, i32], i32),
+            "gnmpc_model_set_inet": ([vp, P(InetDesc), vp, i64], i32),
             "gnmpc_rows_set": ([vp, i32, vp, vp], i32),
             "gnmpc_linearize": ([vp] + [vp] * 8, i32),
             "gnmpc_rollout_linear": ([vp] * 8, i32),
@@ -243,6 +249,14 @@ class Plan:
         a = _i32(act)
         self._check(lib().gnmpc_model_set_msd(self._h, C.byref(p), _hp(a), len(a)), "model_set_msd")
         self.model = "msd"
+
+    def model_set_inet(self, W):
+        """The interaction network (workloads.InetWeights) as the plan's model."""
+        d = InetDesc(len(W.psi_W) - 1, int(W.psi_W[0].shape[0]) if len(W.psi_W) > 1 else 1, W.d_m,
+                     len(W.phi_W) - 1, int(W.phi_W[0].shape[0]) if len(W.phi_W) > 1 else 1, W.nu, W.dt)
+        flat = np.ascontiguousarray(W.flat(), dtype=np.float64)
+        self._check(lib().gnmpc_model_set_inet(self._h, C.byref(d), _hp(flat), flat.shape[0]), "model_set_inet")
+        self.model = "inet"
 
     def model_set_gnn(self, W, act, dtype=F32):
         flat = [W.W_enc, W.b_enc]
