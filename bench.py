@@ -355,6 +355,17 @@ def main():
 
     plan_g, bg = make(P, True)
     plan_m, bm = make(Pm, False)
+
+    def tune(plan, b):
+        """The library's condensing autotuner on this step's own blocks (setup, untimed)."""
+        plan.linearize(b["xhat"], b["uhat"], b["A"], b["B"], b["c"])
+        chosen, entries = plan.autotune_condense(b["A"], b["B"], b["c"], b["x0"], b["Q"], b["q"], b["R"], b["r"],
+                                                 b["rowC"], b["rowd"], b["H"], b["g"], b["Ct"], b["dt"], reps=5)
+        names = {0: "per-node kernel", 1: "node blocks, one stage per launch", 2: "node blocks, two stages per launch"}
+        return {"chosen": chosen, "candidates": [
+            {"variant": names[e["variant"]], "block_nodes": e["block_nodes"], "us": round(e["us"], 1)} for e in entries]}
+
+    tuning = {"gnn": tune(plan_g, bg), "plain": tune(plan_m, bm)}
     el_g, ph_g, st_g = timed(plan_g, bg)
     el_m, ph_m, st_m = timed(plan_m, bm)
     qpi = gn.qp_info(bg["info"])
@@ -402,6 +413,7 @@ def main():
         "phase_ms_gnn": phase_avg(ph_g),
         "phase_ms_plain": phase_avg(ph_m),
         "qp_iters_gnn": qpi.iters,
+        "condense_tuning": tuning,
         "qp_status_gnn": qpi.status,
         "roofline": roofline,
         "phase_roofline_gnn": phase_rooflines(P, int(plan_g.nnz), phase_avg(ph_g), flops),

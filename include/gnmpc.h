@@ -319,6 +319,38 @@ gnmpc_status gnmpc_condense(gnmpc_plan* plan, const void* A, const void* B, cons
                             const void* R, const void* r, const void* rowC, const void* rowd,
                             void* H, void* g, void* Ct, void* dt, void* Gx, void* stream);
 
+/* Tile autotuner of the condensing (set-up time, not for graph capture: it
+ * synchronizes `stream`).  Times gnmpc_condense on the caller's arrays (the
+ * arguments of gnmpc_condense, Gx omitted) `reps` times for every feasible
+ * propagation variant -- the per-node kernel, node blocks of 4, 2 or 1 nodes one
+ * stage per launch, and the same blocks two stages per launch where their halo
+ * fits -- keeps the fastest as the plan's choice for later calls (until the next
+ * gnmpc_graph_set) and writes every measurement to `report` (host).  The
+ * variants compute the same sums; the per-node kernel may round differently.
+ * The outputs hold the last candidate's results. */
+#define GNMPC_TUNE_MAX 16
+typedef struct {
+  int32_t variant;      /* 0 per-node kernel, 1 node blocks one stage per launch, 2 two stages */
+  int32_t block_nodes;  /* nodes per block (0 for the per-node kernel) */
+  double us;            /* mean time of one gnmpc_condense call, microseconds */
+} gnmpc_tune_entry;
+typedef struct {
+  int32_t count;        /* candidates measured */
+  int32_t chosen;       /* index of the fastest: the plan's choice now */
+  gnmpc_tune_entry entry[GNMPC_TUNE_MAX];
+} gnmpc_tune_report;
+gnmpc_status gnmpc_autotune_condense(gnmpc_plan* plan, const void* A, const void* B, const void* c, const void* x0,
+                                     const void* Q, int32_t Q_full, const void* q, const void* R, const void* r,
+                                     const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt,
+                                     int32_t reps, gnmpc_tune_report* report, void* stream);
+/* Set the propagation variant directly (a recorded tuning result; variant and
+ * block_nodes as in gnmpc_tune_entry, -1 for the default choice):
+ * GNMPC_UNSUPPORTED, with the default restored, when those blocks do not fit
+ * LDS or have no two-stage form.  _get reads the current choice (variant -1 =
+ * default; block_nodes = nodes per block of the block records, 0 if none). */
+gnmpc_status gnmpc_condense_variant_set(gnmpc_plan* plan, int32_t variant, int32_t block_nodes);
+gnmpc_status gnmpc_condense_variant_get(const gnmpc_plan* plan, int32_t* variant, int32_t* block_nodes);
+
 /* Solve  min 1/2 u'Hu + g'u  s.t.  lb <= u <= ub,  lc <= Ct u <= uc
  * (the condensed QP of Sec. III-B with native box bounds, Algorithm 1
  * "Solve QP") by ADMM.  Device arrays of the plan dtype: H [n][n] symmetric
@@ -375,11 +407,14 @@ typedef struct {
 /* Batched step: linearize, condense and solve the box QP (Algorithm 1's
  * linearization, condensing and "Solve QP" of one MPC iteration) for `count`
  * independent instances of uneven sizes, each with its own plan on the same
- * device.  The instances run concurrently: the work is forked from `stream`
- * onto up to 4 library-owned streams (instance i on stream i mod 4) and joined
- * back with events, so `stream` is ordered after every instance, and a HIP
- * graph capture of `stream` records the whole batch (the library streams are
- * created on the first call, which must not be captured).  Settings apply to
+ * device.  Linearization, condensing and the QP set-up run concurrently: the
+ * work is forked from `stream` onto up to 4 library-owned streams (instance i
+ * on stream i mod 4) and joined back with events; then every instance's QP is
+ * solved in one launch per pass on `stream` (one workgroup per instance, up to
+ * 16 instances per launch), so `stream` is ordered after every instance and a
+ * HIP graph capture of `stream` records the whole batch (the library streams
+ * are created on the first call, which must not be captured).  Each instance's
+ * results are bitwise those of its single calls.  Settings apply to
  * every QP.  Each instance's arrays are validated as by the single calls; on
  * an error the work already forked is still joined and the first failing
  * status is returned (that plan's last_error names the cause).  Every plan

@@ -165,6 +165,7 @@ gnmpc_status gnmpc_plan_create(gnmpc_plan** plan, const gnmpc_dims* dims, int32_
   alloc(&p->d_qp, p->qp_bytes);
   alloc((void**)&p->d_qp_flag, 64);
   alloc(&p->d_check, lin_check_bytes());
+  alloc(&p->d_qpdesc, kQpDescBytes);
   if (st == GNMPC_OK && hipMemset(p->d_qp_flag, 0, 64) != hipSuccess) st = GNMPC_HIP_ERROR;
   if (st != GNMPC_OK) {
     gnmpc_plan_destroy(p);
@@ -243,6 +244,7 @@ void gnmpc_plan_destroy(gnmpc_plan* p) {
   if (p->d_part) (void)hipFree(p->d_part);
   if (p->d_qp) (void)hipFree(p->d_qp);
   if (p->d_check) (void)hipFree(p->d_check);
+  if (p->d_qpdesc) (void)hipFree(p->d_qpdesc);
   dfree(p->d_qp_flag);
   delete p;
 }
@@ -295,6 +297,7 @@ gnmpc_status gnmpc_graph_set(gnmpc_plan* p, const int32_t* row_ptr, const int32_
   if ((s = upload(p, p->d_diag, diag.data(), diag.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_cptr, cptr.data(), cptr.size())) != GNMPC_OK) return s;
   if ((s = upload(p, p->d_cent, cent.data(), cent.size())) != GNMPC_OK) return s;
+  p->prop_pref = -1;
   if ((s = prop_blocks_build(p)) != GNMPC_OK) return s;
   p->graph_ready = true;
   p->model = 0;  // a model must be (re)bound to the new graph
@@ -468,10 +471,8 @@ gnmpc_status gnmpc_condense(gnmpc_plan* p, const void* A, const void* B, const v
   return launch_condense(p, A, B, c, x0, Q, Q_full, q, R, r, rowC, rowd, H, g, Ct, dt, Gx, (hipStream_t)stream);
 }
 
-gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const void* g, const void* lb,
-                                const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc,
-                                const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, void* stream) {
-  if (!p) return GNMPC_INVALID_ARG;
+static gnmpc_status qp_check(gnmpc_plan* p, int32_t n, const void* H, const void* g, const void* lb, const void* ub,
+                             int32_t n_c, const void* Ct, const gnmpc_admm_settings* st, const void* u) {
   if (!H || !g || !lb || !ub || !u || !st) return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: null array");
   if (n <= 0 || n > p->dims.N * p->dims.nu) return fail(p, GNMPC_SHAPE, "solve_box_qp: n outside 1..N*nu");
   if (n_c < 0 || n_c > p->dims.n_c_max) return fail(p, GNMPC_SHAPE, "solve_box_qp: n_c outside 0..n_c_max");
@@ -479,6 +480,101 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const v
   if (!(st->rho > 0) || !(st->sigma > 0) || !(st->alpha > 0 && st->alpha < 2) || !(st->eps_abs >= 0) ||
       !(st->eps_rel >= 0) || st->max_iter < 1 || st->check_every < 1 || !(st->kappa_fp64 > 0))
     return fail(p, GNMPC_INVALID_ARG, "solve_box_qp: bad settings");
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_condense_variant_set(gnmpc_plan* p, int32_t variant, int32_t block_nodes) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "condense_variant_set: graph must be set");
+  if (variant < -1 || variant > 2 || (variant >= 1 && block_nodes != 1 && block_nodes != 2 && block_nodes != 4))
+    return fail(p, GNMPC_INVALID_ARG, "condense_variant_set: variant -1..2, blocks of 1, 2 or 4 nodes");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  gnmpc_status st = prop_blocks_build_nb(p, variant >= 1 ? block_nodes : 4);
+  if (st != GNMPC_OK) return st;
+  if (variant >= 1 && (p->pb_nodes != block_nodes || (variant == 2 && p->pb2_stride == 0))) {
+    p->prop_pref = -1;
+    const gnmpc_status sb = prop_blocks_build(p);
+    return sb != GNMPC_OK ? sb : fail(p, GNMPC_UNSUPPORTED, "condense_variant_set: these blocks do not fit LDS");
+  }
+  p->prop_pref = variant;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_condense_variant_get(const gnmpc_plan* p, int32_t* variant, int32_t* block_nodes) {
+  if (!p || !variant || !block_nodes) return GNMPC_INVALID_ARG;
+  *variant = p->prop_pref;
+  *block_nodes = p->pb_nodes;
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_autotune_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
+                                     const void* Q, int32_t Q_full, const void* q, const void* R, const void* r,
+                                     const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt,
+                                     int32_t reps, gnmpc_tune_report* rep, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!rep || reps < 1) return fail(p, GNMPC_INVALID_ARG, "autotune_condense: report and reps >= 1 required");
+  const hipStream_t s = (hipStream_t)stream;
+  // validate the arrays once, through the public call
+  gnmpc_status st = gnmpc_condense(p, A, B, c, x0, Q, Q_full, q, R, r, rowC, rowd, H, g, Ct, dt, nullptr, stream);
+  if (st != GNMPC_OK) return st;
+  struct Cand { int variant, nb; };
+  std::vector<Cand> cands{{0, 0}};
+  for (int nb = 4; nb >= 1; nb /= 2) {
+    if ((st = prop_blocks_build_nb(p, nb)) != GNMPC_OK) return st;
+    if (p->pb_nodes != nb) continue;  // blocks of nb nodes do not fit LDS
+    cands.push_back({1, nb});
+    if (p->pb2_stride > 0) cands.push_back({2, nb});
+  }
+  hipEvent_t e0, e1;
+  GNMPC_HIP_TRY(p, hipEventCreate(&e0));
+  GNMPC_HIP_TRY(p, hipEventCreate(&e1));
+  rep->count = 0;
+  rep->chosen = 0;
+  double best = 0.0;
+  for (const Cand& cd : cands) {
+    if (rep->count == GNMPC_TUNE_MAX) break;
+    if (cd.nb > 0 && (st = prop_blocks_build_nb(p, cd.nb)) != GNMPC_OK) break;
+    p->prop_pref = cd.variant;
+    if ((st = launch_condense(p, A, B, c, x0, Q, Q_full, q, R, r, rowC, rowd, H, g, Ct, dt, nullptr, s)) != GNMPC_OK)
+      break;
+    (void)hipEventRecord(e0, s);
+    for (int t = 0; t < reps && st == GNMPC_OK; ++t)
+      st = launch_condense(p, A, B, c, x0, Q, Q_full, q, R, r, rowC, rowd, H, g, Ct, dt, nullptr, s);
+    (void)hipEventRecord(e1, s);
+    if (st != GNMPC_OK || hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    gnmpc_tune_entry& en = rep->entry[rep->count];
+    en.variant = cd.variant;
+    en.block_nodes = cd.nb;
+    en.us = 1e3 * ms / reps;
+    if (rep->count == 0 || en.us < best) {
+      best = en.us;
+      rep->chosen = rep->count;
+    }
+    ++rep->count;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // keep the fastest (also after a failure part-way, so the plan stays usable)
+  if (rep->count > 0) {
+    const gnmpc_tune_entry& ch = rep->entry[rep->chosen];
+    const gnmpc_status sb = prop_blocks_build_nb(p, ch.block_nodes > 0 ? ch.block_nodes : 4);
+    p->prop_pref = ch.variant;
+    if (st == GNMPC_OK) st = sb;
+  } else {
+    p->prop_pref = -1;
+    const gnmpc_status sb = prop_blocks_build(p);
+    if (st == GNMPC_OK) st = sb;
+  }
+  return st;
+}
+
+gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const void* g, const void* lb,
+                                const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc,
+                                const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (const gnmpc_status cs = qp_check(p, n, H, g, lb, ub, n_c, Ct, st, u); cs != GNMPC_OK) return cs;
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
 }
@@ -563,6 +659,7 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
   GNMPC_HIP_TRY(p0, hipEventRecord(bs.fork, caller));
   for (int t = 0; t < used; ++t) GNMPC_HIP_TRY(p0, hipStreamWaitEvent(bs.s[t], bs.fork, 0));
   gnmpc_status first = GNMPC_OK;
+  std::vector<QpPrepared> prepared(count);
   for (int32_t i = 0; i < count && first == GNMPC_OK; ++i) {
     const gnmpc_step_desc& d = descs[i];
     gnmpc_plan* p = d.plan;
@@ -572,8 +669,10 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
     if (s == GNMPC_OK)
       s = gnmpc_condense(p, d.A, d.B, d.c, d.x0, d.Q, d.Q_full, d.q, d.R, d.r, d.rowC, d.rowd, d.H, d.g, d.Ct,
                          d.dt, nullptr, si);
+    if (s == GNMPC_OK) s = qp_check(p, n, d.H, d.g, d.lb, d.ub, p->n_c, d.Ct, st, d.u);
     if (s == GNMPC_OK)
-      s = gnmpc_solve_box_qp(p, n, d.H, d.g, d.lb, d.ub, p->n_c, d.Ct, d.lc, d.uc, st, d.u, d.info, si);
+      s = launch_qp_prep(p, n, d.H, d.g, d.lb, d.ub, p->n_c, d.Ct, d.lc, d.uc, st, d.u, d.info, (hipStream_t)si,
+                         &prepared[i]);
     first = s;
   }
   // join every forked stream, also after an error
@@ -581,7 +680,11 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
     GNMPC_HIP_TRY(p0, hipEventRecord(bs.join[t], bs.s[t]));
     GNMPC_HIP_TRY(p0, hipStreamWaitEvent(caller, bs.join[t], 0));
   }
-  return first;
+  if (first != GNMPC_OK) return first;
+  // every instance's QP in one launch per pass (one workgroup each) on the caller's stream
+  const gnmpc_status qs = launch_qp_batched(prepared.data(), count, caller);
+  if (qs != GNMPC_OK) return fail(p0, qs, "step_batched: batched QP launch failed");
+  return GNMPC_OK;
 }
 
 gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,

@@ -782,11 +782,11 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   const int wmax = p->wmax;
   const size_t pb_lds = sizeof(T) * ((size_t)p->pb_umax * NBX * (kPropCW + 1) + (size_t)p->pb_emax * 36) +
                         sizeof(int32_t) * (size_t)p->pb_rec_stride;
-  const bool use_blocks = p->pb_nodes > 0 && pb_lds <= 64 * 1024;
+  const bool use_blocks = p->pb_nodes > 0 && pb_lds <= 64 * 1024 && p->prop_pref != 0;
   if (use_blocks)
     GNMPC_HIP_TRY(p, set_max_lds((const void*)sprop_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)pb_lds));
-  const bool use2 = use_blocks && p->pb2_stride > 0;
+  const bool use2 = use_blocks && p->pb2_stride > 0 && p->prop_pref != 1;
   size_t pb2_lds = 0;
   if (use2) {
     const Prop2Layout L2 = prop2_layout(p->pb_nodes, p->pb_emax, p->pb2_u1max, p->pb2_e1max, p->pb2_u2max);
@@ -877,17 +877,19 @@ void prop_blocks_free(gnmpc_plan* p) {
   p->pb_nodes = p->pb_count = p->pb_umax = p->pb_emax = p->pb_rec_stride = 0;
 }
 
-// Node blocks for the block propagation kernel: the largest block size (4, 2,
-// 1 nodes: one thread per node and column of a 64-column slice) whose staged
-// union and A blocks fit 64 KB of LDS in the plan's precision; pb_nodes = 0 if
-// even single nodes do not fit.
+// Node blocks for the block propagation kernel: the largest block size (up to
+// nb_max of 4, 2, 1 nodes: one thread per node and column of a 64-column slice)
+// whose staged union and A blocks fit 64 KB of LDS in the plan's precision;
+// pb_nodes = 0 if even single nodes do not fit.
 gnmpc_status prop_blocks2_build(gnmpc_plan* p);
 
-gnmpc_status prop_blocks_build(gnmpc_plan* p) {
+gnmpc_status prop_blocks_build(gnmpc_plan* p) { return prop_blocks_build_nb(p, 4); }
+
+gnmpc_status prop_blocks_build_nb(gnmpc_plan* p, int nb_max) {
   prop_blocks_free(p);
   const int M = p->M;
   const size_t elem = (size_t)p->elem;
-  for (int nb = 4; nb >= 1; nb /= 2) {
+  for (int nb = nb_max; nb >= 1; nb /= 2) {
     std::vector<int32_t> ubeg(1, 0), ulist, epos(p->h_pcol.size());
     int umax = 0, emax = 0;
     for (int node0 = 0; node0 < M; node0 += nb) {

@@ -34,6 +34,9 @@ struct gnmpc_plan {
   // union U2 of U1's pattern rows, U1's entries with their positions in U2
   int pb2_stride = 0, pb2_u1max = 0, pb2_u2max = 0, pb2_e1max = 0;
   int32_t* d_pb2_rec = nullptr;
+  // propagation variant: -1 the default choice, 0 per-node kernel, 1 one-stage
+  // blocks, 2 two-stage blocks where they fit (set by gnmpc_autotune_condense)
+  int prop_pref = -1;
 
   // model
   int model = 0;  // 0 none, 1 mass-spring-damper, 2 GNN, 3 interaction network
@@ -59,6 +62,7 @@ struct gnmpc_plan {
   void* d_qp = nullptr;
   size_t qp_bytes = 0;
   int32_t* d_qp_flag = nullptr;
+  void* d_qpdesc = nullptr;  // the QP's solve descriptor, for batched solves (kQpDescBytes)
 
   // per-block partial counts of the finiteness check of gnmpc_linearize
   void* d_check = nullptr;
@@ -123,10 +127,23 @@ gnmpc_status launch_condense(gnmpc_plan* p, const void* A, const void* B, const 
 // qp_admm.hip
 size_t qp_workspace_bytes(int n, int n_c);
 gnmpc_status prop_blocks_build(gnmpc_plan* p);
+gnmpc_status prop_blocks_build_nb(gnmpc_plan* p, int nb_max);
 void prop_blocks_free(gnmpc_plan* p);
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
                        int n_c, const void* Ct, const void* lc, const void* uc,
                        const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s);
+// A QP whose set-up kernel has been enqueued (launch_qp_prep): that kernel also
+// stored its solve descriptor at desc (the plan's d_qpdesc); launch_qp_batched
+// solves many such QPs in one launch per pass.
+constexpr size_t kQpDescBytes = 256;
+struct QpPrepared {
+  int dtype, n, n_c;
+  void* desc;
+};
+gnmpc_status launch_qp_prep(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
+                            int n_c, const void* Ct, const void* lc, const void* uc, const gnmpc_admm_settings* st,
+                            void* u, gnmpc_qp_info* info, hipStream_t s, QpPrepared* out);
+gnmpc_status launch_qp_batched(const QpPrepared* q, int count, hipStream_t s);
 // Allocation-free QP (workspace in a static device array; see qp_admm.hip).
 constexpr int kQpNoallocMaxN = 464;
 gnmpc_status qp_noalloc_check(int dtype, int n, int n_c);

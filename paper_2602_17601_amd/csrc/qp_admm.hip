@@ -19,7 +19,9 @@
 // right behind it) redoes factorization and iterations in FP64.
 #include <math.h>
 
+#include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -210,8 +212,10 @@ __device__ inline void bmma(double acc[4], const double* A, const double* B) {
 // raise flag[1].  Column slices of Ct are staged through LDS 64 rows at a time.
 constexpr int kPrepRows = 224;  // rows staged per pass (every load of a pass in flight at once)
 template <typename Tin>
-__global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G) {
+__global__ void __launch_bounds__(256) qp_prep_kernel(QpArgs<Tin> a, double* G, QpArgs<Tin>* desc_out) {
   __shared__ double ci[kPrepRows][16], cj[kPrepRows][16], rr[kPrepRows];
+  // the solve descriptor, for a batched solve that reads it from memory
+  if (desc_out && blockIdx.x == 0 && threadIdx.x == 0) *desc_out = a;
   const int n = a.n;
   const int b = blockIdx.x, e = threadIdx.x;
   int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
@@ -823,7 +827,7 @@ __device__ inline void rp_flush(float (&acc)[kMJ], float* part, int n) {
 // workspace).  A compile-time choice, so the LDS instance addresses it with LDS
 // instructions rather than generic ones.
 template <typename T, typename Tin, bool MAT_LDS>
-__global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int mode) {
+__device__ __attribute__((always_inline)) void qp_solve_body(const QpArgs<Tin>& a, int mode) {
   // mode 0: primary pass in T (may hand over to FP64); 1: FP64 pass, runs only
   // if the primary pass raised the flag; 2: the only pass.
   if (mode == 1 && *(volatile int32_t*)a.flag == 0) {
@@ -1241,6 +1245,27 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   }
 }
 
+template <typename T, typename Tin, bool MAT_LDS>
+__global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int mode) {
+  qp_solve_body<T, Tin, MAT_LDS>(a, mode);
+}
+
+// Many instances' QPs in one launch, one workgroup each: each instance's set-up
+// kernel stored its solve descriptor in its plan's memory, and the launch takes
+// the addresses (kernel arguments, so the launch needs no copy and a graph can
+// capture it).  Each workgroup is the single-instance solve of its own
+// descriptor, so results are the same bits.
+constexpr int kQpBatchMax = 256;
+template <typename Tin>
+struct QpBatch {
+  const QpArgs<Tin>* a[kQpBatchMax];
+};
+template <typename T, typename Tin, bool MAT_LDS>
+__global__ void __launch_bounds__(kQpThreads) qp_solve_batched_kernel(QpBatch<Tin> b, int mode) {
+  const QpArgs<Tin> a = *b.a[blockIdx.x];
+  qp_solve_body<T, Tin, MAT_LDS>(a, mode);
+}
+
 size_t lds_bytes(int n, int nc, size_t elem, bool mat) {
   const int m = n + nc;
   auto r4 = [](size_t c) { return (c + 3) & ~(size_t)3; };
@@ -1277,9 +1302,9 @@ __global__ void qp_flag_clear_kernel(int32_t* flag) {
 // 256-byte aligned) and its two flags at `flag`; p (may be null) receives the
 // error text and the phase timer records.
 template <typename Tin>
-gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const void* H, const void* g,
-                 const void* lb, const void* ub, int n_c, const void* Ct, const void* lc, const void* uc,
-                 const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s) {
+QpArgs<Tin> make_args(unsigned char* ws, int32_t* flag, int n, const void* H, const void* g, const void* lb,
+                      const void* ub, int n_c, const void* Ct, const void* lc, const void* uc,
+                      const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info) {
   QpArgs<Tin> a;
   a.n = n;
   a.n_c = n_c;
@@ -1306,8 +1331,22 @@ gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const v
   a.kappa_fp64 = st->kappa_fp64;
   a.max_iter = st->max_iter;
   a.check_every = st->check_every;
+  return a;
+}
+
+template <typename Tin>
+void launch_prep(const QpArgs<Tin>& a, hipStream_t s, QpArgs<Tin>* desc_out = nullptr) {
+  const size_t nbo = bo(nblocks(a.n), 0);
+  qp_prep_kernel<Tin><<<(int)(nbo / 256), 256, 0, s>>>(a, const_cast<double*>(a.G), desc_out);
+}
+
+template <typename Tin>
+gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const void* H, const void* g,
+                 const void* lb, const void* ub, int n_c, const void* Ct, const void* lc, const void* uc,
+                 const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, hipStream_t s) {
+  const QpArgs<Tin> a = make_args<Tin>(ws, flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info);
   if (p) phase_begin(p, GNMPC_PH_QP, s);
-  qp_prep_kernel<Tin><<<(int)(nbo / 256), 256, 0, s>>>(a, (double*)ws);
+  launch_prep(a, s);
   gnmpc_status rc;
   if (sizeof(Tin) == 8) {
     rc = launch_pass<double, Tin>(p, a, 2, s);
@@ -1320,6 +1359,37 @@ gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const v
   if (hipGetLastError() != hipSuccess) {
     if (p) p->last_error = "QP: kernel launch failed";
     return GNMPC_HIP_ERROR;
+  }
+  return GNMPC_OK;
+}
+
+// One pass of the batched solve over the prepared instances of one input type:
+// T is the pass arithmetic; instances whose factor fits LDS and the others go to
+// the two instances of the kernel, up to kQpBatchMax per launch, LDS sized for
+// the largest member of each launch.
+template <typename T, typename Tin>
+gnmpc_status batched_pass(const std::vector<const QpPrepared*>& all, int mode, hipStream_t s) {
+  for (int lds_kind = 1; lds_kind >= 0; --lds_kind) {
+    std::vector<const QpPrepared*> sel;
+    for (const QpPrepared* q : all)
+      if ((lds_bytes(q->n, q->n_c, sizeof(T), true) <= kLdsCap) == (lds_kind == 1)) sel.push_back(q);
+    for (size_t c0 = 0; c0 < sel.size(); c0 += kQpBatchMax) {
+      const int cnt = (int)std::min<size_t>(kQpBatchMax, sel.size() - c0);
+      QpBatch<Tin> b;
+      size_t lds = 0;
+      for (int q = 0; q < cnt; ++q) {
+        b.a[q] = static_cast<const QpArgs<Tin>*>(sel[c0 + q]->desc);
+        lds = std::max(lds, lds_bytes(sel[c0 + q]->n, sel[c0 + q]->n_c, sizeof(T), lds_kind == 1));
+      }
+      for (int q = cnt; q < kQpBatchMax; ++q) b.a[q] = b.a[0];  // not launched
+      if (lds > kLdsCap) return GNMPC_UNSUPPORTED;
+      const void* fn = lds_kind ? (const void*)qp_solve_batched_kernel<T, Tin, true>
+                                : (const void*)qp_solve_batched_kernel<T, Tin, false>;
+      if (set_max_lds(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return GNMPC_HIP_ERROR;
+      if (lds_kind) qp_solve_batched_kernel<T, Tin, true><<<cnt, kQpThreads, lds, s>>>(b, mode);
+      else qp_solve_batched_kernel<T, Tin, false><<<cnt, kQpThreads, lds, s>>>(b, mode);
+      if (hipGetLastError() != hipSuccess) return GNMPC_HIP_ERROR;
+    }
   }
   return GNMPC_OK;
 }
@@ -1343,6 +1413,37 @@ size_t qp_workspace_bytes(int n, int n_c) {
   (void)n_c;
   return (sizeof(double) * (size_t)n * n + 255) / 256 * 256 + sizeof(double) * (2 * bo(nblocks(n), 0) + 64) +
          sizeof(float) * bo(nblocks(n), 0);
+}
+
+static_assert(sizeof(QpArgs<double>) <= kQpDescBytes && sizeof(QpArgs<float>) <= kQpDescBytes,
+              "a plan's descriptor buffer holds a solve descriptor");
+
+gnmpc_status launch_qp_prep(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
+                            int n_c, const void* Ct, const void* lc, const void* uc, const gnmpc_admm_settings* st,
+                            void* u, gnmpc_qp_info* info, hipStream_t s, QpPrepared* out) {
+  unsigned char* ws = (unsigned char*)p->d_qp;
+  out->dtype = p->dims.dtype;
+  out->n = n;
+  out->n_c = n_c;
+  out->desc = p->d_qpdesc;
+  if (p->dims.dtype == GNMPC_F64)
+    launch_prep(make_args<double>(ws, p->d_qp_flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info), s,
+                static_cast<QpArgs<double>*>(p->d_qpdesc));
+  else
+    launch_prep(make_args<float>(ws, p->d_qp_flag, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info), s,
+                static_cast<QpArgs<float>*>(p->d_qpdesc));
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
+}
+
+gnmpc_status launch_qp_batched(const QpPrepared* q, int count, hipStream_t s) {
+  std::vector<const QpPrepared*> f, d;
+  for (int t = 0; t < count; ++t) (q[t].dtype == GNMPC_F64 ? d : f).push_back(&q[t]);
+  gnmpc_status rc = GNMPC_OK;
+  if (!f.empty()) rc = batched_pass<float, float>(f, 0, s);
+  if (rc == GNMPC_OK && !f.empty()) rc = batched_pass<double, float>(f, 1, s);
+  if (rc == GNMPC_OK && !d.empty()) rc = batched_pass<double, double>(d, 2, s);
+  return rc;
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,

@@ -50,6 +50,14 @@ class InetDesc(C.Structure):
                 ("phi_hidden", C.c_int32), ("phi_width", C.c_int32), ("nu", C.c_int32), ("dt", C.c_double)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("block_nodes", C.c_int32), ("us", C.c_double)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("count", C.c_int32), ("chosen", C.c_int32), ("entry", TuneEntry * 16)]
+
+
 class AdmmSettings(C.Structure):
     _fields_ = [("rho", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("eps_abs", C.c_double),
                 ("eps_rel", C.c_double), ("kappa_fp64", C.c_double), ("max_iter", C.c_int32),
@@ -110,6 +118,9 @@ def lib():
             "gnmpc_jvp": ([vp] * 7, i32),
             "gnmpc_vjp": ([vp] * 7, i32),
             "gnmpc_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 11, i32),
+            "gnmpc_condense_variant_set": ([vp, i32, i32], i32),
+            "gnmpc_condense_variant_get": ([vp, P(i32), P(i32)], i32),
+            "gnmpc_autotune_condense": ([vp, vp, vp, vp, vp, vp, i32] + [vp] * 9 + [i32, P(TuneReport), vp], i32),
             "gnmpc_solve_box_qp": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp], i32),
             "gnmpc_gnn_forward": ([vp, vp, vp, vp, vp], i32),
             "gnmpc_msd_simulate": ([vp, i32, i32, vp, vp, vp, vp], i32),
@@ -345,6 +356,34 @@ class Plan:
                 self._dev(Ct, (nc, n), "Ct", allow_none=nc == 0), self._dev(dt, (nc,), "dt", allow_none=nc == 0),
                 self._dev(Gx, (N + 1, M, 6), "Gx", allow_none=True)]
         self._check(lib().gnmpc_condense(self._h, *args, _stream(stream)), "condense")
+
+    def autotune_condense(self, A, B, c, x0, Q, q, R, r, rowC, rowd, H, g, Ct, dt, reps=5, stream=None):
+        """gnmpc_autotune_condense: time every propagation variant on these arrays, keep
+        the fastest; returns (chosen index, [dict(variant, block_nodes, us)])."""
+        M, N, nu, nc = self.M, self.N, self.nu, self.n_c
+        full = 1 if Q.dim() == 4 else 0
+        qshape = (N + 1, M, 6, 6) if full else (N + 1, M, 6)
+        n = N * nu
+        args = [self._dev(A, (N, self.nnz, 6, 6), "A"), self._dev(B, (N, M, 6, nu), "B"),
+                self._dev(c, (N, M, 6), "c"), self._dev(x0, (M, 6), "x0"), self._dev(Q, qshape, "Q"), full,
+                self._dev(q, (N + 1, M, 6), "q"), self._dev(R, (N, nu, nu), "R"), self._dev(r, (N, nu), "r"),
+                self._dev(rowC, (nc, 6), "rowC", allow_none=nc == 0), self._dev(rowd, (nc,), "rowd", allow_none=nc == 0),
+                self._dev(H, (n, n), "H"), self._dev(g, (n,), "g"),
+                self._dev(Ct, (nc, n), "Ct", allow_none=nc == 0), self._dev(dt, (nc,), "dt", allow_none=nc == 0)]
+        rep = TuneReport()
+        self._check(lib().gnmpc_autotune_condense(self._h, *args, int(reps), C.byref(rep), _stream(stream)),
+                    "autotune_condense")
+        return rep.chosen, [dict(variant=rep.entry[t].variant, block_nodes=rep.entry[t].block_nodes, us=rep.entry[t].us)
+                            for t in range(rep.count)]
+
+    def condense_variant(self, variant=None, block_nodes=0):
+        """Set the propagation variant (gnmpc_condense_variant_set) when given; return
+        the current (variant, block_nodes)."""
+        if variant is not None:
+            self._check(lib().gnmpc_condense_variant_set(self._h, int(variant), int(block_nodes)), "condense_variant")
+        v, nb = C.c_int32(), C.c_int32()
+        self._check(lib().gnmpc_condense_variant_get(self._h, C.byref(v), C.byref(nb)), "condense_variant")
+        return v.value, nb.value
 
     def solve_box_qp(self, H, g, lb, ub, Ct, lc, uc, u, info=None, settings=None, stream=None):
         n = g.shape[0]
