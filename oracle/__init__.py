@@ -18,6 +18,8 @@ Modules (each function cites the passage it follows):
   mpc       -- one iteration of the GNN-MPC loop with its shift (Algorithm 1)
   inet      -- the paper's own model, an interaction network with a global input
                (Sec. V-A eq. forward_dynamics), and its forward-mode linearization
+  train     -- the training loss (weighted MSE plus an l2 penalty, Sec. V-A
+               "Training"), its gradient by reverse mode, and the Adam update
 
 Everything is float64.  Cost convention: stage cost 1/2 x'Qx + q'x + 1/2 u'Ru + r'u
 and QP objective 1/2 u'Hu + g'u, under which the paper's formulas for H and g
