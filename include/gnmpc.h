@@ -288,6 +288,29 @@ gnmpc_status gnmpc_gnn_forward(gnmpc_plan* plan, const void* xhat, const void* u
 gnmpc_status gnmpc_gnn_vjp(gnmpc_plan* plan, const void* xhat, const void* uhat, const void* g, void* gx,
                            void* gu, void* stream);
 
+/* Training of the GNN (Sec. V-A "Training"): the loss
+ *   L = 1/S sum_t || x_next[t] - F_theta(x[t], u[t]) ||_O^2 + lambda ||theta||^2
+ * over S = N samples (the plan's horizon is the batch; ||r||_O^2 = sum over the
+ * nodes of r' diag(O) r) and its gradient with respect to theta, by reverse
+ * mode through the decoder, the L rounds and the encoder, FP32 on the device.
+ * theta: device FP32 array of n_params parameters packed as the weights of
+ * gnmpc_model_set_gnn (the plan's own weights are not used, so a training loop
+ * never leaves the device; the plan supplies the graph, Hd, L, dt and the
+ * actuated nodes).  x, x_next [N][M][6], u [N][nu]: FP32 device; O: host [6],
+ * >= 0; workspace: device, workspace_bytes from gnmpc_gnn_train_sizes; loss:
+ * device [1]; grad: device [n_params], every entry written.  Deterministic
+ * (fixed-order sums).  GNMPC_NOT_READY unless the graph and a GNN model are
+ * set; GNMPC_UNSUPPORTED for an FP64 plan. */
+gnmpc_status gnmpc_gnn_train_sizes(const gnmpc_plan* plan, int64_t* n_params, int64_t* workspace_bytes);
+gnmpc_status gnmpc_gnn_loss_grad(gnmpc_plan* plan, const float* theta, const void* x, const void* u,
+                                 const void* x_next, const float* O, double lambda, void* workspace, float* loss,
+                                 float* grad, void* stream);
+/* One Adam update (Kingma and Ba, with bias correction; step counts from 1) of
+ * the n device FP32 parameters theta from grad, with the moment estimates m, v
+ * (device, n each, zero before step 1), in place. */
+gnmpc_status gnmpc_adam_step(int64_t n, float* theta, const float* grad, float* m, float* v, int32_t step,
+                             double lr, double beta1, double beta2, double eps, void* stream);
+
 /* Tangent maps of the linearized one-step model x_{k+1} = f(x_k, u_k) of Sec. V-A,
  * from the blocks gnmpc_linearize produced (A [N][nnz][6][6], B [N][M][6][nu], in
  * the plan's pattern and dtype).  Device arrays of the plan dtype, all N stages:

@@ -457,6 +457,38 @@ gnmpc_status gnmpc_gnn_vjp(gnmpc_plan* p, const void* xhat, const void* uhat, co
   return launch_gnn_vjp(p, xhat, uhat, g, gx, gu, (hipStream_t)stream);
 }
 
+gnmpc_status gnmpc_gnn_train_sizes(const gnmpc_plan* p, int64_t* n_params, int64_t* workspace_bytes) {
+  if (!p || !n_params || !workspace_bytes) return GNMPC_INVALID_ARG;
+  if (!p->graph_ready || p->model != 2) return GNMPC_NOT_READY;
+  *n_params = gnn_param_count(p);
+  *workspace_bytes = (int64_t)gnn_train_workspace_bytes(p);
+  return GNMPC_OK;
+}
+
+gnmpc_status gnmpc_gnn_loss_grad(gnmpc_plan* p, const float* theta, const void* x, const void* u, const void* x_next,
+                                 const float* O, double lambda, void* workspace, float* loss, float* grad,
+                                 void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!theta || !x || !u || !x_next || !O || !workspace || !loss || !grad)
+    return fail(p, GNMPC_INVALID_ARG, "gnn_loss_grad: null array");
+  if (!p->graph_ready || p->model != 2) return fail(p, GNMPC_NOT_READY, "gnn_loss_grad: graph and GNN model must be set");
+  if (p->dims.dtype != GNMPC_F32) return fail(p, GNMPC_UNSUPPORTED, "gnn_loss_grad: the plan's arrays must be FP32");
+  if (!(lambda >= 0) || !std::isfinite(lambda)) return fail(p, GNMPC_INVALID_ARG, "gnn_loss_grad: lambda >= 0");
+  for (int c = 0; c < 6; ++c)
+    if (!(O[c] >= 0) || !std::isfinite(O[c])) return fail(p, GNMPC_INVALID_ARG, "gnn_loss_grad: O must be >= 0");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_gnn_loss_grad(p, theta, x, u, x_next, O, lambda, workspace, loss, grad, (hipStream_t)stream);
+}
+
+gnmpc_status gnmpc_adam_step(int64_t n, float* theta, const float* grad, float* m, float* v, int32_t step, double lr,
+                             double beta1, double beta2, double eps, void* stream) {
+  if (n < 0 || (n > 0 && (!theta || !grad || !m || !v)) || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return GNMPC_INVALID_ARG;
+  if (n == 0) return GNMPC_OK;
+  return launch_adam(n, theta, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
 gnmpc_status gnmpc_condense(gnmpc_plan* p, const void* A, const void* B, const void* c, const void* x0,
                             const void* Q, int32_t Q_full, const void* q, const void* R, const void* r,
                             const void* rowC, const void* rowd, void* H, void* g, void* Ct, void* dt, void* Gx,

@@ -171,6 +171,13 @@ gnmpc_status inet_set(gnmpc_plan* p, const gnmpc_inet_desc* d, const double* w, 
 void inet_free(gnmpc_plan* p);
 gnmpc_status launch_inet_linearize(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c,
                                    void* fnext, hipStream_t s);
+// train.hip
+size_t gnn_train_workspace_bytes(const gnmpc_plan* p);
+long gnn_param_count(const gnmpc_plan* p);
+gnmpc_status launch_gnn_loss_grad(gnmpc_plan* p, const float* theta, const void* x, const void* u, const void* xn,
+                                  const float* O, double lambda, void* ws, float* loss, float* grad, hipStream_t s);
+gnmpc_status launch_adam(long n, float* theta, const float* grad, float* m, float* v, int step, double lr,
+                         double beta1, double beta2, double eps, hipStream_t s);
 // msd_sim.hip
 bool msd_sim_fits(const gnmpc_plan* p);
 gnmpc_status launch_msd_simulate(gnmpc_plan* p, int B, int T, const void* x0, const void* u, void* X, hipStream_t s);

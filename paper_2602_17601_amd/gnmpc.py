@@ -125,6 +125,9 @@ def lib():
             "gnmpc_gnn_forward": ([vp, vp, vp, vp, vp], i32),
             "gnmpc_msd_simulate": ([vp, i32, i32, vp, vp, vp, vp], i32),
             "gnmpc_gnn_vjp": ([vp, vp, vp, vp, vp, vp, vp], i32),
+            "gnmpc_gnn_train_sizes": ([vp, P(i64), P(i64)], i32),
+            "gnmpc_gnn_loss_grad": ([vp, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp], i32),
+            "gnmpc_adam_step": ([i64, vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp], i32),
             "gnmpc_solve_box_qp_noalloc": ([i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp],
                                            i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
@@ -261,6 +264,24 @@ class Plan:
         self._check(lib().gnmpc_model_set_msd(self._h, C.byref(p), _hp(a), len(a)), "model_set_msd")
         self.model = "msd"
 
+    def gnn_train_sizes(self):
+        """(number of parameters, workspace bytes) of gnmpc_gnn_loss_grad."""
+        n, b = C.c_int64(), C.c_int64()
+        self._check(lib().gnmpc_gnn_train_sizes(self._h, C.byref(n), C.byref(b)), "gnn_train_sizes")
+        return n.value, b.value
+
+    def gnn_loss_grad(self, theta, x, u, x_next, O, lam, workspace, loss, grad, stream=None):
+        """gnmpc_gnn_loss_grad over the plan's N samples: loss [1] and grad [n_params]
+        (FP32 device) at theta (FP32 device, the packing of gnn_flat)."""
+        M, N, nu = self.M, self.N, self.nu
+        n, wb = self.gnn_train_sizes()
+        Oh = np.ascontiguousarray(np.asarray(O, dtype=np.float32).reshape(6))
+        args = [self._dev(theta, (n,), "theta", dtype=torch.float32), self._dev(x, (N, M, 6), "x"),
+                self._dev(u, (N, nu), "u"), self._dev(x_next, (N, M, 6), "x_next"), _hp(Oh), float(lam),
+                self._dev(workspace, (wb,), "workspace", dtype=torch.uint8),
+                self._dev(loss, (1,), "loss", dtype=torch.float32), self._dev(grad, (n,), "grad", dtype=torch.float32)]
+        self._check(lib().gnmpc_gnn_loss_grad(self._h, *args, _stream(stream)), "gnn_loss_grad")
+
     def model_set_inet(self, W):
         """The interaction network (workloads.InetWeights) as the plan's model."""
         d = InetDesc(len(W.psi_W) - 1, int(W.psi_W[0].shape[0]) if len(W.psi_W) > 1 else 1, W.d_m,
@@ -270,11 +291,7 @@ class Plan:
         self.model = "inet"
 
     def model_set_gnn(self, W, act, dtype=F32):
-        flat = [W.W_enc, W.b_enc]
-        for l in range(W.L):
-            flat += [W.W_edge[l], W.b_edge[l], W.W_node[l], W.b_node[l]]
-        flat += [W.W_dec, W.b_dec]
-        w = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).reshape(-1) for x in flat]))
+        w = gnn_flat(W)
         d = GnnDesc(W.Hd, W.L, dtype, 0, W.dt)
         a = _i32(act)
         self._check(lib().gnmpc_model_set_gnn(self._h, C.byref(d), _hp(w), w.size, _hp(a), len(a)),
@@ -444,6 +461,29 @@ def solve_box_qp_noalloc(H, g, lb, ub, Ct, lc, uc, u, info=None, settings=None, 
     s = lib().gnmpc_solve_box_qp_noalloc(F64 if dtype == torch.float64 else F32, n, *args, _stream(stream))
     if s != OK:
         raise GnmpcError(s, "solve_box_qp_noalloc: " + status_string(s))
+
+
+def gnn_flat(W):
+    """The GNN's parameters packed as the library takes them (float64): W_enc, b_enc,
+    per round W_e, b_e, W_n, b_n, then W_dec, b_dec."""
+    flat = [W.W_enc, W.b_enc]
+    for l in range(W.L):
+        flat += [W.W_edge[l], W.b_edge[l], W.W_node[l], W.b_node[l]]
+    flat += [W.W_dec, W.b_dec]
+    return np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).reshape(-1) for x in flat]))
+
+
+def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """gnmpc_adam_step in place on FP32 device tensors of equal size."""
+    n = theta.numel()
+    for t, name in ((theta, "theta"), (grad, "grad"), (m, "m"), (v, "v")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and t.numel() == n):
+            raise GnmpcError(SHAPE, f"adam_step: {name} must be a contiguous float32 CUDA tensor of {n} entries")
+    s = lib().gnmpc_adam_step(n, C.c_void_p(theta.data_ptr()), C.c_void_p(grad.data_ptr()), C.c_void_p(m.data_ptr()),
+                              C.c_void_p(v.data_ptr()), int(step), lr, beta1, beta2, eps, _stream(stream))
+    if s != OK:
+        raise GnmpcError(s, "adam_step")
 
 
 def step_desc(plan, b):
