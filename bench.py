@@ -424,6 +424,7 @@ def main():
                         "plain": closed_loop_rate(torch, gn, wl, "msd"),
                         "gnn": closed_loop_rate(torch, gn, wl, "gnn")},
         "paper_model": paper_model_rate(torch, gn, wl),
+        "training": training_rate(torch, gn, wl),
     }
     print(json.dumps(out), flush=True)
 
@@ -595,6 +596,51 @@ def paper_model_rate(torch, gn, wl, iters=50):
     return {"workload": "interaction network (psi 4x50, phi 8x250), 4 nodes x 2 neighbours, n_u=6, N=20, FP32",
             "linearize_ms": lin_ms, "rti_step_ms": rti_ms, "rti_steps_per_s": 1e3 / rti_ms,
             "qp_iters": gn.qp_info(b["info"]).iters}
+
+
+def training_rate(torch, gn, wl, iters=10):
+    """One training step (loss, gradient with respect to every parameter, Adam) of
+    the 1000-node GNN (Hd = 128, L = 3, FP32) on a batch of 20 samples from the
+    spring-damper simulator; HIP events on the stream the step runs on."""
+    M, B, T = 1000, 5, 4
+    sim = wl.simulator_batch(B, T, M=M)
+    S = B * T
+    splan = gn.Plan(M, sim.nu, 1, 0, gn.F32)
+    splan.graph_set(sim.row_ptr, sim.col, 1)
+    splan.model_set_msd(sim.msd, sim.act)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+    X = torch.empty(B, T + 1, M, 6, device="cuda")
+    splan.msd_simulate(t(sim.x0), t(sim.u), X)
+    x, xn = X[:, :T].reshape(S, M, 6).contiguous(), X[:, 1:].reshape(S, M, 6).contiguous()
+    u = t(sim.u).reshape(S, sim.nu)
+    W = wl.gnn_weights(3, 128, 3, dt=sim.msd.dt)
+    plan = gn.Plan(M, sim.nu, S, 0, gn.F32)
+    plan.graph_set(sim.row_ptr, sim.col, 3)
+    # training reads the plan's graph, sizes and inputs only (theta is its own FP32
+    # array); the BF16 setting is the one whose Jacobian tables fit this graph
+    plan.model_set_gnn(W, sim.act, dtype=gn.BF16)
+    n, wb = plan.gnn_train_sizes()
+    theta = t(gn.gnn_flat(W))
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    grad, m, v = (torch.zeros(n, device="cuda") for _ in range(3))
+    loss = torch.empty(1, device="cuda")
+    O = [1, 1, 1, 1, 1, 1]
+
+    def step(k):
+        plan.gnn_loss_grad(theta, x, u, xn, O, 1e-6, ws, loss, grad)
+        gn.adam_step(theta, grad, m, v, k, 1e-3)
+
+    step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(iters):
+        step(k + 2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    return {"workload": f"GNN Hd=128 L=3, {M}-node chain, {S} samples per step, FP32", "params": n,
+            "ms_per_step": ms, "samples_per_s": S * 1e3 / ms, "node_samples_per_s": S * M * 1e3 / ms}
 
 
 def bench_batch(args, torch, gn, wl):
