@@ -424,9 +424,36 @@ def main():
                         "plain": closed_loop_rate(torch, gn, wl, "msd"),
                         "gnn": closed_loop_rate(torch, gn, wl, "gnn")},
         "paper_model": paper_model_rate(torch, gn, wl),
+        "ipm": ipm_rate(torch, gn, plan_g, bg, settings),
         "training": training_rate(torch, gn, wl),
     }
     print(json.dumps(out), flush=True)
+
+
+def ipm_rate(torch, gn, plan, b, settings, reps=10):
+    """The interior-point QP solver on the GNN step's own condensed QP (as left in
+    b by the timed steps: 240 inputs, 200 state rows), against ADMM on it."""
+    u = torch.empty_like(b["u"])
+    info = torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device=u.device)
+    admm = lambda: plan.solve_box_qp(b["H"], b["g"], b["lb"], b["ub"], b["Ct"], None, b["dt"], b["u"], b["info"],
+                                     settings=settings)
+    out = {"workload": "condensed QP of the GNN step: 240 inputs, box bounds, 200 one-sided state rows"}
+    for name, fn in [("admm", admm)] + [
+            (f"ipm_tol_{tol:g}", (lambda tol=tol: plan.solve_qp_ipm(b["H"], b["g"], b["lb"], b["ub"], b["Ct"], None,
+                                                                    b["dt"], u, info, tol=tol)))
+            for tol in (1e-6, 1e-10)]:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        inf = gn.qp_info(info if name != "admm" else b["info"])
+        out[name] = {"ms": e0.elapsed_time(e1) / reps, "iters": inf.iters, "status": inf.status}
+    out["ipm_vs_admm_rel"] = float((u - b["u"]).norm() / b["u"].norm().clamp_min(1e-30))
+    return out
 
 
 def tangent_rates(gn, plan, b, reps):

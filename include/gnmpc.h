@@ -388,6 +388,27 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* plan, int32_t n, const void* H, cons
                                 const void* lc, const void* uc, const gnmpc_admm_settings* settings,
                                 void* u, gnmpc_qp_info* info, void* stream);
 
+/* The same QP (box bounds, rows lc <= Ct u <= uc) by an interior-point method, as
+ * the paper solves its condensed QP (HPIPM): Mehrotra's predictor-corrector
+ * primal-dual method on the inequalities given by every finite bound, FP64 in
+ * one workgroup; each iteration forms H + G' diag(lambda / s) G, factors it and
+ * solves the reduced Newton system for the predictor and the centring
+ * corrector.  Arguments as gnmpc_solve_box_qp (plan dtype, device), with tol
+ * the stopping tolerance on the duality measure (the residuals are held to
+ * max(tol, 1e-9)), both relative to max(1, |g|_inf, |bounds|_inf), e.g. 1e-12,
+ * and max_iter.  Where constraints are nearly degenerate the iterate is
+ * O(sqrt(tol)) from the minimizer.  Near the solution the factorization is
+ * retried with a small diagonal regularization when it loses definiteness.
+ * info (device, may be NULL): status SOLVED / MAXITER / NOT_PD / NONFINITE,
+ * iterations, residuals, objective, and the last duality measure in the
+ * kappa_est field (used_fp64 = 1).  Uses the plan's QP workspace.  Errors as
+ * gnmpc_solve_box_qp, plus GNMPC_INVALID_ARG for tol <= 0 or max_iter < 1, and
+ * GNMPC_UNSUPPORTED when the slot arrays exceed one workgroup's LDS (n = 240
+ * with 200 rows fits). */
+gnmpc_status gnmpc_solve_qp_ipm(gnmpc_plan* plan, int32_t n, const void* H, const void* g, const void* lb,
+                                const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc, double tol,
+                                int32_t max_iter, void* u, gnmpc_qp_info* info, void* stream);
+
 /* Allocation-free variant of gnmpc_solve_box_qp, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  It takes no plan: dtype is GNMPC_F32 or

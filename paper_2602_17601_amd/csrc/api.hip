@@ -611,6 +611,20 @@ gnmpc_status gnmpc_solve_box_qp(gnmpc_plan* p, int32_t n, const void* H, const v
   return launch_qp(p, n, H, g, lb, ub, n_c, Ct, lc, uc, st, u, info, (hipStream_t)stream);
 }
 
+gnmpc_status gnmpc_solve_qp_ipm(gnmpc_plan* p, int32_t n, const void* H, const void* g, const void* lb,
+                                const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc, double tol,
+                                int32_t max_iter, void* u, gnmpc_qp_info* info, void* stream) {
+  if (!p) return GNMPC_INVALID_ARG;
+  if (!H || !g || !lb || !ub || !u) return fail(p, GNMPC_INVALID_ARG, "solve_qp_ipm: null array");
+  if (n <= 0 || n > p->dims.N * p->dims.nu) return fail(p, GNMPC_SHAPE, "solve_qp_ipm: n outside 1..N*nu");
+  if (n_c < 0 || n_c > p->dims.n_c_max) return fail(p, GNMPC_SHAPE, "solve_qp_ipm: n_c outside 0..n_c_max");
+  if (n_c > 0 && !Ct) return fail(p, GNMPC_INVALID_ARG, "solve_qp_ipm: Ct is null");
+  if (!(tol > 0) || max_iter < 1) return fail(p, GNMPC_INVALID_ARG, "solve_qp_ipm: tol > 0 and max_iter >= 1");
+  if (qp_ipm_check(n, n_c) != GNMPC_OK) return fail(p, GNMPC_UNSUPPORTED, "solve_qp_ipm: too large for one workgroup");
+  GNMPC_HIP_TRY(p, hipSetDevice(p->device));
+  return launch_qp_ipm(p, n, H, g, lb, ub, n_c, Ct, lc, uc, tol, max_iter, u, info, (hipStream_t)stream);
+}
+
 gnmpc_status gnmpc_solve_box_qp_noalloc(int32_t dtype, int32_t n, const void* H, const void* g, const void* lb,
                                         const void* ub, int32_t n_c, const void* Ct, const void* lc, const void* uc,
                                         const gnmpc_admm_settings* st, void* u, gnmpc_qp_info* info, void* stream) {

@@ -144,6 +144,11 @@ gnmpc_status launch_qp_prep(gnmpc_plan* p, int n, const void* H, const void* g, 
                             int n_c, const void* Ct, const void* lc, const void* uc, const gnmpc_admm_settings* st,
                             void* u, gnmpc_qp_info* info, hipStream_t s, QpPrepared* out);
 gnmpc_status launch_qp_batched(const QpPrepared* q, int count, hipStream_t s);
+// Interior-point solve of the same QP (one workgroup, FP64).
+gnmpc_status qp_ipm_check(int n, int n_c);
+gnmpc_status launch_qp_ipm(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
+                           int n_c, const void* Ct, const void* lc, const void* uc, double tol, int max_iter, void* u,
+                           gnmpc_qp_info* info, hipStream_t s);
 // Allocation-free QP (workspace in a static device array; see qp_admm.hip).
 constexpr int kQpNoallocMaxN = 464;
 gnmpc_status qp_noalloc_check(int dtype, int n, int n_c);

@@ -1394,6 +1394,288 @@ gnmpc_status batched_pass(const std::vector<const QpPrepared*>& all, int mode, h
   return GNMPC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Interior-point solver of the same QP (the paper solves its condensed QP with an
+// interior-point method, HPIPM): Mehrotra's predictor-corrector primal-dual
+// method (Mehrotra 1992; Nocedal and Wright, Numerical Optimization, Alg. 16.4) on
+//   min 1/2 u'Hu + g'u  s.t.  G u + s = h, s >= 0,
+// G's rows being the finite sides of lb <= u <= ub and lc <= Ct u <= uc.  Each
+// iteration forms K = H + G' diag(lambda / s) G = H + diag(d_box) + Ct' diag(d_c) Ct
+// in the block storage, factors and inverts it (the ADMM's blocked Cholesky),
+// and solves the reduced Newton system twice (predictor, then centring
+// corrector) with W' W.  FP64, one workgroup.  Inequality slots are fixed:
+// 2 i / 2 i + 1 the upper / lower side of u_i, 2 n + 2 r / + 1 those of row r;
+// an infinite side is an inactive slot (s = 1, lambda = 0, masked out).
+struct IpmArgs {
+  int n, n_c, max_iter, f64_in;  // f64_in: the arrays are double (else float)
+  double tol;
+  const void *H, *g, *lb, *ub, *Ct, *lc, *uc;
+  void* u;
+  gnmpc_qp_info* info;
+  double* gmat;  // block storage of K / L / W (global)
+};
+
+__host__ __device__ inline size_t ipm_lds_doubles(int n, int n_c) {
+  const size_t npad = (size_t)kBS * nblocks(n), m = 2 * (size_t)n + 2 * (size_t)n_c;
+  return 8 * npad + 8 * m + 4 * (size_t)n_c + part_elems(n) + 64 + 8;
+}
+
+__device__ inline double ipm_ld(const void* p, int f64, size_t i) {
+  return f64 ? static_cast<const double*>(p)[i] : (double)static_cast<const float*>(p)[i];
+}
+
+__global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
+  extern __shared__ unsigned char ipm_smem[];
+  const int n = a.n, nc = a.n_c, f64 = a.f64_in;
+  const int nb = nblocks(n), npad = kBS * nb, m = 2 * n + 2 * nc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_index();
+  double* sp = reinterpret_cast<double*>(ipm_smem);
+  size_t off = 0;
+  auto take = [&](size_t c) {
+    double* p = sp + off;
+    off += c;
+    return p;
+  };
+  double *u = take(npad), *rd = take(npad), *rhs = take(npad), *du = take(npad), *tv = take(npad);
+  double *dbox = take(npad), *gv = take(npad), *tmp = take(npad);
+  double *sv = take(m), *lam = take(m), *ds = take(m), *dl = take(m), *rp = take(m), *rc = take(m), *hv = take(m);
+  double* act = take(m);
+  double *ctu = take(nc), *dctu = take(nc), *dc = take(nc), *wv = take(nc);
+  Work<double> w;
+  w.mat = a.gmat;
+  w.tv = tv;
+  w.part = take(part_elems(n));
+  w.red = take(64);
+  w.scal = take(8);
+  // ---- slots, starting point u = 0, s = max(h, 1), lambda = 1 (inactive: s = 1, lambda = 0)
+  double hmax = 0.0, gmax = 0.0;
+  for (int q = tid; q < m; q += kQpThreads) {
+    double bound;
+    bool up = (q & 1) == 0;
+    if (q < 2 * n) bound = up ? ipm_ld(a.ub, f64, q >> 1) : ipm_ld(a.lb, f64, q >> 1);
+    else {
+      const int r = (q - 2 * n) >> 1;
+      bound = up ? (a.uc ? ipm_ld(a.uc, f64, r) : INFINITY) : (a.lc ? ipm_ld(a.lc, f64, r) : -INFINITY);
+    }
+    const bool on = isfinite(bound);
+    act[q] = on ? 1.0 : 0.0;
+    hv[q] = on ? (up ? bound : -bound) : 0.0;
+    sv[q] = on ? max(hv[q], 1.0) : 1.0;
+    lam[q] = on ? 1.0 : 0.0;
+    if (on) hmax = max(hmax, fabs(hv[q]));
+  }
+  for (int i = tid; i < npad; i += kQpThreads) {
+    u[i] = 0.0;
+    gv[i] = i < n ? ipm_ld(a.g, f64, i) : 0.0;
+    if (i < n) gmax = max(gmax, fabs(gv[i]));
+  }
+  double nact = 0.0;
+  for (int q = tid; q < m; q += kQpThreads) nact += act[q];
+  nact = block_sum(nact, w.red);
+  const double scale = max(1.0, max(block_max(hmax, w.red), block_max(gmax, w.red)));
+  __syncthreads();
+  // Ct v for the n_c rows into out (one wave per row)
+  auto ct_times = [&](const double* v, double* out) {
+    for (int r = wave; r < nc; r += kWaves) {
+      double t = 0.0;
+      for (int c = lane; c < n; c += 64) t += ipm_ld(a.Ct, f64, (size_t)r * n + c) * v[c];
+      t = wave_sum(t);
+      if (lane == 0) out[r] = t;
+    }
+    __syncthreads();
+  };
+  // G' v over the slots: (v_up - v_lo) of u_i plus Ct' (v_up - v_lo) of the rows; into out
+  auto gt_times = [&](const double* v, double* out) {
+    for (int r = tid; r < nc; r += kQpThreads) wv[r] = v[2 * n + 2 * r] - v[2 * n + 2 * r + 1];
+    __syncthreads();
+    for (int c = tid; c < npad; c += kQpThreads) {
+      double t = 0.0;
+      if (c < n) {
+        t = v[2 * c] - v[2 * c + 1];
+        for (int r = 0; r < nc; ++r) t += ipm_ld(a.Ct, f64, (size_t)r * n + c) * wv[r];
+      }
+      out[c] = t;
+    }
+    __syncthreads();
+  };
+  // G x per slot from x (box) and Ct x (rows)
+  auto g_slot = [&](int q, const double* x, const double* ctx) {
+    const double sg = (q & 1) ? -1.0 : 1.0;
+    return sg * (q < 2 * n ? x[q >> 1] : ctx[(q - 2 * n) >> 1]);
+  };
+  int status = GNMPC_QP_MAXITER, iter = 0;
+  double prim = 0.0, dual = 0.0, mu_last = 0.0;
+  for (iter = 0; iter < a.max_iter; ++iter) {
+    // ---- residuals rd = H u + g + G' lambda, rp = G u + s - h, mu
+    ct_times(u, ctu);
+    gt_times(lam, tmp);
+    for (int i = wave; i < n; i += kWaves) {
+      double t = 0.0;
+      for (int c = lane; c < n; c += 64) t += ipm_ld(a.H, f64, (size_t)i * n + c) * u[c];
+      t = wave_sum(t);
+      if (lane == 0) rd[i] = t + gv[i] + tmp[i];
+    }
+    double pm = 0.0, smu = 0.0;
+    for (int q = tid; q < m; q += kQpThreads) {
+      rp[q] = act[q] * (g_slot(q, u, ctu) + sv[q] - hv[q]);
+      pm = max(pm, fabs(rp[q]));
+      smu += sv[q] * lam[q];
+    }
+    __syncthreads();
+    double dm = 0.0;
+    for (int i = tid; i < n; i += kQpThreads) dm = max(dm, fabs(rd[i]));
+    prim = block_max(pm, w.red);
+    dual = block_max(dm, w.red);
+    const double mu = nact > 0 ? block_sum(smu, w.red) / nact : 0.0;
+    mu_last = mu;
+    if (!isfinite(prim) || !isfinite(dual) || !isfinite(mu)) {
+      status = GNMPC_QP_NONFINITE;
+      break;
+    }
+    // residuals to max(tol, 1e-9) (below that FP64 rounding of H u + g + G' lambda
+    // decides), the duality measure, which sets the distance to the minimizer, to tol
+    const double rtol = max(a.tol, 1e-9) * scale;
+    if (prim <= rtol && dual <= rtol && mu <= a.tol * scale) {
+      status = GNMPC_QP_SOLVED;
+      break;
+    }
+    // ---- K = H + diag(d_box) + Ct' diag(d_c) Ct (+ reg I), then L and W = L^{-1}.
+    // Near the solution lambda / s spans many orders of magnitude and K can lose
+    // definiteness in FP64; the factorization is then retried with a diagonal
+    // regularization reg = 1e-13 (1 + max lambda / s), times 100 per attempt.
+    double wmax = 0.0;
+    for (int i = tid; i < npad; i += kQpThreads) {
+      dbox[i] = i < n ? lam[2 * i] / sv[2 * i] + lam[2 * i + 1] / sv[2 * i + 1] : 0.0;
+      wmax = max(wmax, dbox[i]);
+    }
+    for (int r = tid; r < nc; r += kQpThreads) {
+      dc[r] = lam[2 * n + 2 * r] / sv[2 * n + 2 * r] + lam[2 * n + 2 * r + 1] / sv[2 * n + 2 * r + 1];
+      wmax = max(wmax, dc[r]);
+    }
+    wmax = block_max(wmax, w.red);
+    bool factored = false;
+    for (int attempt = 0; attempt < 4 && !factored; ++attempt) {
+    const double reg = attempt == 0 ? 0.0 : 1e-13 * (1.0 + wmax) * pow(100.0, (double)(attempt - 1));
+    {
+      const int r16 = lane >> 2, c4 = (lane & 3) * 4;
+      const int nblk = nb * (nb + 1) / 2;
+      for (int b = wave; b < nblk; b += kWaves) {
+        int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) / 2 <= b) ++I;
+        while (I * (I + 1) / 2 > b) --I;
+        const int J = b - I * (I + 1) / 2;
+        const int i = kBS * I + r16;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < n) {
+          for (int r = 0; r < nc; ++r) {
+            const double ci = dc[r] * ipm_ld(a.Ct, f64, (size_t)r * n + i);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int j = kBS * J + c4 + k;
+              if (j < n) acc[k] += ci * ipm_ld(a.Ct, f64, (size_t)r * n + j);
+            }
+          }
+        }
+        double* blk = w.mat + bo(I, J) + r16 * kBS + c4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int j = kBS * J + c4 + k;
+          double v;
+          if (i < n && j < n) v = ipm_ld(a.H, f64, (size_t)i * n + j) + (i == j ? dbox[i] + reg : 0.0) + acc[k];
+          else v = i == j ? 1.0 : 0.0;
+          blk[k] = v;
+        }
+      }
+    }
+    __syncthreads();
+    factored = factor_invert(w, nb);
+    __syncthreads();
+    }
+    if (!factored) {
+      status = GNMPC_QP_NOT_PD;
+      break;
+    }
+    // ---- reduced Newton system: K du = -rd - G'(W rp - rc / s); then dlambda, ds
+    auto solve = [&]() {
+      // ds holds v = W rp - rc / s until the step is formed
+      for (int q = tid; q < m; q += kQpThreads) ds[q] = act[q] * (lam[q] / sv[q] * rp[q] - rc[q] / sv[q]);
+      __syncthreads();
+      gt_times(ds, tmp);
+      for (int i = tid; i < npad; i += kQpThreads) rhs[i] = i < n ? -rd[i] - tmp[i] : 0.0;
+      __syncthreads();
+      kinv_apply(w, n, rhs, du);
+      for (int i = n + tid; i < npad; i += kQpThreads) du[i] = 0.0;
+      __syncthreads();
+      ct_times(du, dctu);
+      for (int q = tid; q < m; q += kQpThreads) {
+        const double dlq = act[q] * (lam[q] / sv[q] * (g_slot(q, du, dctu) + rp[q]) - rc[q] / sv[q]);
+        dl[q] = dlq;
+        ds[q] = act[q] ? -(rc[q] + sv[q] * dlq) / lam[q] : 0.0;
+      }
+      __syncthreads();
+    };
+    auto max_step = [&]() {
+      double amin = 1.0;
+      for (int q = tid; q < m; q += kQpThreads) {
+        if (!act[q]) continue;
+        if (ds[q] < 0.0) amin = min(amin, -sv[q] / ds[q]);
+        if (dl[q] < 0.0) amin = min(amin, -lam[q] / dl[q]);
+      }
+      return -block_max(-amin, w.red);
+    };
+    // predictor: rc = s lambda
+    for (int q = tid; q < m; q += kQpThreads) rc[q] = act[q] * sv[q] * lam[q];
+    __syncthreads();
+    solve();
+    double al = max_step();
+    double smu_aff = 0.0;
+    for (int q = tid; q < m; q += kQpThreads) smu_aff += act[q] * (sv[q] + al * ds[q]) * (lam[q] + al * dl[q]);
+    const double mu_aff = nact > 0 ? block_sum(smu_aff, w.red) / nact : 0.0;
+    const double sig = mu > 0.0 ? (mu_aff / mu) * (mu_aff / mu) * (mu_aff / mu) : 0.0;
+    // centring corrector: rc = s lambda + ds_aff dlambda_aff - sigma mu
+    for (int q = tid; q < m; q += kQpThreads) rc[q] = act[q] * (sv[q] * lam[q] + ds[q] * dl[q] - sig * mu);
+    __syncthreads();
+    solve();
+    al = min(1.0, 0.995 * max_step());
+    if (!(al > 1e-14)) break;
+    for (int i = tid; i < n; i += kQpThreads) u[i] += al * du[i];
+    for (int q = tid; q < m; q += kQpThreads) {
+      if (!act[q]) continue;
+      sv[q] += al * ds[q];
+      lam[q] += al * dl[q];
+    }
+    __syncthreads();
+  }
+  // ---- outputs
+  for (int i = tid; i < n; i += kQpThreads) {
+    const double v = status == GNMPC_QP_NOT_PD || status == GNMPC_QP_NONFINITE ? NAN : u[i];
+    if (f64) static_cast<double*>(a.u)[i] = v;
+    else static_cast<float*>(a.u)[i] = (float)v;
+  }
+  double obj = 0.0;
+  if (a.info) {  // the objective 1/2 u'Hu + g'u, rows of H per wave
+    for (int i = wave; i < n; i += kWaves) {
+      double t = 0.0;
+      for (int c = lane; c < n; c += 64) t += ipm_ld(a.H, f64, (size_t)i * n + c) * u[c];
+      t = wave_sum(t);
+      if (lane == 0) tmp[i] = u[i] * (0.5 * t + gv[i]);
+    }
+    __syncthreads();
+    double o = 0.0;
+    for (int i = tid; i < n; i += kQpThreads) o += tmp[i];
+    obj = block_sum(o, w.red);
+  }
+  if (tid == 0 && a.info) {
+    a.info->status = status;
+    a.info->iters = iter;
+    a.info->used_fp64 = 1;
+    a.info->prim_res = prim;
+    a.info->dual_res = dual;
+    a.info->kappa_est = mu_last;  // the interior-point solver reports its duality measure here
+    a.info->obj = obj;
+  }
+}
+
 // Workspace of the allocation-free entry: a file-scope device array (one copy
 // per GPU, held until the process ends).  Host code never passes the array's
 // name to a kernel: it takes the array's device address on each GPU once, by
@@ -1444,6 +1726,40 @@ gnmpc_status launch_qp_batched(const QpPrepared* q, int count, hipStream_t s) {
   if (rc == GNMPC_OK && !f.empty()) rc = batched_pass<double, float>(f, 1, s);
   if (rc == GNMPC_OK && !d.empty()) rc = batched_pass<double, double>(d, 2, s);
   return rc;
+}
+
+gnmpc_status qp_ipm_check(int n, int n_c) {
+  return ipm_lds_doubles(n, n_c) * sizeof(double) <= kLdsCap ? GNMPC_OK : GNMPC_UNSUPPORTED;
+}
+
+gnmpc_status launch_qp_ipm(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub,
+                           int n_c, const void* Ct, const void* lc, const void* uc, double tol, int max_iter, void* u,
+                           gnmpc_qp_info* info, hipStream_t s) {
+  IpmArgs a;
+  a.n = n;
+  a.n_c = n_c;
+  a.max_iter = max_iter;
+  a.f64_in = p->dims.dtype == GNMPC_F64;
+  a.tol = tol;
+  a.H = H;
+  a.g = g;
+  a.lb = lb;
+  a.ub = ub;
+  a.Ct = n_c > 0 ? Ct : nullptr;
+  a.lc = lc;
+  a.uc = uc;
+  a.u = u;
+  a.info = info;
+  unsigned char* ws = (unsigned char*)p->d_qp;
+  a.gmat = (double*)(ws + (sizeof(double) * (size_t)n * n + 255) / 256 * 256);  // the ADMM's factor storage
+  const size_t lds = ipm_lds_doubles(n, n_c) * sizeof(double);
+  if (lds > kLdsCap) return GNMPC_UNSUPPORTED;
+  GNMPC_HIP_TRY(p, set_max_lds((const void*)qp_ipm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (p) phase_begin(p, GNMPC_PH_QP, s);
+  qp_ipm_kernel<<<1, kQpThreads, lds, s>>>(a);
+  if (p) phase_end(p, GNMPC_PH_QP, s);
+  GNMPC_HIP_TRY(p, hipGetLastError());
+  return GNMPC_OK;
 }
 
 gnmpc_status launch_qp(gnmpc_plan* p, int n, const void* H, const void* g, const void* lb, const void* ub, int n_c,

@@ -128,6 +128,7 @@ def lib():
             "gnmpc_gnn_train_sizes": ([vp, P(i64), P(i64)], i32),
             "gnmpc_gnn_loss_grad": ([vp, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp], i32),
             "gnmpc_adam_step": ([i64, vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp], i32),
+            "gnmpc_solve_qp_ipm": ([vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, C.c_double, i32, vp, vp, vp], i32),
             "gnmpc_solve_box_qp_noalloc": ([i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, P(AdmmSettings), vp, vp, vp],
                                            i32),
             "gnmpc_admm_default_settings": ([P(AdmmSettings)], None),
@@ -401,6 +402,17 @@ class Plan:
         v, nb = C.c_int32(), C.c_int32()
         self._check(lib().gnmpc_condense_variant_get(self._h, C.byref(v), C.byref(nb)), "condense_variant")
         return v.value, nb.value
+
+    def solve_qp_ipm(self, H, g, lb, ub, Ct, lc, uc, u, info=None, tol=1e-9, max_iter=100, stream=None):
+        """gnmpc_solve_qp_ipm: the same QP by the interior-point method."""
+        n = g.shape[0]
+        nc = 0 if Ct is None else Ct.shape[0]
+        args = [self._dev(H, (n, n), "H"), self._dev(g, (n,), "g"), self._dev(lb, (n,), "lb"),
+                self._dev(ub, (n,), "ub"), nc, self._dev(Ct, (nc, n), "Ct", allow_none=nc == 0),
+                self._dev(lc, (nc,), "lc", allow_none=True), self._dev(uc, (nc,), "uc", allow_none=True),
+                float(tol), int(max_iter), self._dev(u, (n,), "u"),
+                self._dev(info, (QP_INFO_BYTES,), "info", dtype=torch.uint8, allow_none=True)]
+        self._check(lib().gnmpc_solve_qp_ipm(self._h, n, *args, _stream(stream)), "solve_qp_ipm")
 
     def solve_box_qp(self, H, g, lb, ub, Ct, lc, uc, u, info=None, settings=None, stream=None):
         n = g.shape[0]
