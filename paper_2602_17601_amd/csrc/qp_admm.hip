@@ -170,10 +170,15 @@ struct Work {
 typedef float qfloatx4 __attribute__((ext_vector_type(4)));
 
 // 16x16 block products, row layout: lane l holds acc[t] = (A op(B))[l & 15][4 (l >> 4) + t],
-// op(B) = B' if TRANS else B; blocks are row-major.  FP32 runs the transposed
-// product on v_mfma_f32_16x16x4f32 with the k index permuted (step s takes
-// k = 4 (l >> 4) + s), so A rows, B' rows and the result are read and written
-// as 16-byte runs without LDS bank conflicts.  FP64 uses the VALU.
+// op(B) = B' if TRANS else B; blocks are row-major.  Both types run the transposed
+// product on the matrix cores (v_mfma_f32_16x16x4f32, v_mfma_f64_16x16x4f64) with
+// the k index permuted (step s takes k = 4 (l >> 4) + s), so A rows, B' rows and
+// the result are read and written as 16-byte runs: a lane reads 4 + 4 elements
+// per product, which matters where the blocks sit in global memory (the FP64
+// factor of a large K).  The FP64 instruction leaves row g + 4 t of its result
+// where the FP32 one leaves row 4 g + t (g = l >> 4), so the FP64 product takes
+// op(B)'s columns in the order pi(r) = 4 (r & 3) + (r >> 2), which puts the result
+// in the same row layout.
 template <bool TRANS>
 __device__ inline void bmma(float acc[4], const float* A, const float* B) {
   const int l = threadIdx.x & 63, r = l & 15, kq = l >> 4;
@@ -193,15 +198,28 @@ __device__ inline void bmma(float acc[4], const float* A, const float* B) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = c[i];
 }
+typedef double qdoublex4 __attribute__((ext_vector_type(4)));
 template <bool TRANS>
 __device__ inline void bmma(double acc[4], const double* A, const double* B) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-#pragma unroll 4
-  for (int k = 0; k < 16; ++k) {
-    const double av = A[r * 16 + k];
+  const int l = threadIdx.x & 63, r = l & 15, kq = l >> 4;
+  const double2 a01 = *reinterpret_cast<const double2*>(A + r * 16 + 4 * kq);
+  const double2 a23 = *reinterpret_cast<const double2*>(A + r * 16 + 4 * kq + 2);
+  const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+  const int pr = 4 * (r & 3) + (r >> 2);
+  double b[4];
+  if (TRANS) {
+    const double2 b01 = *reinterpret_cast<const double2*>(B + pr * 16 + 4 * kq);
+    const double2 b23 = *reinterpret_cast<const double2*>(B + pr * 16 + 4 * kq + 2);
+    b[0] = b01.x; b[1] = b01.y; b[2] = b23.x; b[3] = b23.y;
+  } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] += av * (TRANS ? B[(4 * g + t) * 16 + k] : B[k * 16 + 4 * g + t]);
+    for (int st = 0; st < 4; ++st) b[st] = B[(4 * kq + st) * 16 + pr];
   }
+  qdoublex4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) c = __builtin_amdgcn_mfma_f64_16x16x4f64(b[st], av[st], c, 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = c[i];
 }
 
 // Set-up over many workgroups, one workgroup per 16x16 block (I, J <= I) of
@@ -1415,9 +1433,14 @@ struct IpmArgs {
   double* gmat;  // block storage of K / L / W (global)
 };
 
+// K's row term is formed from kIpmRows rows of Ct at a time, staged in LDS and
+// scaled by sqrt(lambda / s) (K_c = W'W); a wave keeps the sums of up to
+// kIpmBlk 16x16 blocks in registers per pass over Ct.
+constexpr int kIpmRows = 16;
+constexpr int kIpmBlk = 4;
 __host__ __device__ inline size_t ipm_lds_doubles(int n, int n_c) {
   const size_t npad = (size_t)kBS * nblocks(n), m = 2 * (size_t)n + 2 * (size_t)n_c;
-  return 8 * npad + 8 * m + 4 * (size_t)n_c + part_elems(n) + 64 + 8;
+  return 8 * npad + 8 * m + 4 * (size_t)n_c + part_elems(n) + 64 + 8 + (size_t)kIpmRows * npad;
 }
 
 __device__ inline double ipm_ld(const void* p, int f64, size_t i) {
@@ -1447,6 +1470,7 @@ __global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
   w.part = take(part_elems(n));
   w.red = take(64);
   w.scal = take(8);
+  double* cs = take((size_t)kIpmRows * npad);  // staged rows of W = diag(sqrt(d_c)) Ct
   // ---- slots, starting point u = 0, s = max(h, 1), lambda = 1 (inactive: s = 1, lambda = 0)
   double hmax = 0.0, gmax = 0.0;
   for (int q = tid; q < m; q += kQpThreads) {
@@ -1474,25 +1498,59 @@ __global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
   nact = block_sum(nact, w.red);
   const double scale = max(1.0, max(block_max(hmax, w.red), block_max(gmax, w.red)));
   __syncthreads();
-  // Ct v for the n_c rows into out (one wave per row)
-  auto ct_times = [&](const double* v, double* out) {
-    for (int r = wave; r < nc; r += kWaves) {
-      double t = 0.0;
-      for (int c = lane; c < n; c += 64) t += ipm_ld(a.Ct, f64, (size_t)r * n + c) * v[c];
-      t = wave_sum(t);
-      if (lane == 0) out[r] = t;
+  // out[r] = (X v)[r] for the rows r < rows of X [rows][n] (Ct or H): a wave takes
+  // eight rows at a time, lanes over the columns, so its loads of the eight rows
+  // are in flight together; then one wave reduction per row.
+  auto rows_times = [&](const void* X, int rows, const double* v, double* out) {
+    for (int r0 = 4 * wave; r0 < rows; r0 += 4 * kWaves) {
+      double t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = 0.0;
+      for (int c = lane; c < n; c += 64) {
+        const double vc = v[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (r0 + q < rows) t[q] += ipm_ld(X, f64, (size_t)(r0 + q) * n + c) * vc;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double sq = wave_sum(t[q]);
+        if (lane == 0 && r0 + q < rows) out[r0 + q] = sq;
+      }
     }
     __syncthreads();
   };
-  // G' v over the slots: (v_up - v_lo) of u_i plus Ct' (v_up - v_lo) of the rows; into out
+  auto ct_times = [&](const double* v, double* out) { rows_times(a.Ct, nc, v, out); };
+  // G' v over the slots: (v_up - v_lo) of u_i plus Ct' (v_up - v_lo) of the rows; into
+  // out.  Wave w sums rows w, w + kWaves, ... of Ct scaled by their weights, lanes
+  // over the columns (coalesced row reads), into w.part[w][.]; the waves' partial
+  // sums are then added in wave order.
   auto gt_times = [&](const double* v, double* out) {
     for (int r = tid; r < nc; r += kQpThreads) wv[r] = v[2 * n + 2 * r] - v[2 * n + 2 * r + 1];
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += 256) {
+      double pc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int r = wave; r < nc; r += kWaves) {
+        const double wr = wv[r];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + lane + 64 * t;
+          if (c < n) pc[t] += ipm_ld(a.Ct, f64, (size_t)r * n + c) * wr;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + lane + 64 * t;
+        if (c < n) w.part[(size_t)wave * n + c] = pc[t];
+      }
+    }
     __syncthreads();
     for (int c = tid; c < npad; c += kQpThreads) {
       double t = 0.0;
       if (c < n) {
         t = v[2 * c] - v[2 * c + 1];
-        for (int r = 0; r < nc; ++r) t += ipm_ld(a.Ct, f64, (size_t)r * n + c) * wv[r];
+        for (int q = 0; q < kWaves; ++q) t += w.part[(size_t)q * n + c];
       }
       out[c] = t;
     }
@@ -1509,12 +1567,8 @@ __global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
     // ---- residuals rd = H u + g + G' lambda, rp = G u + s - h, mu
     ct_times(u, ctu);
     gt_times(lam, tmp);
-    for (int i = wave; i < n; i += kWaves) {
-      double t = 0.0;
-      for (int c = lane; c < n; c += 64) t += ipm_ld(a.H, f64, (size_t)i * n + c) * u[c];
-      t = wave_sum(t);
-      if (lane == 0) rd[i] = t + gv[i] + tmp[i];
-    }
+    rows_times(a.H, n, u, rd);
+    for (int i = tid; i < n; i += kQpThreads) rd[i] += gv[i] + tmp[i];
     double pm = 0.0, smu = 0.0;
     for (int q = tid; q < m; q += kQpThreads) {
       rp[q] = act[q] * (g_slot(q, u, ctu) + sv[q] - hv[q]);
@@ -1557,33 +1611,64 @@ __global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
     for (int attempt = 0; attempt < 4 && !factored; ++attempt) {
     const double reg = attempt == 0 ? 0.0 : 1e-13 * (1.0 + wmax) * pow(100.0, (double)(attempt - 1));
     {
+      // K_c = W'W, W = diag(sqrt(d_c)) Ct: passes over blocks (a wave's kIpmBlk blocks
+      // b = b0 + wave + kWaves q of the lower triangle), each streaming W through LDS
+      // kIpmRows rows at a time; lane (r16, c4) sums K_c[16 I + r16][16 J + c4 + 0..3]
       const int r16 = lane >> 2, c4 = (lane & 3) * 4;
       const int nblk = nb * (nb + 1) / 2;
-      for (int b = wave; b < nblk; b += kWaves) {
-        int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-        while ((I + 1) * (I + 2) / 2 <= b) ++I;
-        while (I * (I + 1) / 2 > b) --I;
-        const int J = b - I * (I + 1) / 2;
-        const int i = kBS * I + r16;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (i < n) {
-          for (int r = 0; r < nc; ++r) {
-            const double ci = dc[r] * ipm_ld(a.Ct, f64, (size_t)r * n + i);
+      for (int b0 = 0; b0 < nblk; b0 += kWaves * kIpmBlk) {
+        int bi[kIpmBlk], bj[kIpmBlk];
+        double acc[kIpmBlk][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int j = kBS * J + c4 + k;
-              if (j < n) acc[k] += ci * ipm_ld(a.Ct, f64, (size_t)r * n + j);
+        for (int q = 0; q < kIpmBlk; ++q) {
+          const int b = b0 + wave + kWaves * q;
+          int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+          while ((I + 1) * (I + 2) / 2 <= b) ++I;
+          while (I * (I + 1) / 2 > b) --I;
+          bi[q] = I;
+          bj[q] = b - I * (I + 1) / 2;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[q][k] = 0.0;
+        }
+        for (int r0 = 0; r0 < nc; r0 += kIpmRows) {
+          __syncthreads();  // every wave is done with the previous rows
+          for (int t = tid; t < kIpmRows * npad; t += kQpThreads) {
+            const int rr = t / npad, c = t - rr * npad, r = r0 + rr;
+            cs[t] = (r < nc && c < n) ? sqrt(dc[r]) * ipm_ld(a.Ct, f64, (size_t)r * n + c) : 0.0;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < kIpmBlk; ++q) {
+            if (b0 + wave + kWaves * q < nblk) {
+              const double* ci = cs + kBS * bi[q] + r16;
+              const double* cj = cs + kBS * bj[q] + c4;
+#pragma unroll 4
+              for (int rr = 0; rr < kIpmRows; ++rr) {
+                const double x = ci[rr * npad];
+                const double2 y01 = *reinterpret_cast<const double2*>(cj + rr * npad);
+                const double2 y23 = *reinterpret_cast<const double2*>(cj + rr * npad + 2);
+                acc[q][0] += x * y01.x;
+                acc[q][1] += x * y01.y;
+                acc[q][2] += x * y23.x;
+                acc[q][3] += x * y23.y;
+              }
             }
           }
         }
-        double* blk = w.mat + bo(I, J) + r16 * kBS + c4;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int j = kBS * J + c4 + k;
-          double v;
-          if (i < n && j < n) v = ipm_ld(a.H, f64, (size_t)i * n + j) + (i == j ? dbox[i] + reg : 0.0) + acc[k];
-          else v = i == j ? 1.0 : 0.0;
-          blk[k] = v;
+        for (int q = 0; q < kIpmBlk; ++q) {
+          if (b0 + wave + kWaves * q < nblk) {
+            const int i = kBS * bi[q] + r16;
+            double* blk = w.mat + bo(bi[q], bj[q]) + r16 * kBS + c4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int j = kBS * bj[q] + c4 + k;
+              double v;
+              if (i < n && j < n) v = ipm_ld(a.H, f64, (size_t)i * n + j) + (i == j ? dbox[i] + reg : 0.0) + acc[q][k];
+              else v = i == j ? 1.0 : 0.0;
+              blk[k] = v;
+            }
+          }
         }
       }
     }
@@ -1653,13 +1738,9 @@ __global__ void __launch_bounds__(kQpThreads) qp_ipm_kernel(IpmArgs a) {
     else static_cast<float*>(a.u)[i] = (float)v;
   }
   double obj = 0.0;
-  if (a.info) {  // the objective 1/2 u'Hu + g'u, rows of H per wave
-    for (int i = wave; i < n; i += kWaves) {
-      double t = 0.0;
-      for (int c = lane; c < n; c += 64) t += ipm_ld(a.H, f64, (size_t)i * n + c) * u[c];
-      t = wave_sum(t);
-      if (lane == 0) tmp[i] = u[i] * (0.5 * t + gv[i]);
-    }
+  if (a.info) {  // the objective 1/2 u'Hu + g'u
+    rows_times(a.H, n, u, tmp);
+    for (int i = tid; i < n; i += kQpThreads) tmp[i] = u[i] * (0.5 * tmp[i] + gv[i]);
     __syncthreads();
     double o = 0.0;
     for (int i = tid; i < n; i += kQpThreads) o += tmp[i];
