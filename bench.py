@@ -9,7 +9,7 @@ mass-spring-damper Jacobians on the same graph) is timed beside it.  The
 step is captured once as a HIP graph and replayed (``--eager`` times eager
 launches instead).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--eager]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--eager] [--only-step]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -244,6 +244,9 @@ def main():
                          "(M ~ U{50..1000}, N ~ U{10..30}) in one batched step; prints its own JSON line")
     ap.add_argument("--eager", action="store_true",
                     help="time eagerly launched steps instead of replays of the step captured as a HIP graph")
+    ap.add_argument("--only-step", action="store_true",
+                    help="time the step (GNN and plain forms) only, without the side measurements (tangent maps, "
+                         "simulator, closed loop, paper model, training, interior-point QP); for profiler runs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB 5 times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -418,15 +421,18 @@ def main():
         "roofline": roofline,
         "phase_roofline_gnn": phase_rooflines(P, int(plan_g.nnz), phase_avg(ph_g), flops),
         "cpu_baseline": cpu,
-        "tangent": tangent_rates(gn, plan_g, bg, args.steps),
-        "simulator": simulator_rate(torch, gn, wl),
-        "closed_loop": {"workload": "1000-node chain, N=20, 200 obstacle rows, spring-damper plant",
-                        "plain": closed_loop_rate(torch, gn, wl, "msd"),
-                        "gnn": closed_loop_rate(torch, gn, wl, "gnn")},
-        "paper_model": paper_model_rate(torch, gn, wl),
-        "ipm": ipm_rate(torch, gn, plan_g, bg, settings),
-        "training": training_rate(torch, gn, wl),
     }
+    if not args.only_step:
+        out.update({
+            "tangent": tangent_rates(gn, plan_g, bg, args.steps),
+            "simulator": simulator_rate(torch, gn, wl),
+            "closed_loop": {"workload": "1000-node chain, N=20, 200 obstacle rows, spring-damper plant",
+                            "plain": closed_loop_rate(torch, gn, wl, "msd"),
+                            "gnn": closed_loop_rate(torch, gn, wl, "gnn")},
+            "paper_model": paper_model_rate(torch, gn, wl),
+            "ipm": ipm_rate(torch, gn, plan_g, bg, settings),
+            "training": training_rate(torch, gn, wl),
+        })
     print(json.dumps(out), flush=True)
 
 
