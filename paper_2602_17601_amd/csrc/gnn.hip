@@ -1082,31 +1082,63 @@ struct FwdMfmaArgs {
 // kFwdCT MFMA column groups.
 constexpr int kFwdCT = 2;
 __host__ __device__ constexpr int fwd_groups(int Hd) { return Hd <= 128 ? kFwdCT : 1; }
-// Dynamic LDS of fwd_mfma_layer_kernel: three bf16 planes of the layer input and
-// of the aggregates, the FP32 W_b h of every column (16-byte chunks XOR-swizzled
-// by column, so the 16 columns of a wave read 16 distinct bank groups), the
+// Dynamic LDS of fwd_mfma_layer_kernel: three bf16 planes of the layer input, one
+// region that holds the FP32 W_b h of every column (16-byte chunks XOR-swizzled by
+// column, so the 16 columns of a wave read 16 distinct bank groups) until the edge
+// terms have read it and the three bf16 planes of the aggregates after that, the
 // staged mask groups, then the tile's lists (sender column of each edge; first
-// edge, edge count and node of each column).
+// edge, edge count and node of each column).  At Hd = 128 with 32-column tiles this
+// is about 52 KB, so three workgroups fit one CU's 160 KB.
 __host__ __device__ constexpr size_t fwd_planes_bytes(int Hd) { return (size_t)16 * fwd_groups(Hd) * Hd * 2; }
+// W_b h (FP32, until the edge terms have read it) and then the three aggregate planes
+// share one region
+__host__ __device__ constexpr size_t fwd_union_bytes(int Hd) {
+  return (size_t)16 * fwd_groups(Hd) * Hd * 4 > 3 * fwd_planes_bytes(Hd) ? (size_t)16 * fwd_groups(Hd) * Hd * 4
+                                                                          : 3 * fwd_planes_bytes(Hd);
+}
+// Staged mask groups: a lane's 4-bit groups of features 16 m + .. and 16 (m + 1) + ..
+// share one byte (Hd >= 128), so a staged row is Hd / 8 bytes (Hd / 4 for Hd = 64).
+__host__ __device__ constexpr int fwd_qrow_bytes(int Hd) { return Hd >= 128 ? Hd / 8 : Hd / 4; }
 __host__ __device__ constexpr size_t fwd_mask_bytes(int Hd, int fedge_cap) {
-  return ((size_t)(fedge_cap + 16 * fwd_groups(Hd)) * (Hd / 4) + 15) / 16 * 16;
+  return ((size_t)(fedge_cap + 16 * fwd_groups(Hd)) * fwd_qrow_bytes(Hd) + 15) / 16 * 16;
 }
 size_t fwd_lds_bytes(int Hd, int fedge_cap) {
   const int NC = 16 * fwd_groups(Hd);
-  return 6 * fwd_planes_bytes(Hd) + (size_t)NC * Hd * 4 + fwd_mask_bytes(Hd, fedge_cap) +
+  return 3 * fwd_planes_bytes(Hd) + fwd_union_bytes(Hd) + fwd_mask_bytes(Hd, fedge_cap) +
          (size_t)(fedge_cap + 3 * NC) * 4;
 }
+// byte and bit offset of 4-bit group g4 in a staged row
+__device__ inline int fwd_qbyte(int Hd, int g4) { return Hd >= 128 ? ((g4 >> 3) << 2) | (g4 & 3) : g4; }
+__device__ inline int fwd_qshift(int Hd, int g4) { return Hd >= 128 ? 4 * ((g4 >> 2) & 1) : 0; }
 
+// Stage this lane's 4-bit groups of one mask row: group m covers features f_lane + 16 m ..
+// + 3 (f_lane = the lane's first feature); for Hd >= 128 groups m and m + 1 share a byte.
+template <int Hd, int MT>
+__device__ inline void fwd_stage_groups(unsigned char* row, const uint32_t (&nibs)[MT], int f_lane) {
+  if constexpr (Hd >= 128) {
+#pragma unroll
+    for (int m = 0; m < MT; m += 2)
+      row[fwd_qbyte(Hd, (f_lane + 16 * m) / 4)] = (unsigned char)(nibs[m] | (nibs[m + 1] << 4));
+  } else {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) row[fwd_qbyte(Hd, (f_lane + 16 * m) / 4)] = (unsigned char)nibs[m];
+  }
+}
+
+// At most 168 registers per lane (three waves per SIMD), which with the LDS above
+// lets three workgroups share a CU: the 720 workgroups of a 1000-node, 20-stage
+// layer then run in one round instead of two.
 template <int MT>
-__global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
   constexpr int Hd = MT * 64, KB = Hd / 32, RW = Hd / 4, CB = Hd * 2, HW = Hd / 32, NQ = Hd / 4;
   constexpr int CT = fwd_groups(Hd), NC = 16 * CT;
   constexpr int PL = NC * CB;  // bytes of one bf16 plane
   extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+  constexpr int QB = fwd_qrow_bytes(Hd);
   unsigned char* Hs = fsm;                                 // [3][NC][CB] layer input: hi, mid, lo
-  unsigned char* Ag = Hs + 3 * PL;                         // [3][NC][CB] aggregates: hi, mid, lo
-  float* Ybs = reinterpret_cast<float*>(Ag + 3 * PL);      // [NC][Hd] W_b h per column
-  unsigned char* qmask = reinterpret_cast<unsigned char*>(Ybs + NC * Hd);  // [edges + NC][NQ] 4-bit groups
+  float* Ybs = reinterpret_cast<float*>(Hs + 3 * PL);      // [NC][Hd] W_b h per column, until the edge terms
+  unsigned char* Ag = Hs + 3 * PL;                         // [3][NC][CB] aggregates: hi, mid, lo (after them)
+  unsigned char* qmask = Hs + 3 * PL + fwd_union_bytes(Hd);  // [edges + NC][QB] 4-bit groups
   int32_t* esrc = reinterpret_cast<int32_t*>(qmask + fwd_mask_bytes(Hd, a.fedge_cap));  // [edges]
   int32_t* epre = esrc + a.fedge_cap;                                                 // [NC]
   int32_t* ecnt = epre + NC;                                                          // [NC]
@@ -1219,13 +1251,15 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
     }
   }
   __syncthreads();
-  // ---- edge terms of the target columns: agg = sum_j relu(P_i - Yb_j)
+  // ---- edge terms of the target columns: agg = sum_j relu(P_i - Yb_j); the sums stay in
+  // registers until every wave has read W_b h, whose region the aggregate planes take
+  float aggv[CT][MT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = 16 * ct + col;
     const int e0 = epre[c];
     const int ne = ecnt[c];
-    float agg[MT][4];
+    float (&agg)[MT][4] = aggv[ct];
     uint32_t ncnt[MT];  // 4 byte counters: in-edges whose ReLU is on, per feature
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -1235,6 +1269,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
     }
     for (int t = 0; t < ne; ++t) {
       const int sc = esrc[e0 + t];
+      uint32_t nibs[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int f0 = wave * RW + 16 * m + 4 * grp;
@@ -1248,8 +1283,9 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
           nib |= (on ? 1u : 0u) << i;
           ncnt[m] += (on ? 1u : 0u) << (8 * i);
         }
-        qmask[(size_t)(e0 + t) * NQ + f0 / 4] = (unsigned char)nib;
+        nibs[m] = nib;
       }
+      fwd_stage_groups<Hd, MT>(qmask + (size_t)(e0 + t) * QB, nibs, wave * RW + 4 * grp);
     }
     if (c < nt) {
       const int node = cnode[c];
@@ -1259,12 +1295,17 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
         *reinterpret_cast<uint32_t*>(a.cnt + ((size_t)k * a.M + node) * Hd + f0) = ncnt[m];
       }
     }
+  }
+  __syncthreads();  // W_b h is dead
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = 16 * ct + col;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int f0 = wave * RW + 16 * m + 4 * grp;
       uint32_t h0, h1, h2, g0, g1, g2;
-      split3_bf16x2(agg[m][0], agg[m][1], h0, h1, h2);
-      split3_bf16x2(agg[m][2], agg[m][3], g0, g1, g2);
+      split3_bf16x2(aggv[ct][m][0], aggv[ct][m][1], h0, h1, h2);
+      split3_bf16x2(aggv[ct][m][2], aggv[ct][m][3], g0, g1, g2);
       const int off = c * CB + swz(2 * f0, c);
       *reinterpret_cast<uint2*>(Ag + off) = make_uint2(h0, g0);
       *reinterpret_cast<uint2*>(Ag + PL + off) = make_uint2(h1, g1);
@@ -1310,6 +1351,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
       const int c = 16 * ct + col;
       if (c < nt) {
         const int node = cnode[c];
+        uint32_t nibs[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           const int f0 = wave * RW + 16 * m + 4 * grp;
@@ -1323,8 +1365,9 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
             nib |= (on ? 1u : 0u) << i;
           }
           *reinterpret_cast<float4*>(a.hout + ((size_t)k * a.M + node) * Hd + f0) = make_float4(hv[0], hv[1], hv[2], hv[3]);
-          qmask[(size_t)(a.fedge_cap + c) * NQ + f0 / 4] = (unsigned char)nib;
+          nibs[m] = nib;
         }
+        fwd_stage_groups<Hd, MT>(qmask + (size_t)(a.fedge_cap + c) * QB, nibs, wave * RW + 4 * grp);
       }
     }
   }
@@ -1335,7 +1378,10 @@ __global__ void __launch_bounds__(256) fwd_mfma_layer_kernel(FwdMfmaArgs a) {
     const int srow = r < ec ? r : a.fedge_cap + (r - ec);
     uint32_t word = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) word |= (uint32_t)(qmask[(size_t)srow * NQ + wd * 8 + q] & 0xF) << (4 * q);
+    for (int q = 0; q < 8; ++q) {
+      const int g4 = wd * 8 + q;
+      word |= ((uint32_t)(qmask[(size_t)srow * QB + fwd_qbyte(Hd, g4)] >> fwd_qshift(Hd, g4)) & 0xFu) << (4 * q);
+    }
     if (r < ec) a.mask_edge[((size_t)k * a.E + a.feid[eb + r]) * HW + wd] = word;
     else a.mask_node[((size_t)k * a.M + cnode[r - ec]) * HW + wd] = word;
   }
