@@ -138,6 +138,10 @@ typedef struct {
   int32_t iters;
   int32_t used_fp64; /* 1 if the condition estimate exceeded kappa_fp64          */
   int32_t reserved;
+  /* kappa_est: the ADMM's estimate of the 1-norm condition number of K, either the
+   * upper bound ||K||_1 ||W||_1 ||W||_inf (W = L^{-1}) when that is at most
+   * kappa_fp64, or else Hager's estimate; the interior-point solver reports its
+   * last duality measure here instead. */
   double prim_res, dual_res, kappa_est, obj;
 } gnmpc_qp_info;
 

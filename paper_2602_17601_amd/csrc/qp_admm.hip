@@ -13,10 +13,11 @@
 // fits) and L is inverted in place, so each iteration costs two packed
 // triangular mat-vecs (W = L^{-1}: x~ = W'(W rhs)) plus one pass over Ct that
 // fuses z~ = Ct x~, the z/y updates and the next A'(rho z - y).
-// The condition number of K is estimated with Hager's 1-norm estimator
-// (Hager 1984, Higham 1988) on the explicit W; above kappa_fp64 the FP32
-// solver raises a flag and the FP64 instance of the same kernel (launched
-// right behind it) redoes factorization and iterations in FP64.
+// The condition number of K is first bounded by ||K||_1 ||W||_1 ||W||_inf (one
+// pass over W); only when that bound exceeds kappa_fp64 is it estimated with
+// Hager's 1-norm estimator (Hager 1984, Higham 1988) on the explicit W.  Above
+// kappa_fp64 the FP32 solver raises a flag and the FP64 instance of the same
+// kernel (launched right behind it) redoes factorization and iterations in FP64.
 #include <math.h>
 
 #include <cstring>
@@ -691,40 +692,79 @@ __device__ T inv_norm1_estimate(const Work<T>& w, int n) {
   return est;
 }
 
-// ||K||_1 (K symmetric: max column abs sum) from the lower block storage.
-// Column c sums |K_rc| over r >= c (block column c/16) and |K_cr| over r < c
-// (block row c/16); a wave takes one block column and one block row per job
-// (lanes: 16 columns x 4 row quarters), so the sum order is fixed.
+// Column and row abs sums of one block column / block row of the lower block storage,
+// for the 16 columns c = 16 B + (lane & 15) (rows split over the four lane groups, then
+// summed across them): col = sum over blocks (I >= B, B) of |X[r][c]|, taking in the
+// diagonal block only the entries with take_col(rr, cc); row = sum over blocks (B, J <= B)
+// of |X[c][r]|, in the diagonal block only those with take_row(rr, cc).  Four partial
+// sums rotate over the blocks, so the loads of several blocks are in flight at once.
+template <typename T, typename FC, typename FR>
+__device__ inline void block_abs_sums(const Work<T>& w, int nb, int B, FC take_col, FR take_row, T& col, T& row) {
+  const int lane = threadIdx.x & 63, cc = lane & 15, rq = lane >> 4;
+  T cs[4] = {T(0), T(0), T(0), T(0)}, rs[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+  for (int I = B; I < nb; ++I) {
+    const T* blk = w.mat + bo(I, B);
+    T p = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rr = 4 * rq + k;
+      if (I > B || take_col(rr, cc)) p += fabs(blk[rr * 16 + cc]);
+    }
+    cs[(I - B) & 3] += p;
+  }
+#pragma unroll 4
+  for (int J = 0; J <= B; ++J) {
+    const T* blk = w.mat + bo(B, J);
+    T p = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rr = 4 * rq + k;  // column index inside the block
+      if (J < B || take_row(rr, cc)) p += fabs(blk[cc * 16 + rr]);
+    }
+    rs[J & 3] += p;
+  }
+  col = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+  row = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+  col += __shfl_xor(col, 16, 64);
+  col += __shfl_xor(col, 32, 64);
+  row += __shfl_xor(row, 16, 64);
+  row += __shfl_xor(row, 32, 64);
+}
+
+// ||K||_1 (K symmetric: max column abs sum) from the lower block storage: column c
+// sums |K_rc| over r >= c (block column c/16) and |K_cr| over r < c (block row c/16).
 template <typename T>
 __device__ T knorm1(const Work<T>& w, int n) {
   const int lane = threadIdx.x & 63, wave = wave_index();
-  const int nb = nblocks(n), cc = lane & 15, rq = lane >> 4;
+  const int nb = nblocks(n), cc = lane & 15;
   T nrm = T(0);
   for (int B = wave; B < nb; B += kWaves) {
-    T s = T(0);
-    // block column B: rows r >= c
-    for (int I = B; I < nb; ++I) {
-      const T* blk = w.mat + bo(I, B);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int rr = 4 * rq + k;
-        if (I > B || rr >= cc) s += fabs(blk[rr * 16 + cc]);
-      }
-    }
-    // block row B: entries (c, r) with r < c, i.e. row c of blocks (B, J <= B)
-    for (int J = 0; J <= B; ++J) {
-      const T* blk = w.mat + bo(B, J);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int rr = 4 * rq + k;  // column index inside the block
-        if (J < B || rr < cc) s += fabs(blk[cc * 16 + rr]);
-      }
-    }
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    if (16 * B + cc < n) nrm = max(nrm, s);
+    T col, row;
+    block_abs_sums(w, nb, B, [](int rr, int c) { return rr >= c; }, [](int rr, int c) { return rr < c; }, col, row);
+    if (16 * B + cc < n) nrm = max(nrm, col + row);
   }
   return block_max(nrm, w.red);
+}
+
+// ||W||_1 and ||W||_inf of the explicit inverse factor W = L^{-1} (lower block storage,
+// diagonal blocks lower triangular with zeros above, identity padding): column sums over
+// block columns, row sums over block rows.
+template <typename T>
+__device__ void wnorms(const Work<T>& w, int n, T& n1, T& ninf) {
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  const int nb = nblocks(n), cc = lane & 15;
+  T c1 = T(0), ci = T(0);
+  for (int B = wave; B < nb; B += kWaves) {
+    T col, row;
+    block_abs_sums(w, nb, B, [](int, int) { return true; }, [](int, int) { return true; }, col, row);
+    if (16 * B + cc < n) {
+      c1 = max(c1, col);
+      ci = max(ci, row);
+    }
+  }
+  n1 = block_max(c1, w.red);
+  ninf = block_max(ci, w.red);
 }
 
 // Factor the K prepared by qp_prep_kernel and invert; false if not positive definite.
@@ -928,7 +968,16 @@ __device__ __attribute__((always_inline)) void qp_solve_body(const QpArgs<Tin>& 
     for (int i = threadIdx.x; i < n; i += kQpThreads) a.u[i] = (Tin)NAN;
     return;
   }
-  T kappa = knorm * inv_norm1_estimate(w, n);
+  // kappa_1(K) = ||K||_1 ||W'W||_1 <= ||K||_1 ||W||_1 ||W||_inf: when that bound is at most
+  // kappa_fp64 the FP32 factor is kept without Hager's estimate (the same decision, since
+  // the estimate never exceeds kappa_1), and the bound is what the info reports
+  T kappa;
+  {
+    T n1, ninf;
+    wnorms(w, n, n1, ninf);
+    const T bound = knorm * n1 * ninf;
+    kappa = (double)bound <= a.kappa_fp64 ? bound : knorm * inv_norm1_estimate(w, n);
+  }
   if (mode == 0 && sizeof(T) == 4 && (double)kappa > a.kappa_fp64) {
     if (threadIdx.x == 0) *a.flag = 1;
     return;
