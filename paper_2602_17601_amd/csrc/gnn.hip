@@ -668,12 +668,21 @@ struct Mfma2Args {
 // Stage images: word w of (tile, stage k) = its source, read from the forward
 // pass's masks and counters of stage k (or a constant).  One thread per word
 // and all stages, so each source entry is read once; the source list holds
-// (kind | round << 4, index) pairs for every tile.
+// (kind | round << 4, index) pairs for every tile.  The workgroups from
+// img_blocks on clear the nzero floats at zero instead (B, whose actuated
+// entries the Jacobian kernel then writes): an independent fill that shares
+// the launch.
 template <int Hd>
 __global__ void stage_image_kernel(int N, int M, int E, long img_words, const int32_t* __restrict__ src,
                                    const uint32_t* __restrict__ mask_enc, const uint32_t* __restrict__ mask_node,
                                    const uint32_t* __restrict__ mask_edge, const uint32_t* __restrict__ cnt,
-                                   uint32_t* __restrict__ img) {
+                                   uint32_t* __restrict__ img, int img_blocks, float* __restrict__ zero, long nzero) {
+  if ((int)blockIdx.x >= img_blocks) {
+    const long nb = (long)gridDim.x - img_blocks;
+    for (long t = (long)(blockIdx.x - img_blocks) * blockDim.x + threadIdx.x; t < nzero; t += nb * blockDim.x)
+      zero[t] = 0.f;
+    return;
+  }
   constexpr int HW = Hd / 32;
   const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= img_words) return;
@@ -2089,7 +2098,9 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
     if (fs != GNMPC_OK) return fs;
   }
   const long nB = (long)N * M * NBX * p->dims.nu;
-  fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
+  const int zero_blocks = (int)std::min<long>(ceil_div(nB, 1024), 2048);
+  if (!g.mfma2)  // else the fill shares the stage-image launch
+    fill_zero_kernel<<<(int)std::min<long>(ceil_div(nB, 256), 4096), 256, 0, s>>>((float*)B, nB);
   JvpArgs ja;
   ja.N = N;
   ja.M = M;
@@ -2127,15 +2138,18 @@ gnmpc_status launch_gnn_linearize(gnmpc_plan* p, const void* xhat, const void* u
   ja.nnz = p->nnz;
   dim3 grid(g.n_tiles, N);
   if (g.mfma2) {
-    // stage images of every (tile, stage) from this forward pass
+    // stage images of every (tile, stage) from this forward pass, and the B fill
     phase_begin(p, GNMPC_PH_GNN_STAGE_IMAGES, s);
-    const dim3 gimg((unsigned)((g.img_words + 255) / 256));
+    const int img_blocks = (int)((g.img_words + 255) / 256);
+    const dim3 gimg((unsigned)(img_blocks + zero_blocks));
     if (Hd == 64)
       stage_image_kernel<64><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
-                                                  g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
+                                                  g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img,
+                                                  img_blocks, (float*)B, nB);
     else
       stage_image_kernel<128><<<gimg, 256, 0, s>>>(N, M, g.E, g.img_words, g.img_src, g.mask_enc, g.mask_node,
-                                                   g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img);
+                                                   g.mask_edge, reinterpret_cast<const uint32_t*>(g.cnt), g.img,
+                                                   img_blocks, (float*)B, nB);
     phase_end(p, GNMPC_PH_GNN_STAGE_IMAGES, s);
   }
   phase_begin(p, GNMPC_PH_GNN_JACOBIAN, s);

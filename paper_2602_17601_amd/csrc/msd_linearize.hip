@@ -109,11 +109,14 @@ __device__ inline T spring_force(const T d[3], T k, T k3, int r) {
 
 constexpr int kTile = 128;  // (stage, entry) pairs per workgroup
 
+// The three parts of the linearization (A blocks, B, offsets c) read only xhat and
+// uhat and write disjoint outputs, so one launch runs all three on disjoint ranges
+// of workgroups (msd_lin_kernel below); each part is a device function of its
+// workgroup index within its range.
 template <typename T>
-__global__ void __launch_bounds__(kTile) msd_A_kernel(MsdArgs<T> a, T* __restrict__ A) {
-  __shared__ T tile[kTile * 36];
+__device__ inline void msd_A_part(const MsdArgs<T>& a, T* __restrict__ A, long blk, T* tile) {
   const long total = (long)a.N * a.nnz;
-  const long base = (long)blockIdx.x * kTile;
+  const long base = blk * kTile;
   const long idx = base + threadIdx.x;
   if (idx < total) {
     int k = (int)(idx / a.nnz);
@@ -135,11 +138,12 @@ __global__ void __launch_bounds__(kTile) msd_A_kernel(MsdArgs<T> a, T* __restric
 }
 
 // B is constant for this model: node i actuated by input a has B[r][3a + r%3]
-// = dt^2/m (positions) or dt/m (velocities).  One lane per output element.
+// = dt^2/m (positions) or dt/m (velocities).  One lane per output element, grid-stride
+// over the nblk workgroups of this part.
 template <typename T>
-__global__ void msd_B_kernel(MsdArgs<T> a, T* __restrict__ B) {
+__device__ inline void msd_B_part(const MsdArgs<T>& a, T* __restrict__ B, long blk, long nblk) {
   const long total = (long)a.N * a.M * NBX * a.nu;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+  for (long t = blk * kTile + threadIdx.x; t < total; t += nblk * kTile) {
     int col = (int)(t % a.nu);
     long rest = t / a.nu;
     int r = (int)(rest % NBX);
@@ -153,11 +157,10 @@ __global__ void msd_B_kernel(MsdArgs<T> a, T* __restrict__ B) {
 
 // c = f(xhat, uhat) - sum_j A^{ij} xhat^j - B uhat, one lane per (stage, node).
 template <typename T>
-__global__ void __launch_bounds__(kTile) msd_c_kernel(MsdArgs<T> a, T* __restrict__ c, T* __restrict__ fnext) {
-  __shared__ T tc[kTile * NBX];
-  __shared__ T tf[kTile * NBX];
+__device__ inline void msd_c_part(const MsdArgs<T>& a, T* __restrict__ c, T* __restrict__ fnext, long blk, T* tc) {
+  T* tf = tc + kTile * NBX;
   const long total = (long)a.N * a.M;
-  const long base = (long)blockIdx.x * kTile;
+  const long base = blk * kTile;
   const long idx = base + threadIdx.x;
   if (idx < total) {
     int k = (int)(idx / a.M);
@@ -223,6 +226,17 @@ __global__ void __launch_bounds__(kTile) msd_c_kernel(MsdArgs<T> a, T* __restric
   }
 }
 
+// Workgroups [0, gA): A blocks; [gA, gA + gC): offsets; the rest: B.
+template <typename T>
+__global__ void __launch_bounds__(kTile) msd_lin_kernel(MsdArgs<T> a, T* __restrict__ A, T* __restrict__ B,
+                                                        T* __restrict__ c, T* __restrict__ fnext, long gA, long gC) {
+  __shared__ T smem[kTile * 36];  // the A part's staged blocks, or the c part's two staged rows
+  const long b = blockIdx.x;
+  if (b < gA) msd_A_part(a, A, b, smem);
+  else if (b < gA + gC) msd_c_part(a, c, fnext, b - gA, smem);
+  else msd_B_part(a, B, b - gA - gC, (long)gridDim.x - gA - gC);
+}
+
 template <typename T>
 gnmpc_status run(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, void* B, void* c, void* fnext,
                  hipStream_t s) {
@@ -246,14 +260,10 @@ gnmpc_status run(gnmpc_plan* p, const void* xhat, const void* uhat, void* A, voi
   a.k3 = (T)p->msd.k3;
   a.grav = (T)p->msd.gravity;
   a.anchor = p->msd.anchor;
-  long nA = (long)a.N * a.nnz;
+  const long nA = (long)a.N * a.nnz, nB = (long)a.N * a.M * NBX * a.nu, nc = (long)a.N * a.M;
+  const long gA = ceil_div(nA, kTile), gC = ceil_div(nc, kTile), gB = std::min<long>(ceil_div(nB, kTile), 8192);
   phase_begin(p, GNMPC_PH_MSD_LINEARIZE, s);
-  msd_A_kernel<T><<<ceil_div(nA, kTile), kTile, 0, s>>>(a, (T*)A);
-  long nB = (long)a.N * a.M * NBX * a.nu;
-  int gB = (int)std::min<long>(ceil_div(nB, 256), 8192);
-  msd_B_kernel<T><<<gB, 256, 0, s>>>(a, (T*)B);
-  long nc = (long)a.N * a.M;
-  msd_c_kernel<T><<<ceil_div(nc, kTile), kTile, 0, s>>>(a, (T*)c, (T*)fnext);
+  msd_lin_kernel<T><<<(unsigned)(gA + gC + gB), kTile, 0, s>>>(a, (T*)A, (T*)B, (T*)c, (T*)fnext, gA, gC);
   phase_end(p, GNMPC_PH_MSD_LINEARIZE, s);
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
