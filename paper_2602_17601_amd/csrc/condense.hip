@@ -778,7 +778,9 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
   T* S = (T*)p->d_S;
   T* G = (T*)p->d_Gx;
   phase_begin(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
-  copy_kernel<T><<<ceil_div((long)M * NBX, 256), 256, 0, s>>>((const T*)x0, G, (long)M * NBX);
+  // Gx_0 = x0: the first launch reads x0 itself (stage 0 of the workspace is only
+  // filled for the optional Gx output below)
+  auto gx_in = [&](int k) { return k ? (const T*)(G + (size_t)k * M * NBX) : (const T*)x0; };
   const int wmax = p->wmax;
   const size_t pb_lds = sizeof(T) * ((size_t)p->pb_umax * NBX * (kPropCW + 1) + (size_t)p->pb_emax * 36) +
                         sizeof(int32_t) * (size_t)p->pb_rec_stride;
@@ -803,7 +805,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
           k, M, nu, p->pb_nodes, p->pb_emax, p->pb2_u1max, p->pb2_e1max, p->pb2_u2max, p->d_pb2_rec,
           (const T*)A + k * sA, (const T*)A + (k + 1) * sA, (const T*)B + k * sB, (const T*)B + (k + 1) * sB,
           (const T*)c + k * sG, (const T*)c + (k + 1) * sG, S_in, S + S_offset(k + 1, M, nu),
-          S + S_offset(k + 2, M, nu), G + k * sG, G + (k + 1) * sG, G + (k + 2) * sG);
+          S + S_offset(k + 2, M, nu), gx_in(k), G + (k + 1) * sG, G + (k + 2) * sG);
       ++k;
       continue;
     }
@@ -812,7 +814,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
       sprop_block_kernel<T><<<grid, 256, pb_lds, s>>>(
           k, M, nu, p->pb_nodes, p->pb_rec_stride, p->pb_umax, p->pb_emax, p->d_pb_rec,
           (const T*)A + (size_t)k * p->nnz * 36, (const T*)B + (size_t)k * M * NBX * nu,
-          (const T*)c + (size_t)k * M * NBX, S_in, S + S_offset(k + 1, M, nu), G + (size_t)k * M * NBX,
+          (const T*)c + (size_t)k * M * NBX, S_in, S + S_offset(k + 1, M, nu), gx_in(k),
           G + (size_t)(k + 1) * M * NBX);
       continue;
     }
@@ -824,7 +826,7 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
     sprop_kernel<T><<<ceil_div(M, npw), kPropThreads, lds, s>>>(
         k, M, nu, npw, p->d_prow, p->d_pcol, (const T*)A + (size_t)k * p->nnz * 36,
         (const T*)B + (size_t)k * M * NBX * nu, (const T*)c + (size_t)k * M * NBX, S_in,
-        S + S_offset(k + 1, M, nu), G + (size_t)k * M * NBX, G + (size_t)(k + 1) * M * NBX, wmax);
+        S + S_offset(k + 1, M, nu), gx_in(k), G + (size_t)(k + 1) * M * NBX, wmax);
   }
   phase_end(p, GNMPC_PH_CONDENSE_PROPAGATE, s);
   GramShape sh = gram_shape(M, nu, N);
@@ -854,9 +856,10 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
                                            (const T*)rowd, S, G, (T*)Ct, (T*)dt);
     phase_end(p, GNMPC_PH_CONDENSE_ROWS, s);
   }
-  if (Gx) {
-    const long ng = (long)(N + 1) * M * NBX;
-    copy_kernel<T><<<(int)std::min<long>(ceil_div(ng, 256), 2048), 256, 0, s>>>(G, (T*)Gx, ng);
+  if (Gx) {  // Gx_0 = x0, then stages 1..N from the workspace
+    const long n0 = (long)M * NBX, ng = (long)N * M * NBX;
+    copy_kernel<T><<<(int)std::min<long>(ceil_div(n0, 256), 2048), 256, 0, s>>>((const T*)x0, (T*)Gx, n0);
+    copy_kernel<T><<<(int)std::min<long>(ceil_div(ng, 256), 2048), 256, 0, s>>>(G + n0, (T*)Gx + n0, ng);
   }
   GNMPC_HIP_TRY(p, hipGetLastError());
   return GNMPC_OK;
