@@ -1317,6 +1317,17 @@ __global__ void __launch_bounds__(kQpThreads) qp_solve_kernel(QpArgs<Tin> a, int
   qp_solve_body<T, Tin, MAT_LDS>(a, mode);
 }
 
+// FP32 pass and, behind it in the same workgroup, the FP64 pass, which returns at
+// once unless the FP32 pass raised the flag (thread 0's write is seen by every wave
+// after the barrier: the waves of a workgroup share one CU); one launch instead of
+// two.  The dynamic LDS is the larger of the two passes' layouts, which share it.
+template <typename Tin, bool LDS32, bool LDS64>
+__global__ void __launch_bounds__(kQpThreads) qp_solve_two_pass_kernel(QpArgs<Tin> a) {
+  qp_solve_body<float, Tin, LDS32>(a, 0);
+  __syncthreads();
+  qp_solve_body<double, Tin, LDS64>(a, 1);
+}
+
 // Many instances' QPs in one launch, one workgroup each: each instance's set-up
 // kernel stored its solve descriptor in its plan's memory, and the launch takes
 // the addresses (kernel arguments, so the launch needs no copy and a graph can
@@ -1358,6 +1369,30 @@ gnmpc_status launch_pass(gnmpc_plan* p, const QpArgs<Tin>& a, int mode, hipStrea
   }
   if (in_lds) qp_solve_kernel<T, Tin, true><<<1, kQpThreads, lds, s>>>(a, mode);
   else qp_solve_kernel<T, Tin, false><<<1, kQpThreads, lds, s>>>(a, mode);
+  return GNMPC_OK;
+}
+
+// The FP32 pass and its FP64 hand-over in one launch (qp_solve_two_pass_kernel).
+template <typename Tin>
+gnmpc_status launch_two_pass(gnmpc_plan* p, const QpArgs<Tin>& a, hipStream_t s) {
+  const bool l32 = lds_bytes(a.n, a.n_c, sizeof(float), true) <= kLdsCap;
+  const bool l64 = lds_bytes(a.n, a.n_c, sizeof(double), true) <= kLdsCap;
+  const size_t lds = std::max(lds_bytes(a.n, a.n_c, sizeof(float), l32), lds_bytes(a.n, a.n_c, sizeof(double), l64));
+  if (lds > kLdsCap) {
+    if (p) p->last_error = "QP too large for one workgroup's LDS";
+    return GNMPC_UNSUPPORTED;
+  }
+  // the FP64 layout fits LDS only where the FP32 one does
+  const void* fn = l64 ? (const void*)qp_solve_two_pass_kernel<Tin, true, true>
+                       : l32 ? (const void*)qp_solve_two_pass_kernel<Tin, true, false>
+                             : (const void*)qp_solve_two_pass_kernel<Tin, false, false>;
+  if (set_max_lds(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    if (p) p->last_error = "QP: could not raise the LDS limit of the solve kernel";
+    return GNMPC_HIP_ERROR;
+  }
+  if (l64) qp_solve_two_pass_kernel<Tin, true, true><<<1, kQpThreads, lds, s>>>(a);
+  else if (l32) qp_solve_two_pass_kernel<Tin, true, false><<<1, kQpThreads, lds, s>>>(a);
+  else qp_solve_two_pass_kernel<Tin, false, false><<<1, kQpThreads, lds, s>>>(a);
   return GNMPC_OK;
 }
 
@@ -1415,11 +1450,10 @@ gnmpc_status run(gnmpc_plan* p, unsigned char* ws, int32_t* flag, int n, const v
   if (p) phase_begin(p, GNMPC_PH_QP, s);
   launch_prep(a, s);
   gnmpc_status rc;
-  if (sizeof(Tin) == 8) {
+  if constexpr (sizeof(Tin) == 8) {
     rc = launch_pass<double, Tin>(p, a, 2, s);
   } else {
-    rc = launch_pass<float, Tin>(p, a, 0, s);
-    if (rc == GNMPC_OK) rc = launch_pass<double, Tin>(p, a, 1, s);
+    rc = launch_two_pass<Tin>(p, a, s);
   }
   if (p) phase_end(p, GNMPC_PH_QP, s);
   if (rc != GNMPC_OK) return rc;
