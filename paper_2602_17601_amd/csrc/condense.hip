@@ -676,13 +676,21 @@ __global__ void gvec_fold_kernel(GramShape sh, const T* __restrict__ gpart, T* _
 // (or r), mirrored to the upper triangle.  g comes from per-stage sums
 // (gstage, [N][n]) or, when gtile is set, from the per-(tile, stage, chunk)
 // partials of the diagonal Gram tiles ([nt][N][nchunks][kT]).
+// One workgroup per 64 consecutive outputs (the lower triangle of H in row order,
+// then g); wave q sums the stages k = k0 + q, k0 + q + 4, ... of each output (k0
+// its first live stage; each stage's chunk partials in chunk order), and the four
+// wave partials are added in wave order: a fixed order, with a quarter of the
+// dependent load rounds per thread.
 template <typename T>
-__global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, const T* __restrict__ gstage,
-                                   const T* __restrict__ gtile, const T* __restrict__ R, const T* __restrict__ r,
-                                   T* __restrict__ H, T* __restrict__ g) {
+__global__ void __launch_bounds__(256) gram_reduce_kernel(GramShape sh, const T* __restrict__ part,
+                                                          const T* __restrict__ gstage, const T* __restrict__ gtile,
+                                                          const T* __restrict__ R, const T* __restrict__ r,
+                                                          T* __restrict__ H, T* __restrict__ g) {
+  __shared__ T red[4][64];
   const int n = sh.n;
   const long nlow = (long)n * (n + 1) / 2;
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const long t = (long)blockIdx.x * 64 + l;
   auto chunk_sum = [&](const T* base, size_t stride) {
     T s = T(0);
     for (int c0 = 0; c0 < sh.nchunks; c0 += 8) {
@@ -694,31 +702,38 @@ __global__ void gram_reduce_kernel(GramShape sh, const T* __restrict__ part, con
     }
     return s;
   };
+  int a = 0, b = 0;
+  T s = T(0);
   if (t < nlow) {
-    int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((long)(a + 1) * (a + 2) / 2 <= t) ++a;
     while ((long)a * (a + 1) / 2 > t) --a;
-    int b = (int)(t - (long)a * (a + 1) / 2);
-    int ta = a / kT, tb = b / kT;
-    int tile = ta * (ta + 1) / 2 + tb;
-    int e = (a % kT) * kT + (b % kT);
-    T s = T(0);
-    for (int k = a / sh.nu + 1; k <= sh.N; ++k)
+    b = (int)(t - (long)a * (a + 1) / 2);
+    const int ta = a / kT, tb = b / kT;
+    const int tile = ta * (ta + 1) / 2 + tb;
+    const int e = (a % kT) * kT + (b % kT);
+    for (int k = a / sh.nu + 1 + q; k <= sh.N; k += 4)
       s += chunk_sum(part + ((((size_t)tile * sh.N) + (k - 1)) * sh.nchunks) * (kT * kT) + e, (size_t)kT * kT);
-    int ka = a / sh.nu, kb = b / sh.nu;
+  } else if (t < nlow + n) {
+    a = (int)(t - nlow);
+    if (gtile) {
+      const int ta = a / kT;
+      for (int k = a / sh.nu + 1 + q; k <= sh.N; k += 4)
+        s += chunk_sum(gtile + (((size_t)ta * sh.N + (k - 1)) * sh.nchunks) * kT + a % kT, (size_t)kT);
+    } else {
+      for (int k = a / sh.nu + 1 + q; k <= sh.N; k += 4) s += gstage[(size_t)(k - 1) * n + a];
+    }
+  }
+  red[q][l] = s;
+  __syncthreads();
+  if (q != 0) return;
+  s = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+  if (t < nlow) {
+    const int ka = a / sh.nu, kb = b / sh.nu;
     if (ka == kb) s += R[((size_t)ka * sh.nu + (a % sh.nu)) * sh.nu + (b % sh.nu)];
     H[(size_t)a * n + b] = s;
     H[(size_t)b * n + a] = s;
   } else if (t < nlow + n) {
-    int a = (int)(t - nlow);
-    T s = T(0);
-    if (gtile) {
-      const int ta = a / kT;
-      for (int k = a / sh.nu + 1; k <= sh.N; ++k)
-        s += chunk_sum(gtile + (((size_t)ta * sh.N + (k - 1)) * sh.nchunks) * kT + a % kT, (size_t)kT);
-    } else {
-      for (int k = a / sh.nu + 1; k <= sh.N; ++k) s += gstage[(size_t)(k - 1) * n + a];
-    }
     g[a] = s + r[a];
   }
 }
@@ -847,8 +862,8 @@ gnmpc_status run(gnmpc_plan* p, const void* A, const void* B, const void* c, con
     gvec_fold_kernel<T><<<ceil_div((long)N * sh.n, 256), 256, 0, s>>>(sh, gpart, gstage);
   }
   long nred = (long)sh.n * (sh.n + 1) / 2 + sh.n;
-  gram_reduce_kernel<T><<<ceil_div(nred, 256), 256, 0, s>>>(sh, part, gstage, gtile, (const T*)R, (const T*)r,
-                                                            (T*)H, (T*)g);
+  gram_reduce_kernel<T><<<ceil_div(nred, 64), 256, 0, s>>>(sh, part, gstage, gtile, (const T*)R, (const T*)r,
+                                                           (T*)H, (T*)g);
   phase_end(p, GNMPC_PH_CONDENSE_GRAM, s);
   if (p->n_c > 0) {
     phase_begin(p, GNMPC_PH_CONDENSE_ROWS, s);
