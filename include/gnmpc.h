@@ -349,7 +349,7 @@ gnmpc_status gnmpc_condense(gnmpc_plan* plan, const void* A, const void* B, cons
 /* Tile autotuner of the condensing (set-up time, not for graph capture: it
  * synchronizes `stream`).  Times gnmpc_condense on the caller's arrays (the
  * arguments of gnmpc_condense, Gx omitted) `reps` times for every feasible
- * propagation variant -- the per-node kernel, node blocks of 4, 2 or 1 nodes one
+ * propagation variant -- the per-node kernel, node blocks of 16, 8, 4, 2 or 1 nodes one
  * stage per launch, and the same blocks two stages per launch where their halo
  * fits -- keeps the fastest as the plan's choice for later calls (until the next
  * gnmpc_graph_set) and writes every measurement to `report` (host).  The

@@ -518,8 +518,10 @@ static gnmpc_status qp_check(gnmpc_plan* p, int32_t n, const void* H, const void
 gnmpc_status gnmpc_condense_variant_set(gnmpc_plan* p, int32_t variant, int32_t block_nodes) {
   if (!p) return GNMPC_INVALID_ARG;
   if (!p->graph_ready) return fail(p, GNMPC_NOT_READY, "condense_variant_set: graph must be set");
-  if (variant < -1 || variant > 2 || (variant >= 1 && block_nodes != 1 && block_nodes != 2 && block_nodes != 4))
-    return fail(p, GNMPC_INVALID_ARG, "condense_variant_set: variant -1..2, blocks of 1, 2 or 4 nodes");
+  if (variant < -1 || variant > 2 ||
+      (variant >= 1 && block_nodes != 1 && block_nodes != 2 && block_nodes != 4 && block_nodes != 8 &&
+       block_nodes != 16))
+    return fail(p, GNMPC_INVALID_ARG, "condense_variant_set: variant -1..2, blocks of 1, 2, 4, 8 or 16 nodes");
   GNMPC_HIP_TRY(p, hipSetDevice(p->device));
   gnmpc_status st = prop_blocks_build_nb(p, variant >= 1 ? block_nodes : 4);
   if (st != GNMPC_OK) return st;
@@ -551,7 +553,7 @@ gnmpc_status gnmpc_autotune_condense(gnmpc_plan* p, const void* A, const void* B
   if (st != GNMPC_OK) return st;
   struct Cand { int variant, nb; };
   std::vector<Cand> cands{{0, 0}};
-  for (int nb = 4; nb >= 1; nb /= 2) {
+  for (int nb = 16; nb >= 1; nb /= 2) {
     if ((st = prop_blocks_build_nb(p, nb)) != GNMPC_OK) return st;
     if (p->pb_nodes != nb) continue;  // blocks of nb nodes do not fit LDS
     cands.push_back({1, nb});

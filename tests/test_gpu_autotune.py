@@ -66,7 +66,7 @@ def test_every_propagation_variant_matches_the_oracle(M, hops, L, N, nu):
     P = wl.make_problem("tune", M=M, hops=hops, N=N, n_act=nu // 3, model="msd", seed=M, n_random_rows=40)
     plan, d, ref, Rb = _setup(P, L)
     tried = 0
-    for variant, nb in [(0, 0), (1, 4), (1, 2), (1, 1), (2, 4), (2, 2), (2, 1)]:
+    for variant, nb in [(0, 0), (1, 16), (1, 8), (1, 4), (1, 2), (1, 1), (2, 16), (2, 8), (2, 4), (2, 2), (2, 1)]:
         try:
             plan.condense_variant(variant, nb)
         except gn.GnmpcError as e:
