@@ -6,7 +6,7 @@
 
 #include "common.hpp"
 
-struct GnnState;   // defined in gnn.hip
+struct GnnState;   // defined in gnn_state.hpp
 struct InetState;  // defined in inet.hip
 
 struct gnmpc_plan {
