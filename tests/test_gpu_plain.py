@@ -261,6 +261,29 @@ def test_qp_ill_conditioned_takes_the_fp64_path():
     assert _qp_rel(u, ref) < 1e-4
 
 
+def test_qp_condition_report_is_an_upper_bound_when_it_decides():
+    """A well-conditioned QP keeps the FP32 factor on the bound ||K||_1 ||W||_1 ||W||_inf
+    (W = L^{-1}), which the info reports: it must lie between kappa_1(K) and n kappa_1(K)
+    (||W||_1 ||W||_inf <= n ||W||_2^2 = n ||K^{-1}||_2 <= n ||K^{-1}||_1), with K = H +
+    sigma I + rho (I + Ct' Ct) formed here in FP64 (default rho 0.1, sigma 1e-6; box and
+    one-sided rows have relative weight 1)."""
+    rng = np.random.default_rng(11)
+    n, nc = 60, 20
+    Qm, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    H = _cast(Qm @ np.diag(np.geomspace(0.1, 10.0, n)) @ Qm.T, torch.float32)
+    H = 0.5 * (H + H.T)
+    g = _cast(rng.normal(size=n), torch.float32)
+    Ct = _cast(rng.normal(size=(nc, n)) / np.sqrt(n), torch.float32)
+    lb, ub = -np.ones(n), np.ones(n)
+    lc, uc = np.full(nc, -np.inf), np.full(nc, 0.5)
+    plan = gn.Plan(1, n, 1, nc, gn.F32)
+    u, info = _solve_gpu(plan, H, g, lb, ub, Ct, lc, uc, torch.float32)
+    K = H + 1e-6 * np.eye(n) + 0.1 * (np.eye(n) + Ct.T @ Ct)
+    kappa1 = np.linalg.norm(K, 1) * np.linalg.norm(np.linalg.inv(K), 1)
+    assert info.status == gn.QP_SOLVED and info.used_fp64 == 0
+    assert kappa1 * (1 - 1e-3) <= info.kappa_est <= 1.01 * n * kappa1, (info.kappa_est, kappa1)
+
+
 def test_qp_reports_infeasible_rows():
     n = 6
     H = np.eye(n)
