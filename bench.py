@@ -626,9 +626,17 @@ def paper_model_rate(torch, gn, wl, iters=50):
 
     lin_ms = timed(lambda: plan.linearize(b["xhat"], b["uhat"], b["A"], b["B"], b["c"]))
     rti_ms = timed(lambda: gn.rti_step(plan, b, xpred, xn, un))
+    qp_iters = gn.qp_info(b["info"]).iters
+    # the iteration's condensed QP (120 inputs, box bounds) by the interior-point solver and by ADMM
+    u_ipm = e(n)
+    info_ipm = torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device="cuda")
+    ipm_ms = timed(lambda: plan.solve_qp_ipm(b["H"], b["g"], b["lb"], b["ub"], None, None, None, u_ipm, info_ipm,
+                                             tol=1e-8))
+    admm_ms = timed(lambda: plan.solve_box_qp(b["H"], b["g"], b["lb"], b["ub"], None, None, None, b["u"], b["info"]))
     return {"workload": "interaction network (psi 4x50, phi 8x250), 4 nodes x 2 neighbours, n_u=6, N=20, FP32",
             "linearize_ms": lin_ms, "rti_step_ms": rti_ms, "rti_steps_per_s": 1e3 / rti_ms,
-            "qp_iters": gn.qp_info(b["info"]).iters}
+            "qp_iters": qp_iters, "qp_ipm_ms": ipm_ms, "qp_ipm_iters": gn.qp_info(info_ipm).iters,
+            "qp_admm_ms": admm_ms}
 
 
 def training_rate(torch, gn, wl, iters=10):

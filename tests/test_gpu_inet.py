@@ -100,6 +100,14 @@ def test_rti_step_with_the_paper_model_matches_the_oracle():
     assert _rel(_np(b["H"]), ref["H"]) < 1e-10 and _rel(_np(b["g"]), ref["g"]) < 1e-10
     assert _rel(_np(b["u"]), ref["u"]) < 1e-3
     assert _rel(_np(xpred), ref["x"]) < 1e-4
+    # the same condensed QP by the interior-point solver, the paper's kind of QP solver
+    u_ipm = e(n)
+    info = torch.zeros(gn.QP_INFO_BYTES, dtype=torch.uint8, device="cuda")
+    plan.solve_qp_ipm(b["H"], b["g"], b["lb"], b["ub"], None, None, None, u_ipm, info, tol=1e-12)
+    torch.cuda.synchronize()
+    inf = gn.qp_info(info)
+    assert inf.status == gn.QP_SOLVED, (inf.status, inf.iters)
+    assert _rel(_np(u_ipm), ref["u"]) < max(1e-6, 10 * np.sqrt(inf.kappa_est))
 
 
 def test_model_set_inet_rejects_bad_calls():
