@@ -489,6 +489,13 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count,
 gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
                             const gnmpc_admm_settings* settings, void* stream);
 
+/* The same iteration with the condensed QP solved by the interior-point method
+ * (gnmpc_solve_qp_ipm with tol and max_iter; its status and duality measure go
+ * to d->info), the kind of QP solver the paper's loop uses (Sec. VI-A).  Other
+ * arguments, aliasing rules and errors as gnmpc_rti_step. */
+gnmpc_status gnmpc_rti_step_ipm(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
+                                double tol, int32_t max_iter, void* stream);
+
 /* ---------------- per-phase GPU timers ---------------- */
 
 /* Phases timed by gnmpc_timers_*: hipEvents are recorded on the caller's stream
@@ -496,13 +503,15 @@ gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_ne
 typedef enum {
   GNMPC_PH_GNN_FORWARD = 0,       /* GNN forward pass at the N linearization points   */
   GNMPC_PH_GNN_JACOBIAN = 1,      /* the forward-mode Jacobian kernel                  */
-  GNMPC_PH_GNN_ASSEMBLY = 2,      /* B zero fill and the offsets c                     */
+  GNMPC_PH_GNN_ASSEMBLY = 2,      /* the offsets c (and the B zero fill, where the
+                                   * Jacobian kernel runs without stage images)        */
   GNMPC_PH_MSD_LINEARIZE = 3,     /* analytic mass-spring-damper linearization         */
   GNMPC_PH_CONDENSE_PROPAGATE = 4,/* the stage recursion for S_k and Gx_k              */
   GNMPC_PH_CONDENSE_GRAM = 5,     /* H and g                                           */
   GNMPC_PH_CONDENSE_ROWS = 6,     /* condensed state rows                              */
   GNMPC_PH_QP = 7,                /* the QP solve                                      */
-  GNMPC_PH_GNN_STAGE_IMAGES = 8,  /* the Jacobian kernel's stage images from the forward pass */
+  GNMPC_PH_GNN_STAGE_IMAGES = 8,  /* the Jacobian kernel's stage images from the forward pass,
+                                   * with the B zero fill in the same launch           */
   GNMPC_PH_COUNT = 9
 } gnmpc_phase;
 

@@ -735,22 +735,45 @@ gnmpc_status gnmpc_step_batched(const gnmpc_step_desc* descs, int32_t count, con
   return GNMPC_OK;
 }
 
-gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
-                            const gnmpc_admm_settings* st, void* stream) {
-  if (!d || !d->plan || !st) return GNMPC_INVALID_ARG;
+// Algorithm 1's iteration around a QP solve (ADMM or interior point, `qp`).
+extern "C++" {
+template <typename QpFn>
+static gnmpc_status rti_iteration(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next, QpFn qp,
+                                  void* stream) {
   gnmpc_plan* p = d->plan;
   if (!xpred || !xhat_next || !uhat_next) return fail(p, GNMPC_INVALID_ARG, "rti_step: null array");
   if (xpred == xhat_next || xpred == d->xhat || xpred == d->x0)
     return fail(p, GNMPC_INVALID_ARG, "rti_step: xpred aliases an input or xhat_next");
-  const int32_t n = p->dims.N * p->dims.nu;
   gnmpc_status s = gnmpc_linearize(p, d->xhat, d->uhat, d->A, d->B, d->c, nullptr, nullptr, stream);
   if (s == GNMPC_OK)
     s = gnmpc_condense(p, d->A, d->B, d->c, d->x0, d->Q, d->Q_full, d->q, d->R, d->r, d->rowC, d->rowd, d->H,
                        d->g, d->Ct, d->dt, nullptr, stream);
-  if (s == GNMPC_OK) s = gnmpc_solve_box_qp(p, n, d->H, d->g, d->lb, d->ub, p->n_c, d->Ct, d->lc, d->uc, st, d->u, d->info, stream);
+  if (s == GNMPC_OK) s = qp(p->dims.N * p->dims.nu);
   if (s == GNMPC_OK) s = gnmpc_rollout_linear(p, d->A, d->B, d->c, d->x0, d->u, xpred, stream);
   if (s == GNMPC_OK) s = launch_rti_shift(p, xpred, d->u, xhat_next, uhat_next, (hipStream_t)stream);
   return s;
+}
+}  // extern "C++"
+
+gnmpc_status gnmpc_rti_step(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next,
+                            const gnmpc_admm_settings* st, void* stream) {
+  if (!d || !d->plan || !st) return GNMPC_INVALID_ARG;
+  gnmpc_plan* p = d->plan;
+  return rti_iteration(d, xpred, xhat_next, uhat_next, [&](int32_t n) {
+    return gnmpc_solve_box_qp(p, n, d->H, d->g, d->lb, d->ub, p->n_c, d->Ct, d->lc, d->uc, st, d->u, d->info,
+                              stream);
+  }, stream);
+}
+
+gnmpc_status gnmpc_rti_step_ipm(const gnmpc_step_desc* d, void* xpred, void* xhat_next, void* uhat_next, double tol,
+                                int32_t max_iter, void* stream) {
+  if (!d || !d->plan) return GNMPC_INVALID_ARG;
+  gnmpc_plan* p = d->plan;
+  if (!(tol > 0) || max_iter < 1) return fail(p, GNMPC_INVALID_ARG, "rti_step_ipm: tol > 0 and max_iter >= 1");
+  return rti_iteration(d, xpred, xhat_next, uhat_next, [&](int32_t n) {
+    return gnmpc_solve_qp_ipm(p, n, d->H, d->g, d->lb, d->ub, p->n_c, d->Ct, d->lc, d->uc, tol, max_iter, d->u,
+                              d->info, stream);
+  }, stream);
 }
 
 }  // extern "C"

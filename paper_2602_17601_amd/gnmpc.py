@@ -135,6 +135,7 @@ def lib():
             "gnmpc_timers_enable": ([vp, i32], i32),
             "gnmpc_step_batched": ([vp, i32, P(AdmmSettings), vp], i32),
             "gnmpc_rti_step": ([P(StepDesc), vp, vp, vp, P(AdmmSettings), vp], i32),
+            "gnmpc_rti_step_ipm": ([P(StepDesc), vp, vp, vp, C.c_double, i32, vp], i32),
             "gnmpc_timers_read": ([vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
@@ -538,6 +539,19 @@ def rti_step(plan, b, xpred, xhat_next=None, uhat_next=None, settings=None, stre
             plan._dev(un, (N, nu), "uhat_next")]
     st = settings or default_admm_settings()
     plan._check(lib().gnmpc_rti_step(C.byref(d), *args, C.byref(st), _stream(stream)), "rti_step")
+
+
+def rti_step_ipm(plan, b, xpred, xhat_next=None, uhat_next=None, tol=1e-9, max_iter=100, stream=None):
+    """gnmpc_rti_step_ipm: rti_step with the condensed QP solved by the
+    interior-point method (tol on the duality measure, max_iter iterations)."""
+    d = step_desc(plan, b)
+    xn = b["xhat"] if xhat_next is None else xhat_next
+    un = b["uhat"] if uhat_next is None else uhat_next
+    M, N, nu = plan.M, plan.N, plan.nu
+    args = [plan._dev(xpred, (N + 1, M, 6), "xpred"), plan._dev(xn, (N + 1, M, 6), "xhat_next"),
+            plan._dev(un, (N, nu), "uhat_next")]
+    plan._check(lib().gnmpc_rti_step_ipm(C.byref(d), *args, float(tol), int(max_iter), _stream(stream)),
+                "rti_step_ipm")
 
 
 def step_batched(descs, settings=None, stream=None):

@@ -87,6 +87,43 @@ def test_rti_closed_loop_fp64_spring_damper_matches_the_oracle():
     assert active > 0
 
 
+def test_rti_with_the_interior_point_qp_matches_the_oracle_loop():
+    """The spring-damper closed loop of the test above with gnmpc_rti_step_ipm: the
+    condensed QPs solved by the device's interior-point method (tol 1e-12), so u*
+    follows the oracle's interior-point solution to the IPM's own accuracy
+    (max(1e-6, 10 sqrt(mu)) at its last duality measure mu), not ADMM's."""
+    prm = wl.MSDParams(k=10.0, c=0.1, m=1.0, dt=0.05, k3=50.0)
+    P = wl.make_problem("rti64ipm", M=40, hops=2, N=15, n_act=2, model="msd", seed=31, msd=prm, x0_sigma=0.05,
+                        umax=0.5, qdiag=(100, 100, 100, 1, 1, 1), rho_r=1e-3)
+    N, M, nu = P.N, P.M, P.nu
+    plan = _msd_plan(P, gn.F64)
+    xh, uh = initial_trajectory(P.x0, N, nu)
+    b = _bufs(plan, P, torch.float64, P.x0, xh, uh)
+    xpred = torch.empty(N + 1, M, 6, dtype=torch.float64, device="cuda")
+    lin = lambda a, c: msd_linearize(a, c, P.row_ptr, P.col, P.act, prm)
+    x = P.x0.copy()
+    active = 0
+    for t in range(8):
+        gn.rti_step_ipm(plan, b, xpred, tol=1e-12)
+        torch.cuda.synchronize()
+        inf = gn.qp_info(b["info"])
+        assert inf.status == gn.QP_SOLVED, (t, inf.status, inf.iters)
+        ref = rti_step(x, xh, uh, lin, P.costs, wl.no_rows(), P.lb, P.ub)
+        tol_u = max(1e-6, 10 * np.sqrt(inf.kappa_est))
+        assert _rel(_np(b["u"]), ref["u"]) < tol_u, (t, _rel(_np(b["u"]), ref["u"]))
+        assert _rel(_np(xpred), ref["x"]) < 1e-4
+        active += int(np.any(np.abs(ref["u"][:nu]) > 0.5 - 1e-6))
+        _plant_step(plan, b, b["x0"], nu)
+        x = msd_step(x, ref["u"][:nu], P.row_ptr, P.col, P.act, prm)
+        xh, uh = ref["xhat"], ref["uhat"]
+        torch.cuda.synchronize()
+        assert _rel(_np(b["x0"]), x) < 1e-4
+    assert active > 0
+    with pytest.raises(gn.GnmpcError) as e:
+        gn.rti_step_ipm(plan, b, xpred, tol=0.0)
+    assert e.value.status == gn.INVALID_ARG
+
+
 def test_rti_gnn_controller_fp32_matches_the_oracle_on_the_measured_states():
     """A GNN controller (FP32 weights, Hd = 64, L = 2, 14 nodes, N = 5) on the
     spring-damper plant: at every iteration the oracle runs the same loop
