@@ -511,7 +511,8 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
       const int r = rb + rr0 + 4 * u;
       const bool vr = r < r1;
       pa[sl][u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
-      pb[sl][u] = (vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
+      // a diagonal tile's two strips are the same columns: the b strip is not loaded
+      pb[sl][u] = (!diag && vr && cb < cols) ? Sk[(size_t)r * cols + cb] : 0.f;
       pq[sl][u] = vr ? Qk[r] : 0.f;
     }
     if (diag && threadIdx.x < kRB) {
@@ -526,7 +527,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         As[rr0 + 4 * u][cc] = pa[sl][u];
-        Bs[rr0 + 4 * u][cc] = pq[sl][u] * pb[sl][u];
+        Bs[rr0 + 4 * u][cc] = pq[sl][u] * (diag ? pa[sl][u] : pb[sl][u]);
       }
       if (diag && threadIdx.x < kRB) Ws[threadIdx.x] = pw[sl];
       if (rb + 2 * kRB < r1) fetch(rb + 2 * kRB, slot);
