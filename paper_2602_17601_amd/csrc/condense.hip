@@ -461,19 +461,51 @@ __device__ inline T qs_value(const T* Sk, const T* Qk, int Q_full, int cols, int
   return v;
 }
 
-// FP32: matrix cores.  grid: x = live (tile, stage) pair, y = row chunk.  Rows
-// are staged 32 at a time (the a strip and the Q-weighted b strip, 64 columns
-// each) with independent loads issued two blocks ahead; each wave owns a 32x32 quarter of the tile
-// (2 x 2 MFMA tiles) and runs 8 k-steps per staged block.
+// FP32 on the matrix cores through bf16 terms.  grid: x = live (tile, stage) pair,
+// y = row chunk.  Every FP32 operand v enters as hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid) (each residual exact in FP32), so hi + mid + lo equals v to
+// about 2^-27 relative; a product takes the six terms hi hi, hi mid, mid hi, hi lo,
+// lo hi, mid mid (the dropped ones are below 2^-26 of it), each exact, summed in FP32
+// by v_mfma_f32_16x16x32_bf16: 6 x 16 cycles per 32-row step of a 16x16 sub-tile
+// against 8 x 32 for v_mfma_f32_16x16x4f32.  Rows are staged 32 at a time (the a
+// strip and the Q-weighted b strip, 64 columns each) with independent loads issued two
+// blocks ahead; thread t owns column t % 64 of the 8 consecutive rows 8 (t / 64) ..,
+// so it packs each term of its column into one 16-byte LDS store, and the MFMA
+// operand of a lane (8 consecutive rows of one column) is one 16-byte LDS read.
+// Each wave owns a 32x32 quarter of the tile (2 x 2 MFMA tiles).
 constexpr int kRB = 32;
+constexpr int kTS = kRB + 8;       // bf16 per staged column (16-byte pad: conflict-free reads)
+typedef __bf16 gbf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 gbf16x2_t __attribute__((ext_vector_type(2)));
+typedef float gfloat2_t __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t gpack_bf16x2(float a, float b) {  // round to nearest even
+  const gfloat2_t f = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, gbf16x2_t));
+}
+// the three bf16 terms of eight FP32 values, each packed as 8 bf16 (v[0] lowest)
+__device__ inline void split3_bf16x8(const float* v, uint4& t0, uint4& t1, uint4& t2) {
+  uint32_t w0[4], w1[4], w2[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = v[2 * i], b = v[2 * i + 1];
+    w0[i] = gpack_bf16x2(a, b);
+    const float ra = a - __uint_as_float(w0[i] << 16), rb = b - __uint_as_float(w0[i] & 0xFFFF0000u);
+    w1[i] = gpack_bf16x2(ra, rb);
+    w2[i] = gpack_bf16x2(ra - __uint_as_float(w1[i] << 16), rb - __uint_as_float(w1[i] & 0xFFFF0000u));
+  }
+  t0 = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+  t1 = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+  t2 = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+}
 __global__ void __launch_bounds__(256)
 gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __restrict__ Q, int Q_full,
                 const float* __restrict__ Gx_all, const float* __restrict__ q, float* __restrict__ part,
                 float* __restrict__ gpart) {
-  __shared__ float As[kRB][kT + 4];
-  __shared__ float Bs[kRB][kT + 4];
+  // [term][column][row] bf16 terms of the a strip and of the Q-weighted b strip
+  __shared__ __attribute__((aligned(16))) __bf16 Ta[3][kT][kTS];
+  __shared__ __attribute__((aligned(16))) __bf16 Tb[3][kT][kTS];
   __shared__ float Ws[kRB];        // w = Q_k Gx_k + q_k of the staged rows (diagonal tiles)
-  __shared__ float Gp[4][kT];      // gradient partials of the 4 row quarters
+  __shared__ float Gp[4][kT];      // gradient partials of the 4 row groups
   int tile;
   const int k = live_pair(sh, blockIdx.x, tile), chunk = blockIdx.y;
   int ta, tb;
@@ -485,7 +517,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   const float* Gxk = Gx_all + (size_t)k * sh.M * NBX;
   const float* qk = q + (size_t)k * sh.M * NBX;
   const bool diag = ta == tb;
-  float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT, rows (kRB / 4) (threadIdx.x / kT) .. + kRB / 4 - 1 of each block
+  float gacc = 0.f;  // diagonal tiles: column threadIdx.x % kT over the thread's rows of each block
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int qa = 32 * (wave >> 1), qb = 32 * (wave & 1);
   const int r0 = chunk * kChunkRows, r1 = min(rows, r0 + kChunkRows);
@@ -496,9 +528,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
     for (int y = 0; y < 2; ++y) acc[x][y] = cfloatx4{0.f, 0.f, 0.f, 0.f};
   // this wave's quarter may lie entirely past the live columns
   const bool live = kT * ta + qa < cols && kT * tb + qb < cols;
-  // staging: thread t owns column cc = t % kT of rows t / kT + 4 u (u < kRB / 4); with a
-  // diagonal Q the row block two ahead is loaded into registers while one is multiplied
-  constexpr int kPer = kRB * kT / 256;
+  constexpr int kPer = kRB * kT / 256;   // rows per thread and block (8)
   const int cc = threadIdx.x % kT, rr0 = threadIdx.x / kT;
   const int ca = kT * ta + cc, cb = kT * tb + cc;
   // two register sets: the block two ahead is in flight while one is multiplied
@@ -508,7 +538,7 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
     constexpr int sl = decltype(slot)::value;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int r = rb + rr0 + 4 * u;
+      const int r = rb + kPer * rr0 + u;
       const bool vr = r < r1;
       pa[sl][u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
       // a diagonal tile's two strips are the same columns: the b strip is not loaded
@@ -522,22 +552,22 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   };
   auto block = [&](int rb, auto slot) {
     constexpr int sl = decltype(slot)::value;
+    float va[kPer], vb[kPer];
     __syncthreads();
     if (!Q_full) {
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        As[rr0 + 4 * u][cc] = pa[sl][u];
-        Bs[rr0 + 4 * u][cc] = pq[sl][u] * (diag ? pa[sl][u] : pb[sl][u]);
+        va[u] = pa[sl][u];
+        vb[u] = pq[sl][u] * (diag ? pa[sl][u] : pb[sl][u]);
       }
       if (diag && threadIdx.x < kRB) Ws[threadIdx.x] = pw[sl];
-      if (rb + 2 * kRB < r1) fetch(rb + 2 * kRB, slot);
     } else {
-      for (int t = threadIdx.x; t < kRB * kT; t += 256) {
-        const int rr = t / kT, c2 = t % kT, r = rb + rr;
-        const int ca2 = kT * ta + c2, cb2 = kT * tb + c2;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int r = rb + kPer * rr0 + u;
         const bool vr = r < r1;
-        As[rr][c2] = (vr && ca2 < cols) ? Sk[(size_t)r * cols + ca2] : 0.f;
-        Bs[rr][c2] = (vr && cb2 < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb2) : 0.f;
+        va[u] = (vr && ca < cols) ? Sk[(size_t)r * cols + ca] : 0.f;
+        vb[u] = (vr && cb < cols) ? qs_value(Sk, Qk, Q_full, cols, r, cb) : 0.f;
       }
       if (diag && threadIdx.x < kRB) {
         const int r = rb + threadIdx.x;
@@ -552,24 +582,45 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
         Ws[threadIdx.x] = wv;
       }
     }
+    {
+      uint4 t0, t1, t2;
+      split3_bf16x8(va, t0, t1, t2);
+      *reinterpret_cast<uint4*>(&Ta[0][cc][kPer * rr0]) = t0;
+      *reinterpret_cast<uint4*>(&Ta[1][cc][kPer * rr0]) = t1;
+      *reinterpret_cast<uint4*>(&Ta[2][cc][kPer * rr0]) = t2;
+      split3_bf16x8(vb, t0, t1, t2);
+      *reinterpret_cast<uint4*>(&Tb[0][cc][kPer * rr0]) = t0;
+      *reinterpret_cast<uint4*>(&Tb[1][cc][kPer * rr0]) = t1;
+      *reinterpret_cast<uint4*>(&Tb[2][cc][kPer * rr0]) = t2;
+    }
+    if (!Q_full && rb + 2 * kRB < r1) fetch(rb + 2 * kRB, slot);
     __syncthreads();
     if (diag) {
 #pragma unroll
-      for (int u = 0; u < kRB / 4; ++u) gacc += As[(kRB / 4) * rr0 + u][cc] * Ws[(kRB / 4) * rr0 + u];
+      for (int u = 0; u < kPer; ++u) gacc += va[u] * Ws[kPer * rr0 + u];
     }
     if (live) {
+      // lane (n, g): column n of a sub-tile, rows 8 g .. 8 g + 7 of the block
+      const int n = lane & 15, g8 = 8 * (lane >> 4);
+      gbf16x8_t av[3][2], bv[3][2];
 #pragma unroll
-      for (int kk = 0; kk < kRB; kk += 4) {
-        float av[2], bv[2];
+      for (int t = 0; t < 3; ++t)
 #pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = As[kk + (lane >> 4)][qa + 16 * x + (lane & 15)];
+        for (int x = 0; x < 2; ++x) {
+          av[t][x] = *reinterpret_cast<const gbf16x8_t*>(&Ta[t][qa + 16 * x + n][g8]);
+          bv[t][x] = *reinterpret_cast<const gbf16x8_t*>(&Tb[t][qb + 16 * x + n][g8]);
+        }
 #pragma unroll
-        for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + (lane >> 4)][qb + 16 * y + (lane & 15)];
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
-      }
+        for (int y = 0; y < 2; ++y) {
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][x], bv[0][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][x], bv[1][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][x], bv[0][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][x], bv[2][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2][x], bv[0][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][x], bv[1][y], acc[x][y], 0, 0, 0);
+        }
     }
   };
   const std::integral_constant<int, 0> s0;
