@@ -242,6 +242,10 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single instance: K independent instances of uneven size "
                          "(M ~ U{50..1000}, N ~ U{10..30}) in one batched step; prints its own JSON line")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="instead of the step: the learned-surrogate pipeline (simulator data set, GNN training, "
+                         "500-step closed loop with GNN against analytic Jacobians); prints its own JSON line")
+    ap.add_argument("--surrogate-steps", type=int, default=2000, help="Adam steps of the --surrogate training")
     ap.add_argument("--eager", action="store_true",
                     help="time eagerly launched steps instead of replays of the step captured as a HIP graph")
     ap.add_argument("--only-step", action="store_true",
@@ -271,6 +275,13 @@ def main():
 
     if args.batch:
         bench_batch(args, torch, gn, wl)
+        return
+    if args.surrogate:
+        from paper_2602_17601_amd import surrogate
+        res = surrogate.run(surrogate.SurrogateConfig(steps=args.surrogate_steps),
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({"metric": "learned-surrogate pipeline: one-step RMSE, Jacobian error, closed loop",
+                          "n_gpus": 1, "data": "synthetic (simulator)", **res}), flush=True)
         return
 
     dev = "cuda"
