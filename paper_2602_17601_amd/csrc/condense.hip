@@ -497,7 +497,8 @@ __device__ inline void split3_bf16x8(const float* v, uint4& t0, uint4& t1, uint4
   t1 = make_uint4(w1[0], w1[1], w1[2], w1[3]);
   t2 = make_uint4(w2[0], w2[1], w2[2], w2[3]);
 }
-__global__ void __launch_bounds__(256)
+// held to 128 registers per lane (no spills), so four waves share each SIMD
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __restrict__ Q, int Q_full,
                 const float* __restrict__ Gx_all, const float* __restrict__ q, float* __restrict__ part,
                 float* __restrict__ gpart) {
