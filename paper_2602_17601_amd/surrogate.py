@@ -252,8 +252,10 @@ def run(cfg: SurrogateConfig, log=print) -> dict:
                           "held_out_samples": nt_eval},
         "jacobian_rel_error": jac_err,
         "closed_loop": {
-            "gnn": {"ms_per_iteration": ms_g, "cost": cost(tr_g, u_g), "qp_unsolved_at_checks": uns_g, "checks": 5},
-            "analytic": {"ms_per_iteration": ms_m, "cost": cost(tr_m, u_m), "qp_unsolved_at_checks": uns_m, "checks": 5},
+            "gnn": {"ms_per_iteration": ms_g, "cost": cost(tr_g, u_g), "qp_unsolved_at_checks": uns_g,
+                    "checks": cfg.loop_steps // max(1, cfg.loop_steps // 5)},
+            "analytic": {"ms_per_iteration": ms_m, "cost": cost(tr_m, u_m), "qp_unsolved_at_checks": uns_m,
+                         "checks": cfg.loop_steps // max(1, cfg.loop_steps // 5)},
             "state_rel_diff": float(torch.linalg.norm(tr_g - tr_m) / torch.linalg.norm(tr_m)),
             "input_rel_diff": float(torch.linalg.norm(u_g - u_m) / max(float(torch.linalg.norm(u_m)), 1e-30)),
             "finite": bool(torch.isfinite(tr_g).all() and torch.isfinite(tr_m).all()),
