@@ -507,8 +507,15 @@ gram_kernel_f32(GramShape sh, const float* __restrict__ S_all, const float* __re
   __shared__ __attribute__((aligned(16))) __bf16 Tb[3][kT][kTS];
   __shared__ float Ws[kRB];        // w = Q_k Gx_k + q_k of the staged rows (diagonal tiles)
   __shared__ float Gp[4][kT];      // gradient partials of the 4 row groups
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the linear index is
+  // remapped to give each XCD a contiguous range of (chunk, pair) items; the live pairs of one
+  // row chunk then run on one XCD at once and share its L2 copy of the S_k strips
   int tile;
-  const int k = live_pair(sh, blockIdx.x, tile), chunk = blockIdx.y;
+  const int npairs = gridDim.x, total = npairs * gridDim.y;
+  const int gid = blockIdx.x + blockIdx.y * npairs;
+  const int xcd = gid % 8, slot = gid / 8, q8 = total / 8, r8 = total % 8;
+  const int lin = xcd < r8 ? xcd * (q8 + 1) + slot : r8 * (q8 + 1) + (xcd - r8) * q8 + slot;
+  const int k = live_pair(sh, lin % npairs, tile), chunk = lin / npairs;
   int ta, tb;
   tile_coords(tile, ta, tb);
   if (k < first_stage(ta, sh.nu)) return;
